@@ -1,0 +1,62 @@
+"""Leapfrog molecular dynamics for the oracle (test infrastructure only).
+
+Equations of motion (left-invariant form, eqs. S2.1-S2.2 with P = -i Pi):
+  dU/dtau = Pi U,   dPi/dtau = -F(U),   F = F_G + F_f,
+with H = K + S_G + S_f, K = -sum tr Pi^2.  The integrator is the second-order
+reversible, symplectic leapfrog named in Sec. III B, in its
+momentum-position-momentum form:
+
+  Pi <- Pi - dt/2 F(U)
+  repeat nsteps times:  U <- reunitarize(exp(dt Pi) U);  Pi <- Pi - dt F(U)
+  (the final kick uses dt/2 instead of dt)
+
+The pseudofermion field phi is held fixed along the trajectory and each force
+evaluation solves (D^dag D) chi = phi from a zero guess.
+"""
+from __future__ import annotations
+
+from .action import gauge_action, fermion_action, kinetic
+from .force import gauge_force, fermion_force_from_solution
+from .solver import solve_ddag_d
+from .su3 import expm_antihermitian, reunitarize
+
+
+def total_force(u, phi, beta, kappa, bc=-1, tol=1e-12, with_fermion=True):
+    f = gauge_force(u, beta)
+    if with_fermion:
+        chi, eta, _, _ = solve_ddag_d(u, phi, kappa, bc, tol)
+        f = f + fermion_force_from_solution(u, chi, eta, kappa, bc)
+    return f
+
+
+def hamiltonian(u, p, phi, beta, kappa, bc=-1, tol=1e-12, with_fermion=True):
+    h = kinetic(p) + gauge_action(u, beta)
+    if with_fermion:
+        h += fermion_action(u, phi, kappa, bc, tol)[0]
+    return h
+
+
+def link_update(u, p, dt):
+    """U <- reunitarize(exp(dt Pi) U)  (eq. 4 / S2.1 with the reunitarization reading)."""
+    return reunitarize(expm_antihermitian(dt * p) @ u)
+
+
+def leapfrog(u, p, phi, beta, kappa, dt, nsteps, bc=-1, tol=1e-12, with_fermion=True):
+    """Returns (U, Pi) after nsteps leapfrog steps of size dt."""
+    def force(v):
+        return total_force(v, phi, beta, kappa, bc, tol, with_fermion)
+
+    p = p - 0.5 * dt * force(u)
+    for k in range(nsteps):
+        u = link_update(u, p, dt)
+        step = dt if k < nsteps - 1 else 0.5 * dt
+        p = p - step * force(u)
+    return u, p
+
+
+def trajectory_dh(u, p, phi, beta, kappa, dt, nsteps, bc=-1, tol=1e-12, with_fermion=True):
+    """(U', Pi', Delta H) for one trajectory."""
+    h0 = hamiltonian(u, p, phi, beta, kappa, bc, tol, with_fermion)
+    u1, p1 = leapfrog(u, p, phi, beta, kappa, dt, nsteps, bc, tol, with_fermion)
+    h1 = hamiltonian(u1, p1, phi, beta, kappa, bc, tol, with_fermion)
+    return u1, p1, h1 - h0
