@@ -1,0 +1,237 @@
+/*
+ * lgt.h -- C ABI of the MI355X (gfx950) Wilson-fermion HMC hot path.
+ *
+ * The library computes, on one GPU, the pieces of Hybrid Monte Carlo for
+ * SU(3) lattice gauge theory with two-flavour Wilson fermions that the paper
+ * ("Lattice Gauge Theory via LLVM-Level Automatic Differentiation") obtains
+ * by reverse-mode AD of the action code:
+ *
+ *   - the Wilson-Dirac operator D(U) (used in S_f of eq. S3.1),
+ *   - the solve of A chi = phi, A = D^dag D (eq. S3.5; "e.g. via conjugate
+ *     gradient", not differentiated),
+ *   - the actions S_G (Wilson plaquette) and S_f = phi^dag (D^dag D)^-1 phi,
+ *   - the MD forces: the pseudofermion force from
+ *     delta S_f = -2 Re[eta^dag (delta D) chi] (eq. S3.11) and the plaquette
+ *     (staple) force, projected to su(3) (eq. 6 / S2.11),
+ *   - the leapfrog step U -> exp(dt Pi) U, Pi -> Pi - dt F (eqs. S2.1-S2.2).
+ *
+ * Here the forces are explicit adjoint kernels, not AD output.
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions shared by every call
+ * ---------------------------------------------------------------------------
+ * Lattice: dims = {Lx, Ly, Lz, Lt}, every extent even and >= 2; lexicographic
+ *   site index  s = x + Lx*(y + Ly*(z + Lz*t));  V = Lx*Ly*Lz*Lt.
+ *   Directions mu = 0,1,2,3 are x,y,z,t.  Links are periodic; the fermion
+ *   field has the temporal boundary sign fermion_t_bc (-1: antiperiodic)
+ *   applied to the t-links of the last time slice inside D only.
+ *
+ * Field buffers (all DEVICE pointers, caller-owned, complex128 = two
+ *   little-endian doubles re, im, at least 16-byte aligned):
+ *     gauge-type (U, momenta Pi, force F, gradient G): [V][4][3][3],
+ *       matrix element (row i, column j) at [s][mu][i][j];
+ *     spinor (phi, X, Y, in/out of D): [V][4][3] (spin, colour).
+ *   The library never frees a caller buffer nor keeps a pointer to it
+ *   past the call.  Input and output buffers of one call must not overlap,
+ *   except where a call documents an in-place update.
+ *
+ * D (the paper leaves it implicit; this is the hopping-parameter form):
+ *   (D psi)(x) = psi(x) - kappa * sum_mu [ (1 - gamma_mu) U~_mu(x) psi(x+mu)
+ *                                       + (1 + gamma_mu) U~_mu(x-mu)^dag psi(x-mu) ]
+ *   chiral basis gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 =
+ *   [[0,1],[1,0]], gamma_5 = diag(1,1,-1,-1); U~ = U except on the t-links of
+ *   the last time slice, where U~ = fermion_t_bc * U.
+ *
+ * Gradients and forces (Sec. S2): the gradient of a real action S is
+ *   G = dS/dRe U + i dS/dIm U (eq. S2.7), so delta S = Re tr(G^dag delta U);
+ *   the force is F = -1/2 P_su3[U G^dag] with
+ *   P_su3[A] = (A - A^dag)/2 - tr(A - A^dag)/6 (eq. 6).  The momentum update
+ *   Pi <- Pi - dt F equals the paper's Pi <- Pi + (dt/2) P_su3[U G^dag].
+ *   Momenta are traceless anti-Hermitian, K = -sum tr Pi^2.
+ *
+ * Streams: every call enqueues its work on the context's HIP stream
+ *   (lgt_create / lgt_set_stream).  Calls that return host values
+ *   (actions, solver statistics, Delta H) synchronise that stream before
+ *   returning; the others return once the work is enqueued.
+ *
+ * Errors: every call returns lgt_status; no C++ exception crosses the ABI.
+ *   On LGT_ERR_NOT_CONVERGED the outputs hold the last iterate and the
+ *   statistics are filled.  On any other error the outputs are unspecified
+ *   and lgt_last_error(ctx) describes the failure.
+ *
+ * Concurrency: one context per stream/thread; contexts are independent.
+ *   Calls on one context must not overlap.
+ */
+#ifndef LGT_H
+#define LGT_H
+
+#include <stdint.h>
+
+/* Symbols of the shared library (built with hidden default visibility). */
+#define LGT_API __attribute__((visibility("default")))
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lgt_status {
+  LGT_OK = 0,
+  LGT_ERR_INVALID_ARGUMENT = 1,
+  LGT_ERR_NOT_CONVERGED = 2,
+  LGT_ERR_NONFINITE = 3,
+  LGT_ERR_OUT_OF_MEMORY = 4,
+  LGT_ERR_DEVICE = 5,
+  LGT_ERR_UNSUPPORTED = 6
+} lgt_status;
+
+/* Precision of the solver's inner iterations.  LGT_FP64: every step in
+ * FP64.  LGT_MIXED_FP32: inner CG with FP32 links, spinors and hops inside
+ * an FP64 reliable-update loop that recomputes the residual in FP64 and
+ * accumulates the solution in FP64; the stopping test is on the FP64
+ * residual.  LGT_MIXED_BF16: as LGT_MIXED_FP32 with the hop input spinors
+ * stored in bfloat16 (FP32 arithmetic). */
+typedef enum lgt_precision {
+  LGT_FP64 = 0,
+  LGT_MIXED_FP32 = 1,
+  LGT_MIXED_BF16 = 2
+} lgt_precision;
+
+/* What a force call writes.
+ *   LGT_OUT_FORCE:    out = F (traceless anti-Hermitian), overwritten.
+ *   LGT_OUT_GRAD:     out = G = dS/dRe U + i dS/dIm U, overwritten.
+ *   LGT_OUT_MOMENTUM: out holds the momenta Pi, updated in place:
+ *                     Pi <- Pi - dt * F. */
+typedef enum lgt_out_mode {
+  LGT_OUT_FORCE = 0,
+  LGT_OUT_GRAD = 1,
+  LGT_OUT_MOMENTUM = 2
+} lgt_out_mode;
+
+typedef struct lgt_geom {
+  int32_t dims[4];      /* Lx, Ly, Lz, Lt: each even and >= 2 */
+  int32_t fermion_t_bc; /* -1 (antiperiodic) or +1 (periodic) */
+} lgt_geom;
+
+typedef struct lgt_solver_params {
+  int32_t precision;     /* lgt_precision */
+  int32_t even_odd;      /* 1: even/odd Schur complement + CGNR (the only form supported) */
+  double tol;            /* stop when ||phi - D^dag D X|| / ||phi|| <= tol (FP64, recomputed) */
+  int32_t max_iter;      /* cap on inner CG iterations per solve (<= 0: 20000) */
+  double reliable_delta; /* mixed precision: FP64 residual update when the inner
+                            residual drops by this factor (<= 0: 0.1) */
+} lgt_solver_params;
+
+typedef struct lgt_solver_stats {
+  int32_t iters;            /* inner CG iterations, summed over the solves of the call */
+  int32_t reliable_updates; /* FP64 residual recomputations (mixed precision) */
+  double true_rel_residual; /* ||phi - D^dag D X|| / ||phi|| in FP64 at exit */
+  double ms;                /* wall time of the call on the stream, milliseconds */
+} lgt_solver_stats;
+
+typedef struct lgt_ctx lgt_ctx;
+
+/* Create a context for one lattice geometry on the current HIP device.
+ * hip_stream: a hipStream_t (NULL = the default stream).  The context owns
+ * its device workspace (packed link copies, solver vectors), allocated here;
+ * it grows on first use of the mixed-precision and MD paths.
+ * Errors: INVALID_ARGUMENT (odd or < 2 extent, bc not +-1, null out),
+ * OUT_OF_MEMORY, DEVICE. */
+LGT_API lgt_status lgt_create(const lgt_geom* geom, void* hip_stream, lgt_ctx** out);
+
+/* Release the context and its workspace (synchronises its stream). */
+LGT_API lgt_status lgt_destroy(lgt_ctx* ctx);
+
+/* Message describing the last failing call on ctx ("" if none).  The
+ * pointer stays valid until the next call on ctx.  ctx == NULL gives the
+ * message of the last failing lgt_create. */
+LGT_API const char* lgt_last_error(const lgt_ctx* ctx);
+
+/* Rebind the context to another HIP stream (NULL = default stream). */
+LGT_API lgt_status lgt_set_stream(lgt_ctx* ctx, void* hip_stream);
+
+/* Number of lattice sites V of the context. */
+LGT_API int64_t lgt_volume(const lgt_ctx* ctx);
+
+/* out = D(U) in (dagger = 0) or D(U)^dag in (dagger = 1), FP64.
+ * The operator of the pseudofermion action (eq. S3.1); written out above.
+ * U: gauge field; in, out: spinors; kappa: hopping parameter. */
+LGT_API lgt_status lgt_dslash(lgt_ctx* ctx, const void* U, const void* in, void* out,
+                      double kappa, int32_t dagger);
+
+/* Solve (D^dag D) X = phi (eq. S3.5) and return Y = D X (the paper's
+ * eta = D chi below eq. S3.10).  The solve is not differentiated (S3,
+ * "Remarks on the role of the linear solver").  Method: two even/odd Schur
+ * complement solves, D^dag Y = phi then D X = Y, each by CG on the normal
+ * equations from a zero initial guess, followed by FP64 defect correction
+ * until ||phi - D^dag D X|| / ||phi|| <= params->tol.  Y_or_null may be NULL.
+ * stats may be NULL.  NOT_CONVERGED if max_iter is reached first (X, Y hold
+ * the last iterate).  NONFINITE if phi or U holds NaN/Inf. */
+LGT_API lgt_status lgt_cg_solve(lgt_ctx* ctx, const void* U, const void* phi, void* X,
+                        void* Y_or_null, double kappa, const lgt_solver_params* params,
+                        lgt_solver_stats* stats);
+
+/* Actions: *S_G = beta * sum_x sum_{mu<nu} (1 - Re tr P_mu,nu(x) / 3) and
+ * *S_F = phi^dag (D^dag D)^-1 phi (eq. S3.1), evaluated in the variational
+ * form 2 Re phi^dag X - ||D X||^2, which is exact at the solution and
+ * second-order accurate in the solver error.  Either output may be NULL
+ * (S_F == NULL skips the solve; phi may then be NULL).  All FP64. */
+LGT_API lgt_status lgt_action(lgt_ctx* ctx, const void* U, const void* phi, double beta, double kappa,
+                      const lgt_solver_params* params, double* S_G, double* S_F,
+                      lgt_solver_stats* stats);
+
+/* Pseudofermion force: solve as in lgt_cg_solve, then the adjoint kernel of
+ * delta S_f = -2 Re[Y^dag (delta D) X] (eq. S3.11) for every link, projected
+ * by F = -1/2 P_su3[U G^dag].  mode/dt/out as in lgt_out_mode; out is a
+ * gauge-type buffer.  The force itself is accumulated in FP64 for every
+ * precision. */
+LGT_API lgt_status lgt_fermion_force(lgt_ctx* ctx, const void* U, const void* phi, double kappa,
+                             const lgt_solver_params* params, int32_t mode, double dt,
+                             void* out, lgt_solver_stats* stats);
+
+/* Building block of the fermion force (eq. S3.13): the gradient/force of
+ * coeff * Re[a^dag D(U) b] for given spinors a, b (no solve).  The
+ * pseudofermion force is coeff = -2, a = Y, b = X.  FP64. */
+LGT_API lgt_status lgt_bilinear_force(lgt_ctx* ctx, const void* U, const void* a, const void* b,
+                              double kappa, double coeff, int32_t mode, double dt, void* out);
+
+/* Wilson plaquette (staple) force of S_G at coupling beta, the derivative
+ * the paper's gauge listing takes by AD of the plaquette action:
+ * G = -(beta/3) A^dag with A the staple sum, F = (beta/6) P_su3[U A].  FP64. */
+LGT_API lgt_status lgt_gauge_force(lgt_ctx* ctx, const void* U, double beta, int32_t mode, double dt,
+                           void* out);
+
+/* U <- reunitarize(exp(dt Pi) U) on every link, in place (eq. 4 / S2.1 in
+ * the anti-Hermitian form).  exp by the Cayley-Hamilton closed form;
+ * reunitarization by row Gram-Schmidt with row3 = conj(row1 x row2).  FP64. */
+LGT_API lgt_status lgt_link_update(lgt_ctx* ctx, void* U, const void* P, double dt);
+
+/* K = -sum_{x,mu} tr Pi_mu(x)^2 for traceless anti-Hermitian momenta.  FP64. */
+LGT_API lgt_status lgt_kinetic(lgt_ctx* ctx, const void* P, double* K);
+
+/* Leapfrog trajectory (Sec. III B; eqs. S2.1-S2.2), nsteps steps of size dt,
+ * updating U and P in place:
+ *   P <- P - dt/2 F(U); then nsteps times { U <- reunit(exp(dt P) U);
+ *   P <- P - dt F(U) } with the last kick dt/2,
+ * F = F_G + F_f with phi fixed (phi == NULL or kappa == 0: pure gauge).
+ * dH_or_null receives H_end - H_start, H = K + S_G + S_f.  stats sums the
+ * solver statistics over all force evaluations. */
+LGT_API lgt_status lgt_md_step(lgt_ctx* ctx, void* U, void* P, const void* phi, double beta,
+                       double kappa, double dt, int32_t nsteps,
+                       const lgt_solver_params* params, double* dH_or_null,
+                       lgt_solver_stats* stats);
+
+/* Measurement entry point: times nrep back-to-back launches of the
+ * even/odd hop kernel H_eo (the dominant kernel of the CG; FP64 for
+ * precision = LGT_FP64, FP32 otherwise) on links U and input spinor psi,
+ * with HIP events on the context stream, and returns the mean duration of
+ * one launch in *avg_ms.  The algorithmic traffic of one launch is
+ * 96 reals per lattice site (all 4V links, the input and output half
+ * spinors). */
+LGT_API lgt_status lgt_hop_benchmark(lgt_ctx* ctx, const void* U, const void* psi, int32_t precision,
+                                     int32_t nrep, double* avg_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LGT_H */

@@ -1,0 +1,20 @@
+"""MI355X (gfx950) Wilson-fermion HMC hot path: HIP kernels behind a C ABI.
+
+The computation lives in ``liblgt.so`` (sources in ``csrc/``, ABI in
+``include/lgt.h``); this package is its Python binding.  Importing it loads
+the library and fails loudly if it has not been built
+(``python paper_2602_20516_amd/build.py``).
+"""
+from . import _lib
+
+_lib.load()
+
+from .api import (Lattice, LGTError, LGTNonFinite, LGTNotConverged, Params,  # noqa: E402
+                  lgt_action, lgt_bilinear_force, lgt_cg_solve, lgt_create, lgt_dslash,
+                  lgt_fermion_force, lgt_gauge_force, lgt_kinetic, lgt_link_update, lgt_md_step)
+
+__all__ = [
+    "Lattice", "Params", "LGTError", "LGTNotConverged", "LGTNonFinite",
+    "lgt_create", "lgt_dslash", "lgt_cg_solve", "lgt_action", "lgt_fermion_force",
+    "lgt_bilinear_force", "lgt_gauge_force", "lgt_link_update", "lgt_kinetic", "lgt_md_step",
+]

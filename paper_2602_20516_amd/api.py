@@ -1,0 +1,279 @@
+"""Python binding of the C ABI (include/lgt.h) over torch device tensors.
+
+Every function marshals arguments and calls the function of the same name in
+liblgt.so; all arithmetic runs in the library's HIP kernels.  Fields are
+contiguous complex128 CUDA/HIP tensors in the canonical layouts:
+gauge-type (Lt, Lz, Ly, Lx, 4, 3, 3), spinor (Lt, Lz, Ly, Lx, 4, 3).  Work is
+ordered on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import (LGT_FP64, LGT_MIXED_FP32, LGT_MIXED_BF16, LGT_OUT_FORCE, LGT_OUT_GRAD,  # noqa: F401
+                   LGT_OUT_MOMENTUM, SolverParams, SolverStats)
+
+_MODES = {"force": LGT_OUT_FORCE, "grad": LGT_OUT_GRAD, "momentum": LGT_OUT_MOMENTUM}
+_PRECISIONS = {"fp64": LGT_FP64, "mixed_fp32": LGT_MIXED_FP32, "mixed_bf16": LGT_MIXED_BF16}
+
+
+class LGTError(RuntimeError):
+    def __init__(self, status: int, message: str, stats: Optional[dict] = None):
+        super().__init__(f"{_lib.STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.stats = stats
+
+
+class LGTNotConverged(LGTError):
+    pass
+
+
+class LGTNonFinite(LGTError):
+    pass
+
+
+@dataclass
+class Params:
+    """Solver parameters (lgt_solver_params)."""
+    precision: str = "fp64"
+    tol: float = 1e-10
+    max_iter: int = 20000
+    reliable_delta: float = 0.1
+    even_odd: int = 1
+
+    def to_c(self) -> SolverParams:
+        return SolverParams(_PRECISIONS[self.precision], self.even_odd, float(self.tol),
+                            int(self.max_iter), float(self.reliable_delta))
+
+
+def _check(lib, ctx, status: int, stats: Optional[SolverStats] = None):
+    if status == _lib.LGT_OK:
+        return
+    msg = lib.lgt_last_error(ctx)
+    msg = msg.decode() if msg else ""
+    st = stats.as_dict() if stats is not None else None
+    if status == _lib.LGT_ERR_NOT_CONVERGED:
+        raise LGTNotConverged(status, msg, st)
+    if status == _lib.LGT_ERR_NONFINITE:
+        raise LGTNonFinite(status, msg, st)
+    raise LGTError(status, msg, st)
+
+
+def _stream_ptr() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Lattice:
+    """A library context (lgt_ctx) for one lattice geometry on the current device."""
+
+    def __init__(self, dims, fermion_bc: int = -1):
+        self.lib = _lib.load()
+        self.dims = tuple(int(d) for d in dims)
+        lx, ly, lz, lt = self.dims
+        self.site_shape = (lt, lz, ly, lx)
+        self.volume = lx * ly * lz * lt
+        self.fermion_bc = int(fermion_bc)
+        geom = _lib.Geom((ctypes.c_int32 * 4)(*self.dims), self.fermion_bc)
+        ctx = ctypes.c_void_p()
+        status = self.lib.lgt_create(ctypes.byref(geom), ctypes.c_void_p(_stream_ptr()), ctypes.byref(ctx))
+        _check(self.lib, None, status)
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.lgt_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- marshalling helpers --------------------------------------------------
+    def _bind_stream(self):
+        self.lib.lgt_set_stream(self.ctx, ctypes.c_void_p(_stream_ptr()))
+
+    def _field(self, t: torch.Tensor, kind: str, name: str) -> ctypes.c_void_p:
+        shape = self.site_shape + ((4, 3, 3) if kind == "gauge" else (4, 3))
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.dtype != torch.complex128 or tuple(t.shape) != shape:
+            raise ValueError(f"{name}: expected complex128 {shape}, got {t.dtype} {tuple(t.shape)}")
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty_gauge(self):
+        return torch.empty(self.site_shape + (4, 3, 3), dtype=torch.complex128, device="cuda")
+
+    def empty_spinor(self):
+        return torch.empty(self.site_shape + (4, 3), dtype=torch.complex128, device="cuda")
+
+    # -- the ABI ----------------------------------------------------------------
+    def dslash(self, U, psi, kappa: float, dagger: bool = False, out=None):
+        """lgt_dslash: D psi (or D^dag psi)."""
+        out = self.empty_spinor() if out is None else out
+        self._bind_stream()
+        st = self.lib.lgt_dslash(self.ctx, self._field(U, "gauge", "U"), self._field(psi, "spinor", "psi"),
+                                 self._field(out, "spinor", "out"), float(kappa), int(bool(dagger)))
+        _check(self.lib, self.ctx, st)
+        return out
+
+    def cg_solve(self, U, phi, kappa: float, params: Optional[Params] = None, want_y: bool = True):
+        """lgt_cg_solve: X = (D^dag D)^-1 phi, Y = D X.  Returns (X, Y, stats)."""
+        params = params or Params()
+        X = self.empty_spinor()
+        Y = self.empty_spinor() if want_y else None
+        stats = SolverStats()
+        cp = params.to_c()
+        self._bind_stream()
+        st = self.lib.lgt_cg_solve(self.ctx, self._field(U, "gauge", "U"), self._field(phi, "spinor", "phi"),
+                                   self._field(X, "spinor", "X"),
+                                   self._field(Y, "spinor", "Y") if Y is not None else None,
+                                   float(kappa), ctypes.byref(cp), ctypes.byref(stats))
+        _check(self.lib, self.ctx, st, stats)
+        return X, Y, stats.as_dict()
+
+    def action(self, U, phi, beta: float, kappa: float, params: Optional[Params] = None,
+               gauge: bool = True, fermion: bool = True):
+        """lgt_action: returns (S_G or None, S_F or None, stats)."""
+        params = params or Params()
+        sg = ctypes.c_double()
+        sf = ctypes.c_double()
+        stats = SolverStats()
+        cp = params.to_c()
+        self._bind_stream()
+        st = self.lib.lgt_action(self.ctx, self._field(U, "gauge", "U"),
+                                 self._field(phi, "spinor", "phi") if fermion else None,
+                                 float(beta), float(kappa), ctypes.byref(cp),
+                                 ctypes.byref(sg) if gauge else None,
+                                 ctypes.byref(sf) if fermion else None, ctypes.byref(stats))
+        _check(self.lib, self.ctx, st, stats)
+        return (sg.value if gauge else None), (sf.value if fermion else None), stats.as_dict()
+
+    def fermion_force(self, U, phi, kappa: float, params: Optional[Params] = None, mode: str = "force",
+                      dt: float = 0.0, out=None):
+        """lgt_fermion_force: returns (out, stats)."""
+        params = params or Params()
+        out = self.empty_gauge() if out is None else out
+        stats = SolverStats()
+        cp = params.to_c()
+        self._bind_stream()
+        st = self.lib.lgt_fermion_force(self.ctx, self._field(U, "gauge", "U"), self._field(phi, "spinor", "phi"),
+                                        float(kappa), ctypes.byref(cp), _MODES[mode], float(dt),
+                                        self._field(out, "gauge", "out"), ctypes.byref(stats))
+        _check(self.lib, self.ctx, st, stats)
+        return out, stats.as_dict()
+
+    def bilinear_force(self, U, a, b, kappa: float, coeff: float, mode: str = "force", dt: float = 0.0,
+                       out=None):
+        """lgt_bilinear_force: force/gradient of coeff * Re[a^dag D(U) b]."""
+        out = self.empty_gauge() if out is None else out
+        self._bind_stream()
+        st = self.lib.lgt_bilinear_force(self.ctx, self._field(U, "gauge", "U"), self._field(a, "spinor", "a"),
+                                         self._field(b, "spinor", "b"), float(kappa), float(coeff), _MODES[mode],
+                                         float(dt), self._field(out, "gauge", "out"))
+        _check(self.lib, self.ctx, st)
+        return out
+
+    def gauge_force(self, U, beta: float, mode: str = "force", dt: float = 0.0, out=None):
+        """lgt_gauge_force."""
+        out = self.empty_gauge() if out is None else out
+        self._bind_stream()
+        st = self.lib.lgt_gauge_force(self.ctx, self._field(U, "gauge", "U"), float(beta), _MODES[mode],
+                                      float(dt), self._field(out, "gauge", "out"))
+        _check(self.lib, self.ctx, st)
+        return out
+
+    def link_update(self, U, P, dt: float):
+        """lgt_link_update: U <- reunit(exp(dt P) U) in place."""
+        self._bind_stream()
+        st = self.lib.lgt_link_update(self.ctx, self._field(U, "gauge", "U"), self._field(P, "gauge", "P"),
+                                      float(dt))
+        _check(self.lib, self.ctx, st)
+        return U
+
+    def kinetic(self, P) -> float:
+        """lgt_kinetic."""
+        k = ctypes.c_double()
+        self._bind_stream()
+        st = self.lib.lgt_kinetic(self.ctx, self._field(P, "gauge", "P"), ctypes.byref(k))
+        _check(self.lib, self.ctx, st)
+        return k.value
+
+    def md_step(self, U, P, phi, beta: float, kappa: float, dt: float, nsteps: int,
+                params: Optional[Params] = None):
+        """lgt_md_step: leapfrog trajectory in place; returns (dH, stats)."""
+        params = params or Params()
+        dh = ctypes.c_double()
+        stats = SolverStats()
+        cp = params.to_c()
+        self._bind_stream()
+        st = self.lib.lgt_md_step(self.ctx, self._field(U, "gauge", "U"), self._field(P, "gauge", "P"),
+                                  self._field(phi, "spinor", "phi") if phi is not None else None,
+                                  float(beta), float(kappa), float(dt), int(nsteps), ctypes.byref(cp),
+                                  ctypes.byref(dh), ctypes.byref(stats))
+        _check(self.lib, self.ctx, st, stats)
+        return dh.value, stats.as_dict()
+
+    def hop_benchmark(self, U, psi, precision: str = "fp64", nrep: int = 50) -> float:
+        """lgt_hop_benchmark: mean duration (ms) of one even/odd hop launch."""
+        ms = ctypes.c_double()
+        self._bind_stream()
+        st = self.lib.lgt_hop_benchmark(self.ctx, self._field(U, "gauge", "U"), self._field(psi, "spinor", "psi"),
+                                        _PRECISIONS[precision], int(nrep), ctypes.byref(ms))
+        _check(self.lib, self.ctx, st)
+        return ms.value
+
+
+# Module-level functions with the ABI's names.
+def lgt_create(dims, fermion_bc: int = -1) -> Lattice:
+    return Lattice(dims, fermion_bc)
+
+
+def lgt_dslash(lat: Lattice, U, psi, kappa, dagger=False, out=None):
+    return lat.dslash(U, psi, kappa, dagger, out)
+
+
+def lgt_cg_solve(lat: Lattice, U, phi, kappa, params=None, want_y=True):
+    return lat.cg_solve(U, phi, kappa, params, want_y)
+
+
+def lgt_action(lat: Lattice, U, phi, beta, kappa, params=None, gauge=True, fermion=True):
+    return lat.action(U, phi, beta, kappa, params, gauge, fermion)
+
+
+def lgt_fermion_force(lat: Lattice, U, phi, kappa, params=None, mode="force", dt=0.0, out=None):
+    return lat.fermion_force(U, phi, kappa, params, mode, dt, out)
+
+
+def lgt_bilinear_force(lat: Lattice, U, a, b, kappa, coeff, mode="force", dt=0.0, out=None):
+    return lat.bilinear_force(U, a, b, kappa, coeff, mode, dt, out)
+
+
+def lgt_gauge_force(lat: Lattice, U, beta, mode="force", dt=0.0, out=None):
+    return lat.gauge_force(U, beta, mode, dt, out)
+
+
+def lgt_link_update(lat: Lattice, U, P, dt):
+    return lat.link_update(U, P, dt)
+
+
+def lgt_kinetic(lat: Lattice, P):
+    return lat.kinetic(P)
+
+
+def lgt_md_step(lat: Lattice, U, P, phi, beta, kappa, dt, nsteps, params=None):
+    return lat.md_step(U, P, phi, beta, kappa, dt, nsteps, params)
+
+
+def lgt_hop_benchmark(lat: Lattice, U, psi, precision="fp64", nrep=50):
+    return lat.hop_benchmark(U, psi, precision, nrep)

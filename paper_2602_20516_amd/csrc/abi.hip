@@ -1,0 +1,438 @@
+// The C ABI (include/lgt.h): argument checking, layout conversion of the
+// caller's canonical buffers, and the drivers that sequence the kernels.
+// No C++ exception crosses this boundary.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "lgt_ctx.h"
+
+using namespace lgt;
+
+namespace {
+
+std::string g_create_error;
+
+enum { kPhi = 0, kX = 1, kY = 2, kStageA = 11, kStageB = 12 };
+
+template <typename F>
+lgt_status guarded(lgt_ctx* ctx, F&& f) {
+  try {
+    if (ctx) ctx->err.clear();
+    f();
+    return LGT_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->err = e.what();
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->err = "host allocation failed";
+    return LGT_ERR_OUT_OF_MEMORY;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what();
+    return LGT_ERR_DEVICE;
+  } catch (...) {
+    if (ctx) ctx->err = "unknown error";
+    return LGT_ERR_DEVICE;
+  }
+}
+
+void require(bool ok, const char* msg) {
+  if (!ok) throw Error(LGT_ERR_INVALID_ARGUMENT, msg);
+}
+
+SolverOpts parse(const lgt_solver_params* p) {
+  SolverOpts o;
+  if (!p) return o;
+  require(p->precision >= LGT_FP64 && p->precision <= LGT_MIXED_BF16, "unknown precision");
+  require(p->even_odd == 1 || p->even_odd == 0, "even_odd must be 0 or 1");
+  if (p->even_odd == 0) throw Error(LGT_ERR_UNSUPPORTED, "only the even/odd solver is implemented");
+  if (p->precision == LGT_MIXED_BF16) throw Error(LGT_ERR_UNSUPPORTED, "bfloat16 spinor storage is not implemented");
+  require(std::isfinite(p->tol) && p->tol > 0.0, "tol must be positive");
+  o.precision = p->precision;
+  o.tol = p->tol;
+  o.max_iter = p->max_iter > 0 ? p->max_iter : 20000;
+  o.delta = p->reliable_delta > 0.0 && p->reliable_delta < 1.0 ? p->reliable_delta : 0.1;
+  return o;
+}
+
+void check_nonfinite(lgt_ctx* c, const char* what) {
+  LGT_HIP(hipMemcpyAsync(c->host_flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+  if (c->host_flags[0]) {
+    LGT_HIP(hipMemsetAsync(c->flags, 0, sizeof(int), c->stream));
+    throw Error(LGT_ERR_NONFINITE, std::string(what) + " holds NaN or Inf");
+  }
+}
+
+void pack_links(lgt_ctx* c, const void* U, bool with32) {
+  if (with32) c->ensure_u32();
+  LGT_HIP(launch_pack(c->g, 36, (const double2*)U, c->U64, with32 ? c->U32 : nullptr, c->flags, c->stream));
+}
+
+void pack_spinor(lgt_ctx* c, const void* in, double2* out) {
+  LGT_HIP(launch_pack(c->g, 12, (const double2*)in, out, nullptr, c->flags, c->stream));
+}
+
+void fill_stats(lgt_solver_stats* out, const SolveStats& s, double ms) {
+  if (!out) return;
+  out->iters = s.iters;
+  out->reliable_updates = s.reliable;
+  out->true_rel_residual = s.true_res;
+  out->ms = ms;
+}
+
+struct Timer {
+  lgt_ctx* c;
+  explicit Timer(lgt_ctx* cc) : c(cc) { LGT_HIP(hipEventRecord(c->ev0, c->stream)); }
+  double stop() {
+    LGT_HIP(hipEventRecord(c->ev1, c->stream));
+    LGT_HIP(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    LGT_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    return ms;
+  }
+};
+
+double gauge_action(lgt_ctx* c, double beta) {
+  LGT_HIP(launch_plaquette(c->g, c->U64, c->red(), 0, c->stream));
+  c->read_results(1);
+  return beta * (6.0 * (double)c->V - c->host_result[0] / 3.0);
+}
+
+void merge(SolveStats& acc, const SolveStats& s) {
+  acc.iters += s.iters;
+  acc.reliable += s.reliable;
+  acc.true_res = std::max(acc.true_res, s.true_res);
+  acc.converged = acc.converged && s.converged;
+}
+
+}  // namespace
+
+extern "C" {
+
+lgt_status lgt_create(const lgt_geom* geom, void* hip_stream, lgt_ctx** out) {
+  g_create_error.clear();
+  if (!geom || !out) {
+    g_create_error = "null argument";
+    return LGT_ERR_INVALID_ARGUMENT;
+  }
+  *out = nullptr;
+  for (int i = 0; i < 4; ++i) {
+    if (geom->dims[i] < 2 || geom->dims[i] % 2 != 0) {
+      g_create_error = "every lattice extent must be even and >= 2";
+      return LGT_ERR_INVALID_ARGUMENT;
+    }
+  }
+  if (geom->fermion_t_bc != 1 && geom->fermion_t_bc != -1) {
+    g_create_error = "fermion_t_bc must be +1 or -1";
+    return LGT_ERR_INVALID_ARGUMENT;
+  }
+  const int64_t V = (int64_t)geom->dims[0] * geom->dims[1] * geom->dims[2] * geom->dims[3];
+  // 72 complex per site (links) must index within int32 in the kernels
+  if (V > (int64_t)1 << 26) {
+    g_create_error = "lattice too large (V > 2^26)";
+    return LGT_ERR_INVALID_ARGUMENT;
+  }
+  lgt_ctx* c = new (std::nothrow) lgt_ctx();
+  if (!c) {
+    g_create_error = "host allocation failed";
+    return LGT_ERR_OUT_OF_MEMORY;
+  }
+  lgt_status st = guarded(c, [&] {
+    for (int i = 0; i < 4; ++i) c->g.L[i] = geom->dims[i];
+    c->g.hx = geom->dims[0] / 2;
+    c->V = V;
+    c->vh = (int)(V / 2);
+    c->g.vh = c->vh;
+    c->g.bc = geom->fermion_t_bc;
+    c->stream = (hipStream_t)hip_stream;
+    LGT_HIP(hipGetDevice(&c->device));
+    LGT_HIP(hipMalloc(&c->U64, (size_t)72 * c->vh * sizeof(double2)));
+    LGT_HIP(hipMalloc(&c->state, sizeof(SolverState)));
+    LGT_HIP(hipMalloc(&c->partials, (size_t)reduce_capacity(c->vh) * 4 * sizeof(double)));
+    LGT_HIP(hipMalloc(&c->ticket, 64 * sizeof(unsigned)));
+    LGT_HIP(hipMalloc(&c->result, 64 * sizeof(double)));
+    LGT_HIP(hipMalloc(&c->flags, 16 * sizeof(int)));
+    LGT_HIP(hipHostMalloc(&c->host_result, 64 * sizeof(double), hipHostMallocDefault));
+    LGT_HIP(hipHostMalloc(&c->host_flags, 16 * sizeof(int), hipHostMallocDefault));
+    LGT_HIP(hipHostMalloc(&c->host_state, sizeof(SolverState), hipHostMallocDefault));
+    LGT_HIP(hipMemsetAsync(c->ticket, 0, 64 * sizeof(unsigned), c->stream));
+    LGT_HIP(hipMemsetAsync(c->flags, 0, 16 * sizeof(int), c->stream));
+    LGT_HIP(hipMemsetAsync(c->state, 0, sizeof(SolverState), c->stream));
+    LGT_HIP(hipEventCreate(&c->ev0));
+    LGT_HIP(hipEventCreate(&c->ev1));
+    c->sync();
+  });
+  if (st != LGT_OK) {
+    g_create_error = c->err;
+    lgt_destroy(c);
+    return st;
+  }
+  *out = c;
+  return LGT_OK;
+}
+
+lgt_status lgt_destroy(lgt_ctx* c) {
+  if (!c) return LGT_OK;
+  if (c->stream || c->U64) (void)hipStreamSynchronize(c->stream);
+  for (auto* p : c->full64) (void)hipFree(p);
+  for (auto* p : c->half32) (void)hipFree(p);
+  (void)hipFree(c->U64);
+  (void)hipFree(c->U32);
+  (void)hipFree(c->P64);
+  (void)hipFree(c->state);
+  (void)hipFree(c->partials);
+  (void)hipFree(c->ticket);
+  (void)hipFree(c->result);
+  (void)hipFree(c->flags);
+  if (c->host_result) (void)hipHostFree(c->host_result);
+  if (c->host_flags) (void)hipHostFree(c->host_flags);
+  if (c->host_state) (void)hipHostFree(c->host_state);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+  return LGT_OK;
+}
+
+const char* lgt_last_error(const lgt_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+lgt_status lgt_set_stream(lgt_ctx* c, void* hip_stream) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  c->stream = (hipStream_t)hip_stream;
+  return LGT_OK;
+}
+
+int64_t lgt_volume(const lgt_ctx* c) { return c ? c->V : 0; }
+
+lgt_status lgt_dslash(lgt_ctx* c, const void* U, const void* in, void* out, double kappa, int32_t dagger) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(U && in && out, "null field pointer");
+    require(std::isfinite(kappa), "kappa must be finite");
+    pack_links(c, U, false);
+    double2* a = c->f64(kStageA);
+    double2* b = c->f64(kStageB);
+    pack_spinor(c, in, a);
+    c->dslash_full(a, b, kappa, dagger != 0);
+    LGT_HIP(launch_unpack(c->g, 12, b, (double2*)out, c->stream));
+  });
+}
+
+lgt_status lgt_cg_solve(lgt_ctx* c, const void* U, const void* phi, void* X, void* Y, double kappa,
+                        const lgt_solver_params* params, lgt_solver_stats* stats) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  bool nc = false;
+  lgt_status s = guarded(c, [&] {
+    require(U && phi && X, "null field pointer");
+    require(std::isfinite(kappa), "kappa must be finite");
+    const SolverOpts o = parse(params);
+    Timer tm(c);
+    pack_links(c, U, o.precision != LGT_FP64);
+    pack_spinor(c, phi, c->f64(kPhi));
+    check_nonfinite(c, "U or phi");
+    c->kappa = kappa;
+    SolveStats st = c->solve_ddagd(c->f64(kPhi), c->f64(kX), c->f64(kY), o);
+    LGT_HIP(launch_unpack(c->g, 12, c->f64(kX), (double2*)X, c->stream));
+    if (Y) LGT_HIP(launch_unpack(c->g, 12, c->f64(kY), (double2*)Y, c->stream));
+    fill_stats(stats, st, tm.stop());
+    nc = !st.converged;
+  });
+  if (s == LGT_OK && nc) {
+    c->err = "solver did not reach the tolerance";
+    return LGT_ERR_NOT_CONVERGED;
+  }
+  return s;
+}
+
+lgt_status lgt_action(lgt_ctx* c, const void* U, const void* phi, double beta, double kappa,
+                      const lgt_solver_params* params, double* S_G, double* S_F, lgt_solver_stats* stats) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  bool nc = false;
+  lgt_status s = guarded(c, [&] {
+    require(U != nullptr, "null U");
+    require(!S_F || phi, "S_F requested without phi");
+    const SolverOpts o = parse(params);
+    Timer tm(c);
+    pack_links(c, U, o.precision != LGT_FP64 && S_F);
+    if (S_F) pack_spinor(c, phi, c->f64(kPhi));
+    check_nonfinite(c, "U or phi");
+    if (S_G) *S_G = gauge_action(c, beta);
+    SolveStats st;
+    if (S_F) {
+      c->kappa = kappa;
+      st = c->solve_ddagd(c->f64(kPhi), c->f64(kX), c->f64(kY), o);
+      *S_F = c->action_fermion(c->f64(kPhi), c->f64(kX), c->f64(kY));
+    }
+    fill_stats(stats, st, tm.stop());
+    nc = !st.converged;
+  });
+  if (s == LGT_OK && nc) {
+    c->err = "solver did not reach the tolerance";
+    return LGT_ERR_NOT_CONVERGED;
+  }
+  return s;
+}
+
+lgt_status lgt_fermion_force(lgt_ctx* c, const void* U, const void* phi, double kappa,
+                             const lgt_solver_params* params, int32_t mode, double dt, void* out,
+                             lgt_solver_stats* stats) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  bool nc = false;
+  lgt_status s = guarded(c, [&] {
+    require(U && phi && out, "null field pointer");
+    require(mode >= LGT_OUT_FORCE && mode <= LGT_OUT_MOMENTUM, "unknown output mode");
+    const SolverOpts o = parse(params);
+    Timer tm(c);
+    pack_links(c, U, o.precision != LGT_FP64);
+    pack_spinor(c, phi, c->f64(kPhi));
+    check_nonfinite(c, "U or phi");
+    c->kappa = kappa;
+    SolveStats st = c->solve_ddagd(c->f64(kPhi), c->f64(kX), c->f64(kY), o);
+    LGT_HIP(launch_bilinear_force(c->g, c->U64, c->f64(kY), c->f64(kX), kappa, -2.0, mode, dt, out, kCanonical,
+                                  c->stream));
+    fill_stats(stats, st, tm.stop());
+    nc = !st.converged;
+  });
+  if (s == LGT_OK && nc) {
+    c->err = "solver did not reach the tolerance";
+    return LGT_ERR_NOT_CONVERGED;
+  }
+  return s;
+}
+
+lgt_status lgt_bilinear_force(lgt_ctx* c, const void* U, const void* a, const void* b, double kappa, double coeff,
+                              int32_t mode, double dt, void* out) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(U && a && b && out, "null field pointer");
+    require(mode >= LGT_OUT_FORCE && mode <= LGT_OUT_MOMENTUM, "unknown output mode");
+    pack_links(c, U, false);
+    pack_spinor(c, a, c->f64(kStageA));
+    pack_spinor(c, b, c->f64(kStageB));
+    LGT_HIP(launch_bilinear_force(c->g, c->U64, c->f64(kStageA), c->f64(kStageB), kappa, coeff, mode, dt, out,
+                                  kCanonical, c->stream));
+  });
+}
+
+lgt_status lgt_gauge_force(lgt_ctx* c, const void* U, double beta, int32_t mode, double dt, void* out) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(U && out, "null field pointer");
+    require(mode >= LGT_OUT_FORCE && mode <= LGT_OUT_MOMENTUM, "unknown output mode");
+    pack_links(c, U, false);
+    LGT_HIP(launch_gauge_force(c->g, c->U64, beta, mode, dt, out, kCanonical, c->stream));
+  });
+}
+
+lgt_status lgt_link_update(lgt_ctx* c, void* U, const void* P, double dt) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(U && P, "null field pointer");
+    LGT_HIP(launch_link_update(c->g, (double2*)U, (const double2*)P, dt, kCanonical, nullptr, c->stream));
+  });
+}
+
+lgt_status lgt_kinetic(lgt_ctx* c, const void* P, double* K) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(P && K, "null pointer");
+    LGT_HIP(launch_kinetic(c->g, (const double2*)P, kCanonical, c->red(), 0, c->stream));
+    c->read_results(1);
+    *K = c->host_result[0];
+  });
+}
+
+lgt_status lgt_md_step(lgt_ctx* c, void* U, void* P, const void* phi, double beta, double kappa, double dt,
+                       int32_t nsteps, const lgt_solver_params* params, double* dH, lgt_solver_stats* stats) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  bool nc = false;
+  lgt_status s = guarded(c, [&] {
+    require(U && P, "null field pointer");
+    require(nsteps >= 1, "nsteps must be >= 1");
+    require(std::isfinite(dt), "dt must be finite");
+    const SolverOpts o = parse(params);
+    const bool ferm = phi != nullptr && kappa != 0.0;
+    const bool mixed = ferm && o.precision != LGT_FP64;
+    Timer tm(c);
+    c->ensure_p64();
+    pack_links(c, U, mixed);
+    LGT_HIP(launch_pack(c->g, 36, (const double2*)P, c->P64, nullptr, c->flags, c->stream));
+    if (ferm) pack_spinor(c, phi, c->f64(kPhi));
+    check_nonfinite(c, "U, P or phi");
+    c->kappa = kappa;
+    SolveStats all;
+    double sf0 = 0.0, sf1 = 0.0;
+
+    LGT_HIP(launch_kinetic(c->g, c->P64, kPacked, c->red(), 0, c->stream));
+    c->read_results(1);
+    const double k0 = c->host_result[0];
+    const double sg0 = gauge_action(c, beta);
+
+    auto kick = [&](double h, bool first, bool last) {
+      LGT_HIP(launch_gauge_force(c->g, c->U64, beta, LGT_OUT_MOMENTUM, h, c->P64, kPacked, c->stream));
+      if (!ferm) return;
+      SolveStats st = c->solve_ddagd(c->f64(kPhi), c->f64(kX), c->f64(kY), o);
+      merge(all, st);
+      if (first) sf0 = c->action_fermion(c->f64(kPhi), c->f64(kX), c->f64(kY));
+      if (last) sf1 = c->action_fermion(c->f64(kPhi), c->f64(kX), c->f64(kY));
+      LGT_HIP(launch_bilinear_force(c->g, c->U64, c->f64(kY), c->f64(kX), kappa, -2.0, LGT_OUT_MOMENTUM, h,
+                                    c->P64, kPacked, c->stream));
+    };
+    kick(0.5 * dt, true, false);
+    for (int k = 0; k < nsteps; ++k) {
+      LGT_HIP(launch_link_update(c->g, c->U64, c->P64, dt, kPacked, mixed ? c->U32 : nullptr, c->stream));
+      const bool last = k == nsteps - 1;
+      kick(last ? 0.5 * dt : dt, false, last);
+    }
+    LGT_HIP(launch_kinetic(c->g, c->P64, kPacked, c->red(), 0, c->stream));
+    c->read_results(1);
+    const double k1 = c->host_result[0];
+    const double sg1 = gauge_action(c, beta);
+    if (dH) *dH = (k1 - k0) + (sg1 - sg0) + (sf1 - sf0);
+    LGT_HIP(launch_unpack(c->g, 36, c->U64, (double2*)U, c->stream));
+    LGT_HIP(launch_unpack(c->g, 36, c->P64, (double2*)P, c->stream));
+    fill_stats(stats, all, tm.stop());
+    nc = !all.converged;
+  });
+  if (s == LGT_OK && nc) {
+    c->err = "solver did not reach the tolerance";
+    return LGT_ERR_NOT_CONVERGED;
+  }
+  return s;
+}
+
+lgt_status lgt_hop_benchmark(lgt_ctx* c, const void* U, const void* psi, int32_t precision, int32_t nrep,
+                             double* avg_ms) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(U && psi && avg_ms && nrep >= 1, "invalid argument");
+    const bool f32 = precision != LGT_FP64;
+    pack_links(c, U, f32);
+    double2* a = c->f64(kStageA);
+    double2* b = c->f64(kStageB);
+    pack_spinor(c, psi, a);
+    const size_t h = c->half_elems();
+    float2* a32 = nullptr;
+    float2* b32 = nullptr;
+    if (f32) {
+      a32 = c->h32(5);
+      b32 = c->h32(6);
+      LGT_HIP(launch_convert_64_32((int)h, a + h, a32, c->stream));
+    }
+    auto once = [&] {
+      if (f32) {
+        HopIn<float> hin{c->U32, a32, a32};
+        LGT_HIP((launch_hop_axpy<float, false>(c->g, 0, hin, b32, b32, nullptr, nullptr, 1.0, c->stream)));
+      } else {
+        HopIn<double> hin{c->U64, a + h, a + h};
+        LGT_HIP((launch_hop_axpy<double, false>(c->g, 0, hin, b, b, nullptr, nullptr, 1.0, c->stream)));
+      }
+    };
+    once();  // warm-up
+    Timer tm(c);
+    for (int i = 0; i < nrep; ++i) once();
+    *avg_ms = tm.stop() / nrep;
+  });
+}
+
+}  // extern "C"

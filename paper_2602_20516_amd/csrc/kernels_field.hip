@@ -1,0 +1,314 @@
+// Layout conversion and vector (BLAS-1) kernels of the solver.
+//
+// Layout conversion: the ABI's canonical site-major complex128 arrays
+// [V][nc] are transposed, through LDS, into the internal even/odd
+// structure-of-arrays [parity][nc][V/2], so both the global reads and the
+// global writes are unit-stride across a wavefront.
+//
+// Vector kernels work on flat arrays of n complex numbers (grid-stride,
+// unit-stride).  Reductions are deterministic (see grid_sum).
+#include "lgt_internal.h"
+
+namespace lgt {
+
+constexpr int kPackSites = 64;  // lexicographic sites per pack block (32 per parity)
+
+template <int NC, bool W32>
+__global__ __launch_bounds__(256) void k_pack(Geom g, const double2* __restrict__ canon,
+                                              double2* __restrict__ out64, float2* __restrict__ out32,
+                                              int* nonfinite) {
+  __shared__ double2 tile[NC][kPackSites];
+  __shared__ int par[kPackSites];
+  const int V = 2 * g.vh;
+  const int s0 = blockIdx.x * kPackSites;
+  const int nsite = min(kPackSites, V - s0);
+  bool bad = false;
+  for (int e = threadIdx.x; e < nsite * NC; e += 256) {
+    double2 v = canon[(size_t)s0 * NC + e];
+    bad |= !(isfinite(v.x) && isfinite(v.y));
+    tile[e % NC][e / NC] = v;
+  }
+  if (threadIdx.x < nsite) {
+    int c[4];
+    lex_coords(g, s0 + threadIdx.x, c);
+    par[threadIdx.x] = parity_of(c);
+  }
+  if (bad && nonfinite) atomicOr(nonfinite, 1);
+  __syncthreads();
+  const int half = kPackSites / 2;
+  const int cb0 = s0 / 2;
+  for (int e = threadIdx.x; e < 2 * NC * half; e += 256) {
+    const int p = e / (NC * half);
+    const int k = (e / half) % NC;
+    const int j = e % half;
+    if (2 * j >= nsite) continue;
+    // of the two sites s0+2j, s0+2j+1 (same cb index) pick the one of parity p
+    const int site = (par[2 * j] == p) ? 2 * j : 2 * j + 1;
+    const double2 v = tile[k][site];
+    const size_t o = ((size_t)p * NC + k) * g.vh + cb0 + j;
+    out64[o] = v;
+    if (W32) out32[o] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void k_unpack(Geom g, const double2* __restrict__ packed,
+                                                double2* __restrict__ canon) {
+  __shared__ double2 tile[NC][kPackSites];
+  __shared__ int par[kPackSites];
+  const int V = 2 * g.vh;
+  const int s0 = blockIdx.x * kPackSites;
+  const int nsite = min(kPackSites, V - s0);
+  if (threadIdx.x < nsite) {
+    int c[4];
+    lex_coords(g, s0 + threadIdx.x, c);
+    par[threadIdx.x] = parity_of(c);
+  }
+  __syncthreads();
+  const int half = kPackSites / 2;
+  const int cb0 = s0 / 2;
+  for (int e = threadIdx.x; e < 2 * NC * half; e += 256) {
+    const int p = e / (NC * half);
+    const int k = (e / half) % NC;
+    const int j = e % half;
+    if (2 * j >= nsite) continue;
+    const int site = (par[2 * j] == p) ? 2 * j : 2 * j + 1;
+    tile[k][site] = packed[((size_t)p * NC + k) * g.vh + cb0 + j];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nsite * NC; e += 256) canon[(size_t)s0 * NC + e] = tile[e % NC][e / NC];
+}
+
+hipError_t launch_pack(const Geom& g, int nc, const double2* canon, double2* out64, float2* out32,
+                       int* nonfinite, hipStream_t s) {
+  const int V = 2 * g.vh;
+  const int nb = (V + kPackSites - 1) / kPackSites;
+  if (nc == 12) {
+    if (out32) hipLaunchKernelGGL((k_pack<12, true>), dim3(nb), dim3(256), 0, s, g, canon, out64, out32, nonfinite);
+    else hipLaunchKernelGGL((k_pack<12, false>), dim3(nb), dim3(256), 0, s, g, canon, out64, out32, nonfinite);
+  } else if (nc == 36) {
+    if (out32) hipLaunchKernelGGL((k_pack<36, true>), dim3(nb), dim3(256), 0, s, g, canon, out64, out32, nonfinite);
+    else hipLaunchKernelGGL((k_pack<36, false>), dim3(nb), dim3(256), 0, s, g, canon, out64, out32, nonfinite);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Geom& g, int nc, const double2* packed, double2* canon, hipStream_t s) {
+  const int V = 2 * g.vh;
+  const int nb = (V + kPackSites - 1) / kPackSites;
+  if (nc == 12) hipLaunchKernelGGL((k_unpack<12>), dim3(nb), dim3(256), 0, s, g, packed, canon);
+  else if (nc == 36) hipLaunchKernelGGL((k_unpack<36>), dim3(nb), dim3(256), 0, s, g, packed, canon);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels
+// ---------------------------------------------------------------------------
+static inline int vec_blocks(int n) {
+  int nb = (n + 255) / 256;
+  return nb < 1024 ? (nb < 1 ? 1 : nb) : 1024;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_init(int n, const R2<R>* __restrict__ b, R2<R>* __restrict__ r,
+                                                 R2<R>* __restrict__ p, R2<R>* __restrict__ x,
+                                                 SolverState* st, double* partials, unsigned* ticket,
+                                                 double tol, int max_iter) {
+  double acc = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const R2<R> v = b[i];
+    r[i] = v;
+    p[i] = v;
+    R2<R> z;
+    z.x = R(0);
+    z.y = R(0);
+    x[i] = z;
+    acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+  }
+  double v[1] = {acc}, tot[1];
+  if (grid_sum<256, 1>(v, partials, ticket, blockIdx.x, gridDim.x, tot) && threadIdx.x == 0) {
+    const double rr = tot[0];
+    st->rr = rr;
+    st->rr0 = rr;
+    st->rr_max = rr;
+    st->rr_stop = tol * tol * rr;
+    st->iter = 0;
+    st->max_iter = max_iter;
+    st->alpha = 0.0;
+    st->beta = 0.0;
+    st->pap = 0.0;
+    st->done = !isfinite(rr) ? kDoneBreakdown : (rr == 0.0 ? kDoneConverged : kDoneRunning);
+  }
+}
+
+template <typename R>
+hipError_t launch_cg_init(int n, const R2<R>* b, R2<R>* r, R2<R>* p, R2<R>* x, SolverState* st,
+                          Reduce red, double tol, int max_iter, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_init<R>), dim3(vec_blocks(n)), dim3(256), 0, s, n, b, r, p, x, st,
+                     red.partials, red.ticket, tol, max_iter);
+  return hipGetLastError();
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_xpay(int n, const R2<R>* __restrict__ r, R2<R>* __restrict__ p,
+                                                 const SolverState* st) {
+  if (st->done != kDoneRunning) return;
+  const R beta = R(st->beta);
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const R2<R> rv = r[i];
+    R2<R> pv = p[i];
+    pv.x = rv.x + beta * pv.x;
+    pv.y = rv.y + beta * pv.y;
+    p[i] = pv;
+  }
+}
+
+template <typename R>
+hipError_t launch_cg_xpay(int n, const R2<R>* r, R2<R>* p, SolverState* st, hipStream_t s) {
+  const int nb = (n + 255) / 256;
+  hipLaunchKernelGGL((k_cg_xpay<R>), dim3(nb), dim3(256), 0, s, n, r, p, st);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_norm_dot(int n, const double2* __restrict__ a,
+                                                  const double2* __restrict__ b, double* partials,
+                                                  unsigned* ticket, double* result) {
+  double nn = 0.0, dd = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const double2 av = a[i];
+    nn += av.x * av.x + av.y * av.y;
+    if (b) {
+      const double2 bv = b[i];
+      dd += av.x * bv.x + av.y * bv.y;
+    }
+  }
+  double v[2] = {nn, dd}, tot[2];
+  if (grid_sum<256, 2>(v, partials, ticket, blockIdx.x, gridDim.x, tot) && threadIdx.x == 0) {
+    result[0] = tot[0];
+    result[1] = tot[1];
+  }
+}
+
+hipError_t launch_norm_dot(int n, const double2* a, const double2* b, Reduce red, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_dot, dim3(vec_blocks(n)), dim3(256), 0, s, n, a, b, red.partials, red.ticket,
+                     red.result + slot);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_axpy64(int n, double a, const double2* __restrict__ x,
+                                                double2* __restrict__ y) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const double2 xv = x[i];
+    double2 yv = y[i];
+    yv.x += a * xv.x;
+    yv.y += a * xv.y;
+    y[i] = yv;
+  }
+}
+hipError_t launch_axpy64(int n, double a, const double2* x, double2* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy64, dim3((n + 255) / 256), dim3(256), 0, s, n, a, x, y);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_copy64(int n, const double2* __restrict__ x, double2* __restrict__ y) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) y[i] = x[i];
+}
+hipError_t launch_copy64(int n, const double2* x, double2* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy64, dim3((n + 255) / 256), dim3(256), 0, s, n, x, y);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_xmy64(int n, const double2* __restrict__ x, double2* __restrict__ y) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const double2 xv = x[i];
+    double2 yv = y[i];
+    yv.x = xv.x - yv.x;
+    yv.y = xv.y - yv.y;
+    y[i] = yv;
+  }
+}
+hipError_t launch_xmy64(int n, const double2* x, double2* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_xmy64, dim3((n + 255) / 256), dim3(256), 0, s, n, x, y);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_zero64(int n, double2* __restrict__ y) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) y[i] = make_double2(0.0, 0.0);
+}
+hipError_t launch_zero64(int n, double2* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero64, dim3((n + 255) / 256), dim3(256), 0, s, n, y);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_convert_64_32(int n, const double2* __restrict__ x, float2* __restrict__ y) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const double2 v = x[i];
+    y[i] = make_float2((float)v.x, (float)v.y);
+  }
+}
+hipError_t launch_convert_64_32(int n, const double2* x, float2* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert_64_32, dim3((n + 255) / 256), dim3(256), 0, s, n, x, y);
+  return hipGetLastError();
+}
+
+// x (FP64) += xs (FP32); xs = 0
+__global__ __launch_bounds__(256) void k_mixed_update(int n, float2* xs, double2* __restrict__ x) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const float2 v = xs[i];
+    double2 xv = x[i];
+    xv.x += (double)v.x;
+    xv.y += (double)v.y;
+    x[i] = xv;
+    xs[i] = make_float2(0.f, 0.f);
+  }
+}
+hipError_t launch_mixed_update(int n, float2* xs, double2* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_mixed_update, dim3((n + 255) / 256), dim3(256), 0, s, n, xs, x);
+  return hipGetLastError();
+}
+
+// Reliable update: r (low precision) = r64; rr = |r64|^2 (FP64); new beta
+// keeps the search direction: beta = rr_new / rr_old.
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_reliable(int n, const double2* __restrict__ r64, R2<R>* __restrict__ r,
+                                                     SolverState* st, double* partials, unsigned* ticket) {
+  double acc = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const double2 v = r64[i];
+    R2<R> w;
+    w.x = R(v.x);
+    w.y = R(v.y);
+    r[i] = w;
+    acc += v.x * v.x + v.y * v.y;
+  }
+  double v[1] = {acc}, tot[1];
+  if (grid_sum<256, 1>(v, partials, ticket, blockIdx.x, gridDim.x, tot) && threadIdx.x == 0) {
+    const double rr = tot[0];
+    st->rr = rr;
+    st->rr_max = rr;
+    if (!isfinite(rr)) st->done = kDoneBreakdown;
+    else if (rr <= st->rr_stop) st->done = kDoneConverged;
+    else if (st->iter >= st->max_iter) st->done = kDoneMaxIter;
+    else st->done = kDoneRunning;
+  }
+}
+template <typename R>
+hipError_t launch_cg_reliable(int n, const double2* r64, R2<R>* r, SolverState* st, Reduce red, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_reliable<R>), dim3(vec_blocks(n)), dim3(256), 0, s, n, r64, r, st, red.partials,
+                     red.ticket);
+  return hipGetLastError();
+}
+
+template hipError_t launch_cg_init<double>(int, const double2*, double2*, double2*, double2*, SolverState*,
+                                           Reduce, double, int, hipStream_t);
+template hipError_t launch_cg_init<float>(int, const float2*, float2*, float2*, float2*, SolverState*, Reduce,
+                                          double, int, hipStream_t);
+template hipError_t launch_cg_xpay<double>(int, const double2*, double2*, SolverState*, hipStream_t);
+template hipError_t launch_cg_xpay<float>(int, const float2*, float2*, SolverState*, hipStream_t);
+template hipError_t launch_cg_reliable<float>(int, const double2*, float2*, SolverState*, Reduce, hipStream_t);
+template hipError_t launch_cg_reliable<double>(int, const double2*, double2*, SolverState*, Reduce, hipStream_t);
+
+}  // namespace lgt

@@ -1,0 +1,406 @@
+// Adjoint (force) kernels, gauge action, kinetic energy and the link update.
+//
+// Conventions (Sec. S2): G = dS/dRe U + i dS/dIm U, delta S = Re tr(G^dag dU),
+// F = -1/2 P_su3[U G^dag] with P_su3 the traceless anti-Hermitian projection
+// of eq. (6); the momentum update is P <- P - dt F.
+//
+// Thread mapping of the per-link kernels: thread t handles link (s, mu) with
+// s = t/4 the lexicographic site and mu = t%4, so a wavefront covers 16
+// consecutive sites and its canonical [V][4][3][3] output is one contiguous
+// 9 KB span.
+#include "lgt_internal.h"
+
+namespace lgt {
+
+// ---------------------------------------------------------------------------
+// Spin projection with a per-lane direction: B_mu of gamma_mu = [[0,B],[B^dag,0]]
+// in the chiral basis, B_0 = -i sigma_1, B_1 = -i sigma_2, B_2 = -i sigma_3, B_3 = 1.
+// h = psi_up + s * B_mu psi_dn (per colour).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void b_matrix(int mu, C<double> B[4]) {
+  const C<double> z = {0.0, 0.0}, one = {1.0, 0.0}, mone = {-1.0, 0.0}, mi = {0.0, -1.0}, pi = {0.0, 1.0};
+  B[0] = mu == 2 ? mi : (mu == 3 ? one : z);
+  B[1] = mu == 0 ? mi : (mu == 1 ? mone : z);
+  B[2] = mu == 0 ? mi : (mu == 1 ? one : z);
+  B[3] = mu == 2 ? pi : (mu == 3 ? one : z);
+}
+
+// load a spinor (12 complex) at (parity half pointer, cb) and return its
+// projection h (6 complex: [spin a][colour]) for sign s
+__device__ __forceinline__ void load_project(const double2* __restrict__ half, int vh, int cb,
+                                             const C<double> B[4], double s, C<double> h[6]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const C<double> u0 = ld<double>(half + (size_t)i * vh + cb);
+    const C<double> u1 = ld<double>(half + (size_t)(3 + i) * vh + cb);
+    const C<double> d0 = ld<double>(half + (size_t)(6 + i) * vh + cb);
+    const C<double> d1 = ld<double>(half + (size_t)(9 + i) * vh + cb);
+    h[i] = u0 + s * (B[0] * d0 + B[1] * d1);
+    h[3 + i] = u1 + s * (B[2] * d0 + B[3] * d1);
+  }
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ size_t link_elem(const Geom& g, int s, int p, int cb, int mu, int k) {
+  if (LAYOUT == kCanonical) return ((size_t)s * 4 + mu) * 9 + k;
+  return ((size_t)(p * 4 + mu) * 9 + k) * g.vh + cb;
+}
+
+// Write F (mode 0), G (mode 1) or P -= dt F (mode 2) for one link.
+template <int LAYOUT>
+__device__ __forceinline__ void emit(const Geom& g, double2* out, int s, int p, int cb, int mu, int mode,
+                                     double dt, const M3<double>& F, const M3<double>& G) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double2* q = out + link_elem<LAYOUT>(g, s, p, cb, mu, k);
+    if (mode == 1) {
+      st<double>(q, G.m[k]);
+    } else if (mode == 0) {
+      st<double>(q, F.m[k]);
+    } else {
+      C<double> v = ld<double>(q);
+      st<double>(q, v - dt * F.m[k]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of I(U) = a^dag D(U) b (eq. S3.13): for the link U_mu(x), with s_bc
+// its fermion boundary sign,
+//   Re I depends on U through -kappa s_bc Re tr(U Z),
+//   Z = sum_j h-[b(x+mu)]_j h-[a(x)]_j^dag + sum_j h+[a(x+mu)]_j h+[b(x)]_j^dag,
+// where h-/h+ are the projections of (1 - gamma_mu)/(1 + gamma_mu).  For the
+// functional coeff * Re I:  G = -coeff kappa s_bc Z^dag and
+// F = -1/2 P[U G^dag] = (coeff kappa s_bc / 2) P[U Z].  The pseudofermion
+// force of eq. S3.11 is coeff = -2, a = Y = D X, b = X.
+// ---------------------------------------------------------------------------
+template <int LAYOUT>
+__global__ __launch_bounds__(256) void k_bilinear(Geom g, const double2* __restrict__ U,
+                                                  const double2* __restrict__ a,
+                                                  const double2* __restrict__ b, double kappa,
+                                                  double coeff, int mode, double dt, double2* out) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int t = lb * 256 + threadIdx.x;
+  const int s = t >> 2, mu = t & 3;
+  if (s >= 2 * g.vh) return;
+  const int vh = g.vh;
+  int c[4];
+  lex_coords(g, s, c);
+  const int p = parity_of(c), cb = s >> 1;
+  const int nf = cb_shift(g, c, mu, +1);
+  const size_t half = (size_t)12 * vh;
+  C<double> B[4];
+  b_matrix(mu, B);
+  C<double> hmb[6], hma[6], hpa[6], hpb[6];
+  load_project(b + (1 - p) * half, vh, nf, B, -1.0, hmb);  // h-[b(x+mu)]
+  load_project(a + p * half, vh, cb, B, -1.0, hma);        // h-[a(x)]
+  load_project(a + (1 - p) * half, vh, nf, B, +1.0, hpa);  // h+[a(x+mu)]
+  load_project(b + p * half, vh, cb, B, +1.0, hpb);        // h+[b(x)]
+  M3<double> Z;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      C<double> z = mulcj(hmb[i], hma[k]);
+      z += mulcj(hmb[3 + i], hma[3 + k]);
+      z += mulcj(hpa[i], hpb[k]);
+      z += mulcj(hpa[3 + i], hpb[3 + k]);
+      Z.m[3 * i + k] = z;
+    }
+  const double sbc = (mu == 3 && c[3] == g.L[3] - 1) ? double(g.bc) : 1.0;
+  M3<double> F, G;
+  if (mode == 1) {
+    G = mscale(-coeff * kappa * sbc, mdag(Z));
+  } else {
+    const M3<double> Ux = load_m3<double>(gptr<double>(U, g, p, mu), vh, cb);
+    F = mscale(0.5 * coeff * kappa * sbc, proj_ta(mmul(Ux, Z)));
+  }
+  emit<LAYOUT>(g, out, s, p, cb, mu, mode, dt, F, G);
+}
+
+static inline int link_blocks(const Geom& g) { return (2 * g.vh * 4 + 255) / 256; }
+
+hipError_t launch_bilinear_force(const Geom& g, const double2* U, const double2* a_full, const double2* b_full,
+                                 double kappa, double coeff, int mode, double dt, void* out, int layout,
+                                 hipStream_t s) {
+  const int nb = link_blocks(g);
+  if (layout == kCanonical)
+    hipLaunchKernelGGL((k_bilinear<kCanonical>), dim3(nb), dim3(256), 0, s, g, U, a_full, b_full, kappa, coeff,
+                       mode, dt, (double2*)out);
+  else
+    hipLaunchKernelGGL((k_bilinear<kPacked>), dim3(nb), dim3(256), 0, s, g, U, a_full, b_full, kappa, coeff,
+                       mode, dt, (double2*)out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Wilson plaquette action: the link U_mu(x) enters S_G through
+// -(beta/3) Re tr(U_mu(x) A_mu(x)) with the staple sum
+//   A = sum_{nu != mu} [ U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+//                      + U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu) ],
+// so G = -(beta/3) A^dag and F = (beta/6) P[U A].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ M3<double> link_at(const double2* U, const Geom& g, const int c[4], int mu) {
+  return load_m3<double>(gptr<double>(U, g, parity_of(c), mu), g.vh, cb_of(g, c));
+}
+
+template <int LAYOUT>
+__global__ __launch_bounds__(256) void k_gauge_force(Geom g, const double2* __restrict__ U, double beta,
+                                                     int mode, double dt, double2* out) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int t = lb * 256 + threadIdx.x;
+  const int s = t >> 2, mu = t & 3;
+  if (s >= 2 * g.vh) return;
+  int c[4];
+  lex_coords(g, s, c);
+  const int p = parity_of(c), cb = s >> 1;
+  int xpm[4];
+  shifted(g, c, mu, +1, xpm);
+  M3<double> A;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) A.m[k] = czero<double>();
+#pragma unroll
+  for (int k = 1; k < 4; ++k) {
+    const int nu = (mu + k) & 3;
+    int xpn[4], xmn[4], xpmmn[4];
+    shifted(g, c, nu, +1, xpn);
+    shifted(g, c, nu, -1, xmn);
+    shifted(g, xpm, nu, -1, xpmmn);
+    {
+      const M3<double> u1 = link_at(U, g, xpm, nu), u2 = link_at(U, g, xpn, mu), u3 = link_at(U, g, c, nu);
+      A = madd(A, mmul_nd(mmul_nd(u1, u2), u3));
+    }
+    {
+      const M3<double> v1 = link_at(U, g, xpmmn, nu), v2 = link_at(U, g, xmn, mu), v3 = link_at(U, g, xmn, nu);
+      A = madd(A, mmul_dn(mmul(v2, v1), v3));
+    }
+  }
+  M3<double> F, G;
+  if (mode == 1) {
+    G = mscale(-beta / 3.0, mdag(A));
+  } else {
+    const M3<double> Ux = load_m3<double>(gptr<double>(U, g, p, mu), g.vh, cb);
+    F = mscale(beta / 6.0, proj_ta(mmul(Ux, A)));
+  }
+  emit<LAYOUT>(g, out, s, p, cb, mu, mode, dt, F, G);
+}
+
+hipError_t launch_gauge_force(const Geom& g, const double2* U, double beta, int mode, double dt, void* out,
+                              int layout, hipStream_t s) {
+  const int nb = link_blocks(g);
+  if (layout == kCanonical)
+    hipLaunchKernelGGL((k_gauge_force<kCanonical>), dim3(nb), dim3(256), 0, s, g, U, beta, mode, dt,
+                       (double2*)out);
+  else
+    hipLaunchKernelGGL((k_gauge_force<kPacked>), dim3(nb), dim3(256), 0, s, g, U, beta, mode, dt,
+                       (double2*)out);
+  return hipGetLastError();
+}
+
+// sum over sites and mu<nu of Re tr P_mu,nu(x)
+__global__ __launch_bounds__(256) void k_plaquette(Geom g, const double2* __restrict__ U, double* partials,
+                                                   unsigned* ticket, double* result) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int s = lb * 256 + threadIdx.x;
+  double acc = 0.0;
+  if (s < 2 * g.vh) {
+    int c[4];
+    lex_coords(g, s, c);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      int xpm[4];
+      shifted(g, c, mu, +1, xpm);
+      const M3<double> a = link_at(U, g, c, mu);
+#pragma unroll
+      for (int nu = mu + 1; nu < 4; ++nu) {
+        int xpn[4];
+        shifted(g, c, nu, +1, xpn);
+        const M3<double> ab = mmul(a, link_at(U, g, xpm, nu));
+        const M3<double> dc = mmul(link_at(U, g, c, nu), link_at(U, g, xpn, mu));
+        // Re tr(A B C^dag D^dag) = Re tr((AB)(DC)^dag)
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) t += ab.m[k].re * dc.m[k].re + ab.m[k].im * dc.m[k].im;
+        acc += t;
+      }
+    }
+  }
+  double v[1] = {acc}, tot[1];
+  if (grid_sum<256, 1>(v, partials, ticket, lb, gridDim.x, tot) && threadIdx.x == 0) result[0] = tot[0];
+}
+
+hipError_t launch_plaquette(const Geom& g, const double2* U, Reduce red, int slot, hipStream_t s) {
+  const int nb = (2 * g.vh + 255) / 256;
+  if (nb > red.capacity) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_plaquette, dim3(nb), dim3(256), 0, s, g, U, red.partials, red.ticket, red.result + slot);
+  return hipGetLastError();
+}
+
+// -sum Re tr(P P) over all links
+__global__ __launch_bounds__(256) void k_kinetic(Geom g, const double2* __restrict__ P, int layout,
+                                                 double* partials, unsigned* ticket, double* result) {
+  const int nlink = 8 * g.vh;
+  double acc = 0.0;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < nlink; t += gridDim.x * 256) {
+    M3<double> m;
+    if (layout == kCanonical) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) m.m[k] = ld<double>(P + (size_t)t * 9 + k);
+    } else {
+      const int cb = t % g.vh, pm = t / g.vh;  // pm = parity*4 + mu
+#pragma unroll
+      for (int k = 0; k < 9; ++k) m.m[k] = ld<double>(P + ((size_t)pm * 9 + k) * g.vh + cb);
+    }
+    double tr = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) tr += (m.m[3 * i + j] * m.m[3 * j + i]).re;
+    acc -= tr;
+  }
+  double v[1] = {acc}, tot[1];
+  if (grid_sum<256, 1>(v, partials, ticket, blockIdx.x, gridDim.x, tot) && threadIdx.x == 0) result[0] = tot[0];
+}
+
+hipError_t launch_kinetic(const Geom& g, const double2* P, int layout, Reduce red, int slot, hipStream_t s) {
+  int nb = (8 * g.vh + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL(k_kinetic, dim3(nb), dim3(256), 0, s, g, P, layout, red.partials, red.ticket,
+                     red.result + slot);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// exp(X) for traceless anti-Hermitian X, by Cayley-Hamilton: with Q = -iX
+// (Hermitian, traceless), exp(iQ) = f0 + f1 Q + f2 Q^2 and the f_j of
+// Morningstar & Peardon (Phys. Rev. D 69, 054501), using
+// c0 = det Q = tr(Q^3)/3, c1 = tr(Q^2)/2 and the symmetry
+// f_j(-c0) = (-1)^j conj(f_j(c0)).  Below c1 = 1e-10 a 4th-order series
+// through Q^3 = c1 Q + c0 is used instead (error < 1e-25).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ M3<double> exp_ah(const M3<double>& X) {
+  M3<double> Q;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Q.m[k] = cmk<double>(X.m[k].im, -X.m[k].re);  // -i X
+  const M3<double> Q2 = mmul(Q, Q);
+  const double c1 = 0.5 * (Q2.m[0].re + Q2.m[4].re + Q2.m[8].re);
+  double c0 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c0 += (Q2.m[3 * i + j] * Q.m[3 * j + i]).re;
+  c0 *= (1.0 / 3.0);
+  C<double> f0, f1, f2;
+  if (c1 < 1e-10) {
+    f0 = cmk(1.0, -c0 / 6.0);
+    f1 = cmk(c0 / 24.0, 1.0 - c1 / 6.0);
+    f2 = cmk(-0.5 + c1 / 24.0, 0.0);
+  } else {
+    const bool neg = c0 < 0.0;
+    const double c0a = fabs(c0);
+    const double c0max = 2.0 * c1 / 3.0 * sqrt(c1 / 3.0);
+    double ratio = c0a / c0max;
+    ratio = ratio > 1.0 ? 1.0 : ratio;
+    const double theta = acos(ratio);
+    const double u = sqrt(c1 / 3.0) * cos(theta / 3.0);
+    const double w = sqrt(c1) * sin(theta / 3.0);
+    const double w2 = w * w, u2 = u * u;
+    const double xi0 = fabs(w) < 0.05 ? 1.0 - w2 / 6.0 * (1.0 - w2 / 20.0 * (1.0 - w2 / 42.0)) : sin(w) / w;
+    const double cw = cos(w);
+    const C<double> e2iu = cmk(cos(2.0 * u), sin(2.0 * u));
+    const C<double> emiu = cmk(cos(u), -sin(u));
+    const C<double> h0 = (u2 - w2) * e2iu + emiu * cmk(8.0 * u2 * cw, 2.0 * u * (3.0 * u2 + w2) * xi0);
+    const C<double> h1 = (2.0 * u) * e2iu - emiu * cmk(2.0 * u * cw, -(3.0 * u2 - w2) * xi0);
+    const C<double> h2 = e2iu - emiu * cmk(cw, 3.0 * u * xi0);
+    const double inv = 1.0 / (9.0 * u2 - w2);
+    f0 = inv * h0;
+    f1 = inv * h1;
+    f2 = inv * h2;
+    if (neg) {
+      f0 = conj(f0);
+      f1 = -conj(f1);
+      f2 = conj(f2);
+    }
+  }
+  M3<double> E;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) E.m[k] = f1 * Q.m[k] + f2 * Q2.m[k];
+  E.m[0] += f0;
+  E.m[4] += f0;
+  E.m[8] += f0;
+  return E;
+}
+
+// Row Gram-Schmidt on rows 1 and 2, row 3 = conj(row1 x row2).
+__device__ __forceinline__ M3<double> reunitarize(const M3<double>& a) {
+  C<double> r1[3], r2[3];
+  double n1 = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) n1 += norm2(a.m[j]);
+  n1 = 1.0 / sqrt(n1);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) r1[j] = n1 * a.m[j];
+  C<double> d = czero<double>();
+#pragma unroll
+  for (int j = 0; j < 3; ++j) d += cjmul(r1[j], a.m[3 + j]);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) r2[j] = a.m[3 + j] - d * r1[j];
+  double n2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) n2 += norm2(r2[j]);
+  n2 = 1.0 / sqrt(n2);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) r2[j] = n2 * r2[j];
+  M3<double> o;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    o.m[j] = r1[j];
+    o.m[3 + j] = r2[j];
+  }
+  o.m[6] = conj(r1[1] * r2[2] - r1[2] * r2[1]);
+  o.m[7] = conj(r1[2] * r2[0] - r1[0] * r2[2]);
+  o.m[8] = conj(r1[0] * r2[1] - r1[1] * r2[0]);
+  return o;
+}
+
+// U <- reunit(exp(dt P) U).  Canonical: thread = (s, mu) matrix index t.
+// Packed: thread = (parity*4+mu, cb), cb fastest.
+template <int LAYOUT>
+__global__ __launch_bounds__(256) void k_link_update(Geom g, double2* __restrict__ U, const double2* __restrict__ P,
+                                                     double dt, float2* __restrict__ U32) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= 8 * g.vh) return;
+  size_t base, stride;
+  if (LAYOUT == kCanonical) {
+    base = (size_t)t * 9;
+    stride = 1;
+  } else {
+    const int cb = t % g.vh, pm = t / g.vh;
+    base = (size_t)pm * 9 * g.vh + cb;
+    stride = g.vh;
+  }
+  M3<double> u, x;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    u.m[k] = ld<double>(U + base + k * stride);
+    x.m[k] = dt * ld<double>(P + base + k * stride);
+  }
+  const M3<double> un = reunitarize(mmul(exp_ah(x), u));
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    st<double>(U + base + k * stride, un.m[k]);
+    if (LAYOUT == kPacked && U32) U32[base + k * stride] = make_float2((float)un.m[k].re, (float)un.m[k].im);
+  }
+}
+
+hipError_t launch_link_update(const Geom& g, double2* U, const double2* P, double dt, int layout, float2* U32,
+                              hipStream_t s) {
+  const int nb = (8 * g.vh + 255) / 256;
+  if (layout == kCanonical)
+    hipLaunchKernelGGL((k_link_update<kCanonical>), dim3(nb), dim3(256), 0, s, g, U, P, dt, U32);
+  else
+    hipLaunchKernelGGL((k_link_update<kPacked>), dim3(nb), dim3(256), 0, s, g, U, P, dt, U32);
+  return hipGetLastError();
+}
+
+}  // namespace lgt

@@ -1,0 +1,375 @@
+// Wilson hop H_{p,1-p} on the even/odd lattice, with the epilogues the
+// solver fuses into it.
+//
+//   (H psi)(x) = sum_mu [ (1 - gamma_mu) U~_mu(x) psi(x+mu) + (1 + gamma_mu) U~_mu(x-mu)^dag psi(x-mu) ]
+//   (H^dag: the signs of gamma_mu flip)
+//
+// so that D = 1 - kappa H (the operator of the pseudofermion action, S3.1).
+//
+// Work decomposition (gfx950): a 256-thread block owns 64 consecutive
+// checkerboard sites of one parity; wave w (= direction mu) computes both
+// hops along mu for the 64 sites, using the chiral-basis spin projection
+// (1 + s gamma_mu) psi = (h ; s B_mu^dag h), h = psi_up + s B_mu psi_dn, so
+// only two colour vectors go through each SU(3) multiply.  The four
+// per-direction partial spinors meet in LDS and wave w then owns spin
+// component w of the 64 output sites for the epilogue, so every global load
+// and store is a unit-stride 64-lane access in the [12][vh] SoA layout.
+// Blocks are numbered XCD-contiguously (see xcd_block).
+#include "lgt_internal.h"
+
+namespace lgt {
+
+// h = u + S * B_mu d  for one spinor (comp = 3*spin + colour); S = +-1.
+template <typename R, int MU, int S>
+__device__ __forceinline__ void project(const C<R>* psi, C<R>* h) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const C<R> u0 = psi[i], u1 = psi[3 + i], d0 = psi[6 + i], d1 = psi[9 + i];
+    const R s = R(S);
+    if constexpr (MU == 0) {         // B = -i sigma_1: B d = (-i d1, -i d0)
+      h[i] = u0 - s * itimes(d1);
+      h[3 + i] = u1 - s * itimes(d0);
+    } else if constexpr (MU == 1) {  // B = -i sigma_2: B d = (-d1, d0)
+      h[i] = u0 - s * d1;
+      h[3 + i] = u1 + s * d0;
+    } else if constexpr (MU == 2) {  // B = -i sigma_3: B d = (-i d0, i d1)
+      h[i] = u0 - s * itimes(d0);
+      h[3 + i] = u1 + s * itimes(d1);
+    } else {                         // B = 1
+      h[i] = u0 + s * d0;
+      h[3 + i] = u1 + s * d1;
+    }
+  }
+}
+
+// acc_up += w ; acc_dn += S * B_mu^dag w
+template <typename R, int MU, int S>
+__device__ __forceinline__ void reconstruct(const C<R>* w, C<R>* acc) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const C<R> w0 = w[i], w1 = w[3 + i];
+    const R s = R(S);
+    acc[i] += w0;
+    acc[3 + i] += w1;
+    if constexpr (MU == 0) {         // B^dag = i sigma_1: (i w1, i w0)
+      acc[6 + i] += s * itimes(w1);
+      acc[9 + i] += s * itimes(w0);
+    } else if constexpr (MU == 1) {  // B^dag = i sigma_2: (w1, -w0)
+      acc[6 + i] += s * w1;
+      acc[9 + i] -= s * w0;
+    } else if constexpr (MU == 2) {  // B^dag = i sigma_3: (i w0, -i w1)
+      acc[6 + i] += s * itimes(w0);
+      acc[9 + i] -= s * itimes(w1);
+    } else {
+      acc[6 + i] += s * w0;
+      acc[9 + i] += s * w1;
+    }
+  }
+}
+
+// Both hops along MU for output site (p, cb) with coordinates c.
+template <typename R, int MU, bool DAG>
+__device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__ gauge,
+                                        const R2<R>* __restrict__ in, int p, int cb, const int c[4],
+                                        C<R>* acc) {
+  constexpr int SF = DAG ? +1 : -1;  // forward projector 1 + SF gamma
+  constexpr int SB = -SF;
+  const int vh = g.vh;
+  C<R> psi[12], h[6], w[6];
+  {  // forward: (1 + SF gamma) U_mu(x) psi(x + mu)
+    const int nf = cb_shift(g, c, MU, +1);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = ld<R>(in + (size_t)k * vh + nf);
+    project<R, MU, SF>(psi, h);
+    const M3<R> U = load_m3<R>(gptr<R>(gauge, g, p, MU), vh, cb);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        C<R> s = U.m[3 * i] * h[3 * a];
+        s += U.m[3 * i + 1] * h[3 * a + 1];
+        s += U.m[3 * i + 2] * h[3 * a + 2];
+        w[3 * a + i] = s;
+      }
+    if (MU == 3 && c[3] == g.L[3] - 1) {
+      const R b = R(g.bc);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) w[k] = b * w[k];
+    }
+    reconstruct<R, MU, SF>(w, acc);
+  }
+  {  // backward: (1 + SB gamma) U_mu(x - mu)^dag psi(x - mu)
+    const int nb = cb_shift(g, c, MU, -1);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = ld<R>(in + (size_t)k * vh + nb);
+    project<R, MU, SB>(psi, h);
+    const M3<R> U = load_m3<R>(gptr<R>(gauge, g, 1 - p, MU), vh, nb);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        C<R> s = cjmul(U.m[i], h[3 * a]);
+        s += cjmul(U.m[3 + i], h[3 * a + 1]);
+        s += cjmul(U.m[6 + i], h[3 * a + 2]);
+        w[3 * a + i] = s;
+      }
+    if (MU == 3 && c[3] == 0) {
+      const R b = R(g.bc);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) w[k] = b * w[k];
+    }
+    reconstruct<R, MU, SB>(w, acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Epilogues.  apply() gets the 3 colour components of spin `spin` of the hop
+// result at (p, cb); red accumulates this thread's reduction contribution.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct EpiAxpy {  // out = self + coef * acc
+  static constexpr bool kReduce = false;
+  R2<R>* out[2];
+  const R2<R>* self[2];
+  R coef;
+  int vh;
+  const SolverState* guard;  // if set, the launch is a no-op once the solve has finished
+  __device__ bool skip() const { return guard && guard->done != kDoneRunning; }
+  __device__ void apply(int p, int cb, int spin, const C<R>* acc, double&) const {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const size_t o = (size_t)(3 * spin + i) * vh + cb;
+      C<R> v = coef * acc[i];
+      if (self[p]) v += ld<R>(self[p] + o);
+      st<R>(out[p] + o, v);
+    }
+  }
+  __device__ void finalize(const double*) const {}
+};
+
+template <typename R>
+struct EpiSchurNorm {  // w = x + coef * acc (odd sites), reduce |w|^2 -> pap, alpha
+  static constexpr bool kReduce = true;
+  R2<R>* w;
+  const R2<R>* x;
+  R coef;
+  int vh;
+  SolverState* state;
+  __device__ bool skip() const { return state->done != kDoneRunning; }
+  __device__ void apply(int, int cb, int spin, const C<R>* acc, double& red) const {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const size_t o = (size_t)(3 * spin + i) * vh + cb;
+      C<R> v = ld<R>(x + o) + coef * acc[i];
+      st<R>(w + o, v);
+      red += (double)norm2(v);
+    }
+  }
+  __device__ void finalize(const double* tot) const {
+    const double pap = tot[0];
+    state->pap = pap;
+    if (!(pap > 0.0) || !isfinite(pap)) {
+      state->alpha = 0.0;
+      state->done = kDoneBreakdown;
+    } else {
+      state->alpha = state->rr / pap;
+    }
+  }
+};
+
+template <typename R>
+struct EpiSchurCG {  // q = w + coef * acc; x += alpha p; r -= alpha q; reduce |r|^2
+  static constexpr bool kReduce = true;
+  const R2<R>* w;
+  R2<R>* x;
+  R2<R>* r;
+  const R2<R>* p;
+  R coef;
+  int vh;
+  SolverState* state;
+  __device__ bool skip() const { return state->done != kDoneRunning; }
+  __device__ void apply(int, int cb, int spin, const C<R>* acc, double& red) const {
+    const R alpha = R(state->alpha);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const size_t o = (size_t)(3 * spin + i) * vh + cb;
+      const C<R> q = ld<R>(w + o) + coef * acc[i];
+      const C<R> pv = ld<R>(p + o);
+      C<R> xv = ld<R>(x + o) + alpha * pv;
+      C<R> rv = ld<R>(r + o) - alpha * q;
+      st<R>(x + o, xv);
+      st<R>(r + o, rv);
+      red += (double)norm2(rv);
+    }
+  }
+  __device__ void finalize(const double* tot) const {
+    const double rr = tot[0];
+    state->beta = rr / state->rr;
+    state->rr = rr;
+    state->iter += 1;
+    if (rr > state->rr_max) state->rr_max = rr;
+    if (!isfinite(rr)) state->done = kDoneBreakdown;
+    else if (rr <= state->rr_stop) state->done = kDoneConverged;
+    else if (state->iter >= state->max_iter) state->done = kDoneMaxIter;
+  }
+};
+
+struct EpiResidual {  // r = phi - (self + coef * acc) over both parities, reduce |r|^2
+  static constexpr bool kReduce = true;
+  const double2* self[2];
+  const double2* phi[2];
+  double2* r[2];
+  double coef;
+  int vh;
+  double* result;
+  __device__ bool skip() const { return false; }
+  __device__ void apply(int p, int cb, int spin, const C<double>* acc, double& red) const {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const size_t o = (size_t)(3 * spin + i) * vh + cb;
+      C<double> v = ld<double>(phi[p] + o) - (ld<double>(self[p] + o) + coef * acc[i]);
+      st<double>(r[p] + o, v);
+      red += norm2(v);
+    }
+  }
+  __device__ void finalize(const double* tot) const { result[0] = tot[0]; }
+};
+
+// ---------------------------------------------------------------------------
+// The hop kernel.  Grid: nbp blocks per parity (p_fixed >= 0) or 2*nbp
+// (p_fixed < 0, parity = logical block / nbp).
+// ---------------------------------------------------------------------------
+template <typename R, bool DAG, typename Epi>
+__global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, HopIn<R> hin, Epi epi,
+                                             double* partials, unsigned* ticket) {
+  if (epi.skip()) return;
+  __shared__ R2<R> lds[4][12][64];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int p = p_fixed >= 0 ? p_fixed : lb / nbp;
+  const int blk = p_fixed >= 0 ? lb : lb % nbp;
+  const int lane = threadIdx.x & 63;
+  const int mu = threadIdx.x >> 6;
+  const int cb = blk * 64 + lane;
+  const bool active = cb < g.vh;
+
+  C<R> acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = czero<R>();
+  if (active) {
+    int c[4];
+    cb_coords(g, p, cb, c);
+    const R2<R>* in = p ? hin.in_even : hin.in_odd;
+    switch (mu) {
+      case 0: hop_dir<R, 0, DAG>(g, hin.gauge, in, p, cb, c, acc); break;
+      case 1: hop_dir<R, 1, DAG>(g, hin.gauge, in, p, cb, c, acc); break;
+      case 2: hop_dir<R, 2, DAG>(g, hin.gauge, in, p, cb, c, acc); break;
+      default: hop_dir<R, 3, DAG>(g, hin.gauge, in, p, cb, c, acc); break;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    R2<R> v;
+    v.x = acc[k].re;
+    v.y = acc[k].im;
+    lds[mu][k][lane] = v;
+  }
+  __syncthreads();
+  // wave `mu` now owns spin component `mu` of the 64 sites
+  const int spin = mu;
+  C<R> out[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int k = 3 * spin + i;
+    R2<R> a = lds[0][k][lane], b = lds[1][k][lane], cc = lds[2][k][lane], d = lds[3][k][lane];
+    out[i] = cmk<R>(((a.x + b.x) + cc.x) + d.x, ((a.y + b.y) + cc.y) + d.y);
+  }
+  double red = 0.0;
+  if (active) epi.apply(p, cb, spin, out, red);
+  if constexpr (Epi::kReduce) {
+    double v[1] = {red}, tot[1];
+    if (grid_sum<256, 1>(v, partials, ticket, lb, gridDim.x, tot) && threadIdx.x == 0)
+      epi.finalize(tot);
+  }
+}
+
+static inline int nblk_parity(const Geom& g) { return (g.vh + 63) / 64; }
+
+template <typename R, bool DAG, typename Epi>
+static hipError_t launch(const Geom& g, int p_out, const HopIn<R>& hin, const Epi& epi, double* partials,
+                         unsigned* ticket, hipStream_t s, int capacity = 0) {
+  const int nbp = nblk_parity(g);
+  const int nb = p_out >= 0 ? nbp : 2 * nbp;
+  if (Epi::kReduce && nb > capacity) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_hop<R, DAG, Epi>), dim3(nb), dim3(256), 0, s, g, nbp, p_out, hin, epi, partials,
+                     ticket);
+  return hipGetLastError();
+}
+
+template <typename R, bool DAG>
+hipError_t launch_hop_axpy(const Geom& g, int p_out, HopIn<R> hin, R2<R>* out_even, R2<R>* out_odd,
+                           const R2<R>* self_even, const R2<R>* self_odd, double coef, hipStream_t s,
+                           const SolverState* guard) {
+  EpiAxpy<R> e;
+  e.guard = guard;
+  e.out[0] = out_even;
+  e.out[1] = out_odd;
+  e.self[0] = self_even;
+  e.self[1] = self_odd;
+  e.coef = R(coef);
+  e.vh = g.vh;
+  return launch<R, DAG>(g, p_out, hin, e, nullptr, nullptr, s);
+}
+
+template <typename R, bool DAG>
+hipError_t launch_hop_schur_norm(const Geom& g, HopIn<R> hin, R2<R>* w, const R2<R>* x, double coef,
+                                 SolverState* st, Reduce red, hipStream_t s) {
+  EpiSchurNorm<R> e{w, x, R(coef), g.vh, st};
+  return launch<R, DAG>(g, 1, hin, e, red.partials, red.ticket, s, red.capacity);
+}
+
+template <typename R, bool DAG>
+hipError_t launch_hop_schur_cg(const Geom& g, HopIn<R> hin, const R2<R>* w, R2<R>* x, R2<R>* r,
+                               const R2<R>* p, double coef, SolverState* st, Reduce red,
+                               hipStream_t s) {
+  EpiSchurCG<R> e{w, x, r, p, R(coef), g.vh, st};
+  return launch<R, DAG>(g, 1, hin, e, red.partials, red.ticket, s, red.capacity);
+}
+
+template <bool DAG>
+hipError_t launch_hop_residual(const Geom& g, HopIn<double> hin, const double2* self_full,
+                               const double2* phi_full, double2* r_full, double coef, Reduce red,
+                               int slot, hipStream_t s) {
+  const size_t half = (size_t)12 * g.vh;
+  EpiResidual e;
+  e.self[0] = self_full;
+  e.self[1] = self_full + half;
+  e.phi[0] = phi_full;
+  e.phi[1] = phi_full + half;
+  e.r[0] = r_full;
+  e.r[1] = r_full + half;
+  e.coef = coef;
+  e.vh = g.vh;
+  e.result = red.result + slot;
+  return launch<double, DAG>(g, -1, hin, e, red.partials, red.ticket, s, red.capacity);
+}
+
+#define LGT_INST_HOP(R, DAG)                                                                          \
+  template hipError_t launch_hop_axpy<R, DAG>(const Geom&, int, HopIn<R>, R2<R>*, R2<R>*, const R2<R>*, \
+                                               const R2<R>*, double, hipStream_t, const SolverState*); \
+  template hipError_t launch_hop_schur_norm<R, DAG>(const Geom&, HopIn<R>, R2<R>*, const R2<R>*,      \
+                                                     double, SolverState*, Reduce, hipStream_t);     \
+  template hipError_t launch_hop_schur_cg<R, DAG>(const Geom&, HopIn<R>, const R2<R>*, R2<R>*,        \
+                                                   R2<R>*, const R2<R>*, double, SolverState*, Reduce, \
+                                                   hipStream_t);
+
+LGT_INST_HOP(double, false)
+LGT_INST_HOP(double, true)
+LGT_INST_HOP(float, false)
+LGT_INST_HOP(float, true)
+
+template hipError_t launch_hop_residual<false>(const Geom&, HopIn<double>, const double2*, const double2*,
+                                               double2*, double, Reduce, int, hipStream_t);
+template hipError_t launch_hop_residual<true>(const Geom&, HopIn<double>, const double2*, const double2*,
+                                              double2*, double, Reduce, int, hipStream_t);
+
+}  // namespace lgt

@@ -1,0 +1,100 @@
+// Host-side context: geometry, stream, device workspace, and the solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/lgt.h"
+#include "lgt_internal.h"
+
+namespace lgt {
+
+// Error carrying an ABI status across the C++ layers (never across the ABI).
+struct Error : std::runtime_error {
+  lgt_status status;
+  Error(lgt_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define LGT_HIP(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw ::lgt::Error(e_ == hipErrorOutOfMemory ? LGT_ERR_OUT_OF_MEMORY : LGT_ERR_DEVICE, \
+                         std::string(#call) + ": " + hipGetErrorString(e_));                \
+  } while (0)
+
+struct SolveStats {
+  int iters = 0;
+  int reliable = 0;
+  double true_res = 0.0;
+  bool converged = true;
+};
+
+struct SolverOpts {
+  int precision = LGT_FP64;
+  double tol = 1e-10;
+  int max_iter = 20000;
+  double delta = 0.1;
+};
+
+}  // namespace lgt
+
+struct lgt_ctx {
+  lgt::Geom g{};
+  int64_t V = 0;
+  int vh = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+
+  // packed links: FP64 [2][4][9][vh], FP32 copy (mixed precision)
+  double2* U64 = nullptr;
+  float2* U32 = nullptr;
+  // packed momenta for the MD driver
+  double2* P64 = nullptr;
+
+  // spinor workspace: FP64 full fields (24*vh complex each) and FP32 half fields
+  std::vector<double2*> full64;
+  std::vector<float2*> half32;
+
+  // reductions / solver state
+  lgt::SolverState* state = nullptr;
+  double* partials = nullptr;
+  unsigned* ticket = nullptr;
+  double* result = nullptr;      // device results
+  double* host_result = nullptr; // pinned mirror
+  int* flags = nullptr;          // device: [0] non-finite input
+  int* host_flags = nullptr;     // pinned
+  lgt::SolverState* host_state = nullptr;  // pinned
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  size_t half_elems() const { return (size_t)12 * vh; }
+  size_t full_elems() const { return (size_t)24 * vh; }
+  lgt::Reduce red() const { return lgt::Reduce{partials, ticket, result, lgt::reduce_capacity(vh)}; }
+
+  double2* f64(int i);   // full FP64 spinor scratch i (allocated on demand)
+  float2* h32(int i);    // half FP32 spinor scratch i
+  void ensure_u32();
+  void ensure_p64();
+
+  // solver (solver.hip)
+  lgt::SolveStats solve_ddagd(const double2* phi, double2* X, double2* Y, const lgt::SolverOpts& o);
+  void dslash_full(const double2* in, double2* out, double kappa, bool dag);
+  double action_fermion(const double2* phi, const double2* X, const double2* Y);
+  void sync();
+  void read_results(int n);
+
+  double kappa = 0.0;  // hopping parameter of the current solve
+ private:
+  void solve_M(bool dag, double2* z, const double2* b, double tol, int max_iter, bool mixed,
+               double delta, lgt::SolveStats& st);
+  int cg_normal64(bool dag, double2* z, const double2* rhs, double tol, int max_iter,
+                  lgt::SolveStats& st);
+  int cg_normal_mixed(bool dag, double2* z, const double2* rhs, double tol, int max_iter, double delta,
+                      lgt::SolveStats& st);
+  void apply_mhat_dag_mhat64(bool dag, const double2* x, double2* out);
+};

@@ -1,0 +1,287 @@
+// Device-side building blocks for the gfx950 kernels: complex arithmetic,
+// SU(3) algebra, lattice geometry in the even/odd (checkerboard) layout,
+// XCD-aware block numbering and the deterministic two-level reduction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lgt {
+
+// ---------------------------------------------------------------------------
+// Complex numbers.  Storage type R2 (double2 / float2) is what lives in HBM;
+// arithmetic type C<R> is a plain struct the compiler keeps in VGPRs.
+// ---------------------------------------------------------------------------
+template <typename R> struct R2of;
+template <> struct R2of<double> { using type = double2; };
+template <> struct R2of<float> { using type = float2; };
+template <typename R> using R2 = typename R2of<R>::type;
+
+template <typename R> struct C { R re, im; };
+
+template <typename R> __device__ __forceinline__ C<R> cmk(R a, R b) { return C<R>{a, b}; }
+template <typename R> __device__ __forceinline__ C<R> czero() { return C<R>{R(0), R(0)}; }
+template <typename R> __device__ __forceinline__ C<R> operator+(C<R> a, C<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> __device__ __forceinline__ C<R> operator-(C<R> a, C<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> __device__ __forceinline__ C<R> operator-(C<R> a) { return {-a.re, -a.im}; }
+template <typename R> __device__ __forceinline__ C<R> operator*(C<R> a, C<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ C<R> operator*(R s, C<R> a) { return {s * a.re, s * a.im}; }
+template <typename R> __device__ __forceinline__ C<R>& operator+=(C<R>& a, C<R> b) { a.re += b.re; a.im += b.im; return a; }
+template <typename R> __device__ __forceinline__ C<R>& operator-=(C<R>& a, C<R> b) { a.re -= b.re; a.im -= b.im; return a; }
+template <typename R> __device__ __forceinline__ C<R> conj(C<R> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <typename R> __device__ __forceinline__ C<R> cjmul(C<R> a, C<R> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// a * conj(b)
+template <typename R> __device__ __forceinline__ C<R> mulcj(C<R> a, C<R> b) {
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename R> __device__ __forceinline__ C<R> itimes(C<R> a) { return {-a.im, a.re}; }
+template <typename R> __device__ __forceinline__ R norm2(C<R> a) { return a.re * a.re + a.im * a.im; }
+
+template <typename R> __device__ __forceinline__ C<R> ld(const R2<R>* p) {
+  R2<R> v = *p;
+  return {v.x, v.y};
+}
+template <typename R> __device__ __forceinline__ void st(R2<R>* p, C<R> a) {
+  R2<R> v;
+  v.x = a.re;
+  v.y = a.im;
+  *p = v;
+}
+// Non-temporal store: output streams that are not re-read by this kernel.
+template <typename R> __device__ __forceinline__ void st_nt(R2<R>* p, C<R> a) {
+  R2<R> v;
+  v.x = a.re;
+  v.y = a.im;
+  __builtin_nontemporal_store(v, p);
+}
+
+template <typename R, typename S> __device__ __forceinline__ C<R> cvt(C<S> a) {
+  return {R(a.re), R(a.im)};
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 complex matrices (row-major, m[3*i + j]).
+// ---------------------------------------------------------------------------
+template <typename R> struct M3 { C<R> m[9]; };
+
+template <typename R> __device__ __forceinline__ M3<R> mmul(const M3<R>& a, const M3<R>& b) {
+  M3<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      C<R> s = a.m[3 * i] * b.m[j];
+      s += a.m[3 * i + 1] * b.m[3 + j];
+      s += a.m[3 * i + 2] * b.m[6 + j];
+      c.m[3 * i + j] = s;
+    }
+  return c;
+}
+// a * b^dag
+template <typename R> __device__ __forceinline__ M3<R> mmul_nd(const M3<R>& a, const M3<R>& b) {
+  M3<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      C<R> s = mulcj(a.m[3 * i], b.m[3 * j]);
+      s += mulcj(a.m[3 * i + 1], b.m[3 * j + 1]);
+      s += mulcj(a.m[3 * i + 2], b.m[3 * j + 2]);
+      c.m[3 * i + j] = s;
+    }
+  return c;
+}
+// a^dag * b
+template <typename R> __device__ __forceinline__ M3<R> mmul_dn(const M3<R>& a, const M3<R>& b) {
+  M3<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      C<R> s = cjmul(a.m[i], b.m[j]);
+      s += cjmul(a.m[3 + i], b.m[3 + j]);
+      s += cjmul(a.m[6 + i], b.m[6 + j]);
+      c.m[3 * i + j] = s;
+    }
+  return c;
+}
+template <typename R> __device__ __forceinline__ M3<R> madd(const M3<R>& a, const M3<R>& b) {
+  M3<R> c;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) c.m[k] = a.m[k] + b.m[k];
+  return c;
+}
+template <typename R> __device__ __forceinline__ M3<R> mscale(R s, const M3<R>& a) {
+  M3<R> c;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) c.m[k] = s * a.m[k];
+  return c;
+}
+template <typename R> __device__ __forceinline__ M3<R> mdag(const M3<R>& a) {
+  M3<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c.m[3 * i + j] = conj(a.m[3 * j + i]);
+  return c;
+}
+template <typename R> __device__ __forceinline__ M3<R> mident() {
+  M3<R> c;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) c.m[k] = czero<R>();
+  c.m[0].re = c.m[4].re = c.m[8].re = R(1);
+  return c;
+}
+template <typename R> __device__ __forceinline__ C<R> mtrace(const M3<R>& a) {
+  return a.m[0] + a.m[4] + a.m[8];
+}
+// Traceless anti-Hermitian part: (A - A^dag)/2 - tr(A - A^dag)/6.
+template <typename R> __device__ __forceinline__ M3<R> proj_ta(const M3<R>& a) {
+  M3<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      C<R> x = a.m[3 * i + j], y = a.m[3 * j + i];
+      c.m[3 * i + j] = cmk<R>(R(0.5) * (x.re - y.re), R(0.5) * (x.im + y.im));
+    }
+  // tr(A - A^dag) = 2i Im tr A; subtract (2i Im tr A)/6 from the diagonal
+  R imtr = (a.m[0].im + a.m[4].im + a.m[8].im) * (R(1) / R(3));
+  c.m[0].im -= imtr;
+  c.m[4].im -= imtr;
+  c.m[8].im -= imtr;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// Lattice geometry.  Even/odd (checkerboard) index of lexicographic site
+// s = x + Lx*(y + Ly*(z + Lz*t)) with parity (x+y+z+t)&1 is cb = s/2
+// (Lx even), unique within a parity.
+// ---------------------------------------------------------------------------
+struct Geom {
+  int L[4];   // Lx, Ly, Lz, Lt
+  int hx;     // Lx / 2
+  int vh;     // V / 2 (sites per parity)
+  int bc;     // fermion temporal boundary sign
+};
+
+__device__ __forceinline__ void cb_coords(const Geom& g, int p, int cb, int c[4]) {
+  int xh = cb % g.hx;
+  int r = cb / g.hx;
+  c[1] = r % g.L[1];
+  r /= g.L[1];
+  c[2] = r % g.L[2];
+  c[3] = r / g.L[2];
+  c[0] = 2 * xh + ((p + c[1] + c[2] + c[3]) & 1);
+}
+__device__ __forceinline__ void lex_coords(const Geom& g, int s, int c[4]) {
+  c[0] = s % g.L[0];
+  int r = s / g.L[0];
+  c[1] = r % g.L[1];
+  r /= g.L[1];
+  c[2] = r % g.L[2];
+  c[3] = r / g.L[2];
+}
+__device__ __forceinline__ int cb_of(const Geom& g, const int c[4]) {
+  return (c[0] >> 1) + g.hx * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+}
+__device__ __forceinline__ int parity_of(const int c[4]) { return (c[0] + c[1] + c[2] + c[3]) & 1; }
+// cb index of the site c + d*mu_hat (d = +-1), periodic.
+__device__ __forceinline__ int cb_shift(const Geom& g, const int c[4], int mu, int d) {
+  int n[4] = {c[0], c[1], c[2], c[3]};
+  int v = n[mu] + d;
+  n[mu] = v < 0 ? v + g.L[mu] : (v >= g.L[mu] ? v - g.L[mu] : v);
+  return cb_of(g, n);
+}
+__device__ __forceinline__ void shifted(const Geom& g, const int c[4], int mu, int d, int n[4]) {
+  n[0] = c[0]; n[1] = c[1]; n[2] = c[2]; n[3] = c[3];
+  int v = n[mu] + d;
+  n[mu] = v < 0 ? v + g.L[mu] : (v >= g.L[mu] ? v - g.L[mu] : v);
+}
+
+// Packed gauge-type field: [parity][mu][9][vh] complex, element (i,j) at k = 3i+j.
+template <typename R> __device__ __forceinline__ const R2<R>* gptr(const R2<R>* f, const Geom& g, int p, int mu) {
+  return f + (size_t)((p * 4 + mu) * 9) * g.vh;
+}
+template <typename R> __device__ __forceinline__ M3<R> load_m3(const R2<R>* f, int vh, int cb) {
+  M3<R> u;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) u.m[k] = ld<R>(f + (size_t)k * vh + cb);
+  return u;
+}
+template <typename R> __device__ __forceinline__ void store_m3(R2<R>* f, int vh, int cb, const M3<R>& u) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) st<R>(f + (size_t)k * vh + cb, u.m[k]);
+}
+
+// ---------------------------------------------------------------------------
+// Block numbering.  Workgroups are handed to the 8 XCDs round-robin by
+// workgroup id; remapping so that XCD k processes one contiguous range of
+// blocks keeps each stencil's neighbours in that XCD's L2.
+// ---------------------------------------------------------------------------
+constexpr int kXcd = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  int q = nb / kXcd, r = nb % kXcd;
+  int x = b % kXcd, slot = b / kXcd;
+  return x < r ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reduction: wave shuffles, LDS across the block's waves, one
+// partial per block, and the last block to arrive (integer ticket) sums the
+// partials in a fixed order.  No floating-point atomics, so every run gives
+// the same bits.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) t += sh[i];
+  }
+  return t;  // valid in thread 0
+}
+
+// Reduce NV values per thread.  Block partials go to partials[blk*NV + k];
+// returns true in the whole last block, whose thread 0 then holds the totals
+// in out[k].
+template <int NT, int NV>
+__device__ __forceinline__ bool grid_sum(const double (&v)[NV], double* partials, unsigned* ticket,
+                                         int blk, int nblk, double (&out)[NV]) {
+  __shared__ double sh[NT / 64];
+  __shared__ bool last;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double t = block_sum<NT>(v[k], sh);
+    if (threadIdx.x == 0)
+      __hip_atomic_store(partials + (size_t)blk * NV + k, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (threadIdx.x == 0) {
+    unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (prev == (unsigned)(nblk - 1));
+  }
+  __syncthreads();
+  if (!last) return false;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += NT)
+      s += __hip_atomic_load(partials + (size_t)i * NV + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    out[k] = block_sum<NT>(s, sh);
+  }
+  if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
+}  // namespace lgt

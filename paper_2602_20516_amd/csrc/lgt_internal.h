@@ -1,0 +1,130 @@
+// Internal (non-ABI) interface between the C ABI layer, the solver driver
+// and the kernel launchers.  Host and device code both include it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "lgt_device.h"
+
+namespace lgt {
+
+// Device-resident state of one CG solve.  Scalars are produced by the last
+// block of the reduction kernels and consumed by the next kernels, so the
+// host never has to read them inside the iteration.
+struct SolverState {
+  double rr;        // |r|^2 of the current iterate
+  double pap;       // |M p|^2 = p^dag A p
+  double alpha;
+  double beta;
+  double rr_stop;   // stop when rr <= rr_stop
+  double rr0;       // |b|^2
+  double rr_max;    // mixed precision: largest |r|^2 since the last FP64 update
+  double pad0;
+  int iter;
+  int max_iter;
+  int done;         // 0 running, 1 converged, 2 iteration cap, 3 breakdown / non-finite
+  int pad1;
+};
+
+enum { kDoneRunning = 0, kDoneConverged = 1, kDoneMaxIter = 2, kDoneBreakdown = 3 };
+
+// Output layout of the gauge-type kernels (forces, link update).
+enum Layout { kCanonical = 0, kPacked = 1 };
+
+// Arguments of a hop launch.  Half-fields are [12][vh] complex; a "full"
+// spinor is even half followed by odd half.
+template <typename R>
+struct HopIn {
+  const R2<R>* gauge;  // packed links [2][4][9][vh]
+  const R2<R>* in_even;
+  const R2<R>* in_odd;
+};
+
+// Workspace scalars used by reductions.
+struct Reduce {
+  double* partials;   // capacity * 4 doubles
+  unsigned* ticket;   // one counter, reset by the last block
+  double* result;     // small array of results read by the host
+  int capacity;       // largest grid a reduction kernel may use
+};
+
+// Reduction capacity needed for a lattice with vh sites per parity: the
+// largest reducing grid is the both-parity hop (2 * ceil(vh/64) blocks).
+inline int reduce_capacity(int vh) {
+  const int nb = 2 * ((vh + 63) / 64);
+  return nb < 1024 ? 1024 : nb;
+}
+
+// ---- launchers (kernels_*.hip) --------------------------------------------
+// All launchers enqueue on `s` and return hipError_t of the launch.
+
+// pack: canonical complex128 [V][nc] -> packed [2][nc][vh] (FP64 and, if
+// out32 != nullptr, FP32).  nonfinite: integer flag set to 1 if any input is NaN/Inf.
+hipError_t launch_pack(const Geom& g, int nc, const double2* canon, double2* out64, float2* out32,
+                       int* nonfinite, hipStream_t s);
+hipError_t launch_unpack(const Geom& g, int nc, const double2* packed, double2* canon, hipStream_t s);
+
+// Hop variants (kernels_hop.hip).  p_out in {0,1}: one parity; -1: both.
+// out = self + coef * H in   (self may be null)
+template <typename R, bool DAG>
+hipError_t launch_hop_axpy(const Geom& g, int p_out, HopIn<R> hin, R2<R>* out_even, R2<R>* out_odd,
+                           const R2<R>* self_even, const R2<R>* self_odd, double coef, hipStream_t s,
+                           const SolverState* guard = nullptr);
+// Schur step of CG: w = x + coef * H in on parity 1, pap = |w|^2, alpha = rr / pap
+template <typename R, bool DAG>
+hipError_t launch_hop_schur_norm(const Geom& g, HopIn<R> hin, R2<R>* w, const R2<R>* x, double coef,
+                                 SolverState* st, Reduce red, hipStream_t s);
+// Schur dagger step fused with the CG update:
+// q = w + coef * H in;  x += alpha p;  r -= alpha q;  rr = |r|^2; beta, convergence
+template <typename R, bool DAG>
+hipError_t launch_hop_schur_cg(const Geom& g, HopIn<R> hin, const R2<R>* w, R2<R>* x, R2<R>* r,
+                               const R2<R>* p, double coef, SolverState* st, Reduce red,
+                               hipStream_t s);
+// Residual of the full operator: r = phi - (self + coef * H in) over both parities,
+// result[slot] = |r|^2
+template <bool DAG>
+hipError_t launch_hop_residual(const Geom& g, HopIn<double> hin, const double2* self_full,
+                               const double2* phi_full, double2* r_full, double coef, Reduce red,
+                               int slot, hipStream_t s);
+
+// Vector kernels (kernels_field.hip).  n = number of complex elements.
+template <typename R>
+hipError_t launch_cg_init(int n, const R2<R>* b, R2<R>* r, R2<R>* p, R2<R>* x, SolverState* st,
+                          Reduce red, double tol, int max_iter, hipStream_t s);
+template <typename R>
+hipError_t launch_cg_xpay(int n, const R2<R>* r, R2<R>* p, SolverState* st, hipStream_t s);
+// result[slot] = |a|^2 (and result[slot+1] = Re <a,b> if b != null)
+hipError_t launch_norm_dot(int n, const double2* a, const double2* b, Reduce red, int slot,
+                           hipStream_t s);
+hipError_t launch_axpy64(int n, double a, const double2* x, double2* y, hipStream_t s);  // y += a x
+hipError_t launch_copy64(int n, const double2* x, double2* y, hipStream_t s);
+hipError_t launch_xmy64(int n, const double2* x, double2* y, hipStream_t s);             // y = x - y
+hipError_t launch_zero64(int n, double2* y, hipStream_t s);
+hipError_t launch_convert_64_32(int n, const double2* x, float2* y, hipStream_t s);
+// mixed precision helpers
+hipError_t launch_mixed_update(int n, float2* xs, double2* x, hipStream_t s);  // x += xs; xs = 0
+template <typename R>
+hipError_t launch_cg_reliable(int n, const double2* r64, R2<R>* r, SolverState* st, Reduce red,
+                              hipStream_t s);
+
+// Forces / gauge kernels (kernels_force.hip).  Gauge-type outputs: layout
+// kCanonical -> [V][4][3][3] complex128, kPacked -> [2][4][9][vh].
+// mode: 0 force, 1 grad, 2 momentum (P -= dt F).
+hipError_t launch_bilinear_force(const Geom& g, const double2* U, const double2* a_full,
+                                 const double2* b_full, double kappa, double coeff, int mode, double dt,
+                                 void* out, int layout, hipStream_t s);
+hipError_t launch_gauge_force(const Geom& g, const double2* U, double beta, int mode, double dt,
+                              void* out, int layout, hipStream_t s);
+// result[slot] = sum_x sum_{mu<nu} Re tr P_mu,nu(x)
+hipError_t launch_plaquette(const Geom& g, const double2* U, Reduce red, int slot, hipStream_t s);
+// result[slot] = -sum Re tr P^2 over a gauge-type field of either layout
+hipError_t launch_kinetic(const Geom& g, const double2* P, int layout, Reduce red, int slot,
+                          hipStream_t s);
+// U <- reunit(exp(dt P) U), both in `layout`; U32 (packed FP32 copy) refreshed if non-null
+hipError_t launch_link_update(const Geom& g, double2* U, const double2* P, double dt, int layout,
+                              float2* U32, hipStream_t s);
+
+}  // namespace lgt

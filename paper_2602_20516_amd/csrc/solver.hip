@@ -1,0 +1,297 @@
+// Solver driver: A X = phi with A = D^dag D (eq. S3.5), X = chi, Y = D X.
+//
+// Method (the paper only says "e.g. via conjugate gradient"; the solve is
+// not differentiated): two even/odd Schur-complement solves,
+//     D^dag Y = phi,   D X = Y,
+// each written as M z = b with M = D or D^dag = 1 - kappa H^(dag):
+//     b'_o = b_o + kappa H_oe b_e,     Mhat = 1 - kappa^2 H_oe H_eo  (odd sites),
+//     CG on Mhat^dag Mhat z_o = Mhat^dag b'_o   (zero initial guess),
+//     z_e = b_e + kappa H_eo z_o,
+// then Y is recomputed as D X and the FP64 residual phi - D^dag D X checked;
+// FP64 defect-correction passes follow until it meets the tolerance.
+//
+// The CG iteration is five stream-ordered kernels whose scalars (alpha,
+// beta, |r|^2, the convergence flag) stay on the device; the host only
+// reads the state at chunk boundaries and predicts the next chunk length
+// from the observed convergence rate.  Once converged, the remaining
+// launches of a chunk return immediately.
+//
+// Mixed precision: the same CG in FP32 (FP32 links and vectors) with
+// reliable updates: whenever the FP32 residual has dropped by reliable_delta
+// since the last update (checked at chunk boundaries), the FP32 solution is
+// folded into the FP64 one and the residual recomputed in FP64.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "lgt_ctx.h"
+
+using namespace lgt;
+
+double2* lgt_ctx::f64(int i) {
+  if ((int)full64.size() <= i) full64.resize(i + 1, nullptr);
+  if (!full64[i]) {
+    LGT_HIP(hipMalloc(&full64[i], full_elems() * sizeof(double2)));
+    LGT_HIP(hipMemsetAsync(full64[i], 0, full_elems() * sizeof(double2), stream));
+  }
+  return full64[i];
+}
+
+float2* lgt_ctx::h32(int i) {
+  if ((int)half32.size() <= i) half32.resize(i + 1, nullptr);
+  if (!half32[i]) {
+    LGT_HIP(hipMalloc(&half32[i], half_elems() * sizeof(float2)));
+    LGT_HIP(hipMemsetAsync(half32[i], 0, half_elems() * sizeof(float2), stream));
+  }
+  return half32[i];
+}
+
+void lgt_ctx::ensure_u32() {
+  if (!U32) LGT_HIP(hipMalloc(&U32, (size_t)72 * vh * sizeof(float2)));
+}
+
+void lgt_ctx::ensure_p64() {
+  if (!P64) LGT_HIP(hipMalloc(&P64, (size_t)72 * vh * sizeof(double2)));
+}
+
+void lgt_ctx::sync() { LGT_HIP(hipStreamSynchronize(stream)); }
+
+void lgt_ctx::read_results(int n) {
+  LGT_HIP(hipMemcpyAsync(host_result, result, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+  sync();
+}
+
+// scratch full fields
+enum {
+  kPhi = 0, kX = 1, kY = 2, kRes = 3, kE = 4, kYtmp = 5,
+  kW0 = 6, kW1 = 7, kW2 = 8, kW3 = 9, kW4 = 10,
+  kStageA = 11, kStageB = 12
+};
+
+void lgt_ctx::dslash_full(const double2* in, double2* out, double k, bool dag) {
+  const size_t h = half_elems();
+  HopIn<double> hin{U64, in, in + h};
+  if (dag)
+    LGT_HIP((launch_hop_axpy<double, true>(g, -1, hin, out, out + h, in, in + h, -k, stream)));
+  else
+    LGT_HIP((launch_hop_axpy<double, false>(g, -1, hin, out, out + h, in, in + h, -k, stream)));
+}
+
+template <typename R, bool DAG>
+static void hop(const Geom& g, int p_out, const R2<R>* gauge, const R2<R>* in, R2<R>* out, const R2<R>* self,
+                double coef, hipStream_t s, const SolverState* guard = nullptr) {
+  HopIn<R> hin{gauge, in, in};
+  LGT_HIP((launch_hop_axpy<R, DAG>(g, p_out, hin, out, out, self, self, coef, s, guard)));
+}
+
+// out_o = Mhat^dag Mhat x_o in FP64 (4 hops), using kW0 even half as scratch.
+void lgt_ctx::apply_mhat_dag_mhat64(bool dag, const double2* x, double2* out) {
+  const double k2 = -kappa * kappa;
+  double2* t = f64(kW0);            // even half
+  double2* w = f64(kW4) + half_elems();  // odd half (not used by the mixed CG)
+  if (!dag) {
+    hop<double, false>(g, 0, U64, x, t, nullptr, 1.0, stream);
+    hop<double, false>(g, 1, U64, t, w, x, k2, stream);
+    hop<double, true>(g, 0, U64, w, t, nullptr, 1.0, stream);
+    hop<double, true>(g, 1, U64, t, out, w, k2, stream);
+  } else {
+    hop<double, true>(g, 0, U64, x, t, nullptr, 1.0, stream);
+    hop<double, true>(g, 1, U64, t, w, x, k2, stream);
+    hop<double, false>(g, 0, U64, w, t, nullptr, 1.0, stream);
+    hop<double, false>(g, 1, U64, t, out, w, k2, stream);
+  }
+}
+
+// Next chunk length from the convergence history.
+static int next_chunk(int iter, double rr, double rr_stop, int it_prev, double rr_prev) {
+  if (iter <= it_prev || rr_prev <= 0.0 || rr <= 0.0) return 32;
+  const double rate = (std::log(rr) - std::log(rr_prev)) / double(iter - it_prev);
+  if (!(rate < 0.0)) return 32;
+  const double left = (std::log(rr_stop) - std::log(rr)) / rate;
+  int n = (int)std::ceil(left * 1.02) + 1;
+  return std::min(std::max(n, 4), 512);
+}
+
+template <typename R, bool DAG>
+static void cg_iteration(const Geom& g, const R2<R>* gauge, double kappa, R2<R>* t, R2<R>* w, R2<R>* x,
+                         R2<R>* r, R2<R>* p, SolverState* st, Reduce red, hipStream_t s, int n) {
+  const double k2 = -kappa * kappa;
+  HopIn<R> h1{gauge, p, p};
+  LGT_HIP((launch_hop_axpy<R, DAG>(g, 0, h1, t, t, nullptr, nullptr, 1.0, s, st)));
+  HopIn<R> h2{gauge, t, t};
+  LGT_HIP((launch_hop_schur_norm<R, DAG>(g, h2, w, p, k2, st, red, s)));
+  HopIn<R> h3{gauge, w, w};
+  LGT_HIP((launch_hop_axpy<R, !DAG>(g, 0, h3, t, t, nullptr, nullptr, 1.0, s, st)));
+  HopIn<R> h4{gauge, t, t};
+  LGT_HIP((launch_hop_schur_cg<R, !DAG>(g, h4, w, x, r, p, k2, st, red, s)));
+  LGT_HIP((launch_cg_xpay<R>(n, r, p, st, s)));
+}
+
+// CG on Mhat^dag Mhat z = rhs (odd half fields), FP64.  Returns the state's done code.
+int lgt_ctx::cg_normal64(bool dag, double2* z, const double2* rhs, double tol, int max_iter, SolveStats& stt) {
+  const int n = (int)half_elems();
+  double2* t = f64(kW0);
+  double2* r = f64(kW2) + half_elems();
+  double2* p = f64(kW3) + half_elems();
+  double2* w = f64(kW4) + half_elems();
+  LGT_HIP(launch_cg_init<double>(n, rhs, r, p, z, state, red(), tol, max_iter, stream));
+  int it_prev = 0;
+  double rr_prev = 0.0;
+  int chunk = 32;
+  for (;;) {
+    for (int j = 0; j < chunk; ++j) {
+      if (dag) cg_iteration<double, true>(g, U64, kappa, t, w, z, r, p, state, red(), stream, n);
+      else cg_iteration<double, false>(g, U64, kappa, t, w, z, r, p, state, red(), stream, n);
+    }
+    LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
+    sync();
+    const SolverState s = *host_state;
+    if (s.done != kDoneRunning) {
+      stt.iters += s.iter;
+      return s.done;
+    }
+    chunk = next_chunk(s.iter, s.rr, s.rr_stop, it_prev, rr_prev);
+    it_prev = s.iter;
+    rr_prev = s.rr;
+  }
+}
+
+// Mixed-precision CG with reliable updates.  z, rhs: FP64 odd halves.
+int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double tol, int max_iter, double delta,
+                             SolveStats& stt) {
+  const int n = (int)half_elems();
+  ensure_u32();
+  float2* ts = h32(0);
+  float2* ws = h32(1);
+  float2* xs = h32(2);
+  float2* rs = h32(3);
+  float2* ps = h32(4);
+  double2* r64 = f64(kW2) + half_elems();
+  LGT_HIP(launch_zero64(n, z, stream));
+  LGT_HIP(launch_convert_64_32(n, rhs, ts, stream));
+  LGT_HIP(launch_cg_init<float>(n, ts, rs, ps, xs, state, red(), tol, max_iter, stream));
+  // the stopping threshold refers to the FP64 right-hand side
+  LGT_HIP(launch_norm_dot(n, rhs, nullptr, red(), 0, stream));
+  read_results(1);
+  const double bb = host_result[0];
+  {
+    SolverState s;
+    LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
+    sync();
+    s = *host_state;
+    s.rr_stop = tol * tol * bb;
+    if (s.done == kDoneConverged && bb > 0.0) s.done = kDoneRunning;
+    *host_state = s;
+    LGT_HIP(hipMemcpyAsync(state, host_state, sizeof(SolverState), hipMemcpyHostToDevice, stream));
+  }
+  const double d2 = delta * delta;
+  int it_prev = 0;
+  double rr_prev = 0.0;
+  int chunk = 16;
+  for (;;) {
+    for (int j = 0; j < chunk; ++j) {
+      if (dag) cg_iteration<float, true>(g, U32, kappa, ts, ws, xs, rs, ps, state, red(), stream, n);
+      else cg_iteration<float, false>(g, U32, kappa, ts, ws, xs, rs, ps, state, red(), stream, n);
+    }
+    LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
+    sync();
+    SolverState s = *host_state;
+    const bool trigger = s.done != kDoneRunning || s.rr <= d2 * s.rr_max;
+    if (trigger && s.done != kDoneBreakdown) {
+      // fold the FP32 solution into FP64 and recompute the residual in FP64
+      LGT_HIP(launch_mixed_update(n, xs, z, stream));
+      apply_mhat_dag_mhat64(dag, z, r64);             // r64 = A z
+      LGT_HIP(launch_xmy64(n, rhs, r64, stream));     // r64 = rhs - A z
+      LGT_HIP(launch_cg_reliable<float>(n, r64, rs, state, red(), stream));
+      stt.reliable += 1;
+      LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
+      sync();
+      s = *host_state;
+    }
+    if (s.done != kDoneRunning) {
+      stt.iters += s.iter;
+      return s.done;
+    }
+    chunk = next_chunk(s.iter, s.rr, s.rr_stop, it_prev, rr_prev);
+    chunk = std::min(chunk, 64);
+    it_prev = s.iter;
+    rr_prev = s.rr;
+  }
+}
+
+void lgt_ctx::solve_M(bool dag, double2* z, const double2* b, double tol, int max_iter, bool mixed,
+                      double delta, SolveStats& stt) {
+  const size_t h = half_elems();
+  const double2* be = b;
+  const double2* bo = b + h;
+  double2* bp = f64(kW0) + h;    // b'_o
+  double2* te = f64(kW0);        // even scratch
+  double2* rhs = f64(kW1) + h;   // Mhat^dag b'_o
+  const double k = kappa;
+  if (dag) {
+    hop<double, true>(g, 1, U64, be, bp, bo, k, stream);
+    hop<double, false>(g, 0, U64, bp, te, nullptr, 1.0, stream);
+    hop<double, false>(g, 1, U64, te, rhs, bp, -k * k, stream);
+  } else {
+    hop<double, false>(g, 1, U64, be, bp, bo, k, stream);
+    hop<double, true>(g, 0, U64, bp, te, nullptr, 1.0, stream);
+    hop<double, true>(g, 1, U64, te, rhs, bp, -k * k, stream);
+  }
+  double2* zo = z + h;
+  const int code = mixed ? cg_normal_mixed(dag, zo, rhs, tol, max_iter, delta, stt)
+                         : cg_normal64(dag, zo, rhs, tol, max_iter, stt);
+  if (code == kDoneBreakdown) throw Error(LGT_ERR_NONFINITE, "CG breakdown (non-finite or zero curvature)");
+  if (code == kDoneMaxIter) stt.converged = false;
+  if (dag) hop<double, true>(g, 0, U64, zo, z, be, k, stream);
+  else hop<double, false>(g, 0, U64, zo, z, be, k, stream);
+}
+
+SolveStats lgt_ctx::solve_ddagd(const double2* phi, double2* X, double2* Y, const SolverOpts& o) {
+  SolveStats st;
+  const int nf = (int)full_elems();
+  LGT_HIP(launch_norm_dot(nf, phi, nullptr, red(), 0, stream));
+  read_results(1);
+  const double pp = host_result[0];
+  if (!std::isfinite(pp)) throw Error(LGT_ERR_NONFINITE, "phi holds NaN or Inf");
+  if (pp == 0.0) {
+    LGT_HIP(launch_zero64(nf, X, stream));
+    LGT_HIP(launch_zero64(nf, Y, stream));
+    st.true_res = 0.0;
+    return st;
+  }
+  const bool mixed = o.precision != LGT_FP64;
+  // inner tolerance: the two Schur solves and D^dag D compound their
+  // residuals, so each aims a little below the requested true residual
+  const double tol_in = o.tol * 0.25;
+  solve_M(true, Y, phi, tol_in, o.max_iter, mixed, o.delta, st);
+  solve_M(false, X, Y, tol_in, o.max_iter, mixed, o.delta, st);
+  double2* r = f64(kRes);
+  HopIn<double> hin{U64, nullptr, nullptr};
+  const size_t h = half_elems();
+  for (int pass = 0;; ++pass) {
+    dslash_full(X, Y, kappa, false);
+    hin.in_even = Y;
+    hin.in_odd = Y + h;
+    LGT_HIP(launch_hop_residual<true>(g, hin, Y, phi, r, -kappa, red(), 0, stream));
+    read_results(1);
+    st.true_res = std::sqrt(host_result[0] / pp);
+    if (!std::isfinite(st.true_res)) throw Error(LGT_ERR_NONFINITE, "non-finite residual");
+    if (st.true_res <= o.tol || !st.converged || pass >= 4) break;
+    // defect correction: D^dag D e = r, X += e
+    double2* ytmp = f64(kYtmp);
+    double2* e = f64(kE);
+    solve_M(true, ytmp, r, tol_in, o.max_iter, mixed, o.delta, st);
+    solve_M(false, e, ytmp, tol_in, o.max_iter, mixed, o.delta, st);
+    LGT_HIP(launch_axpy64(nf, 1.0, e, X, stream));
+  }
+  if (st.true_res > o.tol) st.converged = false;
+  return st;
+}
+
+double lgt_ctx::action_fermion(const double2* phi, const double2* X, const double2* Y) {
+  const int nf = (int)full_elems();
+  LGT_HIP(launch_norm_dot(nf, X, phi, red(), 0, stream));
+  LGT_HIP(launch_norm_dot(nf, Y, nullptr, red(), 2, stream));
+  read_results(4);
+  return 2.0 * host_result[1] - host_result[2];
+}

@@ -1,0 +1,260 @@
+"""GPU parity: every call of the C ABI against the FP64 oracle on seeded inputs.
+
+Tolerances (relative, global Frobenius norm unless stated):
+* deterministic FP64 maps (D, D^dag, the bilinear adjoint, staple force,
+  plaquette, kinetic energy, link update): 1e-13 -- the two sides differ
+  only in summation order;
+* solver outputs are compared with both sides solved well below the gate
+  (the GPU path is even/odd, the oracle unpreconditioned): 1e-11 on X and on
+  the force at true residual 1e-13;
+* mixed precision against the FP64 oracle: 1e-9 on the force.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import lgt_inputs as li
+from oracle import action, dirac, force, md, solver, su3
+
+from gpu_common import link_errors, max_rel_err, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(4, 4, 4, 4), (6, 6, 6, 6), (2, 2, 2, 4), (8, 4, 6, 4)]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lgt():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2602_20516_amd as m
+    return m
+
+
+def fields(dims, eps=0.5, seed=1):
+    u = li.random_links(dims, eps, seed)
+    eta = li.gaussian_spinor(dims, seed + 1)
+    return u, eta
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("dagger", [False, True])
+def test_dslash(lgt, dims, dagger):
+    say("dslash", dims, dagger)
+    u, psi = fields(dims)
+    lat = lgt.Lattice(dims)
+    got = to_host(lat.dslash(to_dev(u), to_dev(psi), 0.13, dagger))
+    ref = (dirac.dslash_dag if dagger else dirac.dslash)(u, psi, 0.13)
+    assert rel_err(got, ref) < 1e-13
+    assert max_rel_err(got, ref) < 1e-13
+
+
+def test_dslash_periodic_bc(lgt):
+    dims = (4, 4, 4, 4)
+    u, psi = fields(dims)
+    lat = lgt.Lattice(dims, fermion_bc=+1)
+    got = to_host(lat.dslash(to_dev(u), to_dev(psi), 0.11, False))
+    assert rel_err(got, dirac.dslash(u, psi, 0.11, bc=+1)) < 1e-13
+
+
+def test_dslash_16(lgt):
+    dims = (16, 16, 16, 16)
+    say("dslash 16^4")
+    u, psi = fields(dims, 0.3, 201)
+    lat = lgt.Lattice(dims)
+    for dag in (False, True):
+        got = to_host(lat.dslash(to_dev(u), to_dev(psi), 0.125, dag))
+        ref = (dirac.dslash_dag if dag else dirac.dslash)(u, psi, 0.125)
+        assert rel_err(got, ref) < 1e-13
+
+
+def test_gamma5_hermiticity_on_gpu(lgt):
+    dims = (8, 8, 8, 8)
+    u, psi = fields(dims, 0.4, 7)
+    lat = lgt.Lattice(dims)
+    U = to_dev(u)
+    g5 = np.array([1, 1, -1, -1])[:, None]
+    a = to_host(lat.dslash(U, to_dev(psi), 0.12, True))
+    b = g5 * to_host(lat.dslash(U, to_dev(g5 * psi), 0.12, False))
+    assert rel_err(a, b) < 1e-14
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 6, 6, 6), (2, 2, 2, 4)])
+@pytest.mark.parametrize("mode", ["force", "grad", "momentum"])
+def test_bilinear_force(lgt, dims, mode):
+    say("bilinear", dims, mode)
+    u, a = fields(dims)
+    b = li.gaussian_spinor(dims, 77)
+    k, coeff, dt = 0.12, -2.0, 0.05
+    lat = lgt.Lattice(dims)
+    g = coeff * force.bilinear_grad(u, a, b, k)
+    if mode == "grad":
+        ref = g
+        got = to_host(lat.bilinear_force(to_dev(u), to_dev(a), to_dev(b), k, coeff, "grad"))
+    elif mode == "force":
+        ref = force.force_from_grad(u, g)
+        got = to_host(lat.bilinear_force(to_dev(u), to_dev(a), to_dev(b), k, coeff, "force"))
+    else:
+        p = li.random_momenta(dims, 5)
+        ref = p - dt * force.force_from_grad(u, g)
+        P = to_dev(p)
+        lat.bilinear_force(to_dev(u), to_dev(a), to_dev(b), k, coeff, "momentum", dt, out=P)
+        got = to_host(P)
+    assert rel_err(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 6, 6, 6), (2, 2, 2, 4)])
+@pytest.mark.parametrize("mode", ["force", "grad", "momentum"])
+def test_gauge_force(lgt, dims, mode):
+    say("gauge", dims, mode)
+    u, _ = fields(dims)
+    beta, dt = 5.7, 0.05
+    lat = lgt.Lattice(dims)
+    if mode == "grad":
+        ref = force.gauge_grad(u, beta)
+        got = to_host(lat.gauge_force(to_dev(u), beta, "grad"))
+    elif mode == "force":
+        ref = force.gauge_force(u, beta)
+        got = to_host(lat.gauge_force(to_dev(u), beta, "force"))
+    else:
+        p = li.random_momenta(dims, 5)
+        ref = p - dt * force.gauge_force(u, beta)
+        P = to_dev(p)
+        lat.gauge_force(to_dev(u), beta, "momentum", dt, out=P)
+        got = to_host(P)
+    assert rel_err(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 6, 6, 6)])
+def test_gauge_action_and_kinetic(lgt, dims):
+    u, _ = fields(dims)
+    p = li.random_momenta(dims, 9)
+    lat = lgt.Lattice(dims)
+    sg, _, _ = lat.action(to_dev(u), None, 5.7, 0.0, fermion=False)
+    assert abs(sg - action.gauge_action(u, 5.7)) / abs(action.gauge_action(u, 5.7)) < 1e-13
+    k = lat.kinetic(to_dev(p))
+    assert abs(k - action.kinetic(p)) / action.kinetic(p) < 1e-13
+    # plaquette = 1 at U = 1
+    sg1, _, _ = lat.action(to_dev(li.unit_links(dims)), None, 5.7, 0.0, fermion=False)
+    assert abs(sg1) < 1e-10
+
+
+@pytest.mark.parametrize("dt", [0.05, 0.5, 1e-7, 0.0])
+def test_link_update(lgt, dt):
+    dims = (4, 4, 4, 4)
+    u, _ = fields(dims)
+    p = li.random_momenta(dims, 9)
+    lat = lgt.Lattice(dims)
+    U = to_dev(u)
+    lat.link_update(U, to_dev(p), dt)
+    got = to_host(U)
+    ref = md.link_update(u, p, dt)
+    assert rel_err(got, ref) < 1e-13
+    assert su3.unitarity_defect(got) < 1e-14
+
+
+def test_cg_solve_heat_bath(lgt):
+    """Config-1 workload: S_f(D^dag eta) = eta^dag eta, X against the oracle."""
+    dims = (4, 4, 4, 4)
+    u, eta = li.random_links(dims, 0.5, 101), li.gaussian_spinor(dims, 102)
+    k = 0.12
+    lat = lgt.Lattice(dims)
+    U = to_dev(u)
+    phi = lat.dslash(U, to_dev(eta), k, dagger=True)
+    X, Y, st = lat.cg_solve(U, phi, k, lgt.Params(tol=1e-12))
+    say("cg 4^4", st)
+    assert st["true_rel_residual"] <= 1e-12
+    phi_ref = dirac.dslash_dag(u, eta, k)
+    assert rel_err(to_host(phi), phi_ref) < 1e-14
+    x_ref, y_ref, it, res = solver.solve_ddag_d(u, phi_ref, k, tol=1e-14)
+    assert rel_err(to_host(X), x_ref) < 1e-10
+    assert rel_err(to_host(Y), y_ref) < 1e-10
+    assert rel_err(to_host(Y), eta) < 1e-10
+    _, sf, st2 = lat.action(U, phi, 5.7, k, lgt.Params(tol=1e-10), gauge=False)
+    ee = float(np.vdot(eta.ravel(), eta.ravel()).real)
+    assert abs(sf - ee) / ee < 1e-12
+
+
+@pytest.mark.parametrize("precision,gate", [("fp64", 1e-11), ("mixed_fp32", 1e-9)])
+def test_fermion_force(lgt, precision, gate):
+    dims = (4, 4, 4, 4)
+    u, eta = li.random_links(dims, 0.5, 101), li.gaussian_spinor(dims, 102)
+    k = 0.12
+    phi = dirac.dslash_dag(u, eta, k)
+    ref = force.fermion_force(u, phi, k, tol=1e-14)
+    lat = lgt.Lattice(dims)
+    got, st = lat.fermion_force(to_dev(u), to_dev(phi), k, lgt.Params(precision=precision, tol=1e-13))
+    got = to_host(got)
+    say("force", precision, st, rel_err(got, ref), link_errors(got, ref))
+    assert st["true_rel_residual"] <= 1e-13
+    assert rel_err(got, ref) < gate
+
+
+def test_md_step_config1(lgt):
+    """One leapfrog step of config 1 against the oracle (U, Pi, Delta H)."""
+    c = li.config(1)
+    dims = c["dims"]
+    u = li.random_links(dims, c["eps"], c["seeds"]["links"])
+    eta = li.gaussian_spinor(dims, c["seeds"]["eta"])
+    p = li.random_momenta(dims, c["seeds"]["mom"])
+    beta, k, dt = c["beta"], c["kappa"], c["dt"]
+    phi = dirac.dslash_dag(u, eta, k)
+    u1, p1, dh_ref = md.trajectory_dh(u, p, phi, beta, k, dt, 1, tol=1e-14)
+    lat = lgt.Lattice(dims)
+    U, P = to_dev(u), to_dev(p)
+    dh, st = lat.md_step(U, P, to_dev(phi), beta, k, dt, 1, lgt.Params(tol=1e-13))
+    say("md c1", dh, dh_ref, st)
+    assert rel_err(to_host(U), u1) < 1e-13
+    assert rel_err(to_host(P), p1) < 1e-11
+    assert abs(dh - dh_ref) < 1e-9 * max(1.0, abs(dh_ref))
+
+
+def test_md_reversibility_gpu(lgt):
+    dims = (8, 8, 8, 8)
+    u, eta = fields(dims, 0.3, 31)
+    p = li.random_momenta(dims, 33)
+    k, beta = 0.12, 5.7
+    lat = lgt.Lattice(dims)
+    U, P = to_dev(u), to_dev(p)
+    phi = lat.dslash(U, to_dev(eta), k, dagger=True)
+    prm = lgt.Params(tol=1e-13)
+    dh1, _ = lat.md_step(U, P, phi, beta, k, 0.05, 4, prm)
+    P.neg_()
+    dh2, _ = lat.md_step(U, P, phi, beta, k, 0.05, 4, prm)
+    assert rel_err(to_host(U), u) < 1e-11
+    assert rel_err(-to_host(P), p) < 1e-11
+    assert abs(dh1 + dh2) < 1e-8
+
+
+def test_determinism(lgt):
+    dims = (6, 6, 6, 6)
+    u, eta = fields(dims, 0.4, 3)
+    lat = lgt.Lattice(dims)
+    U, E = to_dev(u), to_dev(eta)
+    a, _ = lat.fermion_force(U, E, 0.12, lgt.Params(tol=1e-10))
+    b, _ = lat.fermion_force(U, E, 0.12, lgt.Params(tol=1e-10))
+    assert np.array_equal(to_host(a), to_host(b))
+
+
+def test_error_paths(lgt):
+    dims = (4, 4, 4, 4)
+    u, eta = fields(dims)
+    lat = lgt.Lattice(dims)
+    U = to_dev(u)
+    bad = eta.copy()
+    bad[1, 2, 3, 0, 2, 1] = np.nan
+    with pytest.raises(lgt.LGTNonFinite):
+        lat.cg_solve(U, to_dev(bad), 0.12)
+    with pytest.raises(lgt.LGTNotConverged) as ei:
+        lat.cg_solve(U, to_dev(eta), 0.12, lgt.Params(max_iter=1))
+    assert ei.value.stats["iters"] >= 1
+    with pytest.raises(lgt.LGTError):
+        lgt.Lattice((4, 4, 3, 4))
+    # the context still works after errors
+    X, _, st = lat.cg_solve(U, to_dev(eta), 0.12, lgt.Params(tol=1e-10))
+    assert st["true_rel_residual"] <= 1e-10
