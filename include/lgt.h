@@ -220,6 +220,39 @@ LGT_API lgt_status lgt_md_step(lgt_ctx* ctx, void* U, void* P, const void* phi, 
                        const lgt_solver_params* params, double* dH_or_null,
                        lgt_solver_stats* stats);
 
+/* Stout smearing (Morningstar-Peardon, the smearing cited in Sec. I and used
+ * in Sec. III B): U_out = stout^nlevels(U_in), each level
+ *   C_mu(x) = rho * sum_{nu != mu} [U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
+ *                                   + U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu)],
+ *   U' = exp(P_su3[C U^dag]) U,
+ * all directions from the previous level, no reunitarization.  FP64;
+ * nlevels >= 0; U_in and U_out may not overlap. */
+LGT_API lgt_status lgt_stout_smear(lgt_ctx* ctx, const void* U_in, void* U_out, double rho, int32_t nlevels);
+
+/* Reverse mode through the smearing (the adjoint update of eq. 3, written
+ * by hand): G_out = gradient at U_in of Re tr(G_top^dag stout^n(U_in)), in the
+ * G convention.  Intermediate levels are recomputed from U_in, not stored.
+ * FP64.  G_top is a gauge-type buffer at the smeared links. */
+LGT_API lgt_status lgt_stout_backprop(lgt_ctx* ctx, const void* U_in, const void* G_top, double rho,
+                                      int32_t nlevels, void* G_out);
+
+/* Force of the smeared action S = S_G(U) + phi^dag (D^dag D)^-1 phi with D
+ * built on stout^n(U) (links enter D only): the pseudofermion force on the
+ * smeared links (as lgt_fermion_force), back-propagated through the
+ * smearing, plus the staple force of the thin links.  mode/dt/out as
+ * lgt_out_mode; S_F_or_null receives S_f. */
+LGT_API lgt_status lgt_smeared_force(lgt_ctx* ctx, const void* U, const void* phi, double beta, double kappa,
+                                     double rho, int32_t nlevels, const lgt_solver_params* params,
+                                     int32_t mode, double dt, void* out, double* S_F_or_null,
+                                     lgt_solver_stats* stats);
+
+/* Leapfrog trajectory (as lgt_md_step) for the smeared action:
+ * H = K + S_G(U) + S_f(stout^n(U)). */
+LGT_API lgt_status lgt_md_step_smeared(lgt_ctx* ctx, void* U, void* P, const void* phi, double beta,
+                                       double kappa, double rho, int32_t nlevels, double dt, int32_t nsteps,
+                                       const lgt_solver_params* params, double* dH_or_null,
+                                       lgt_solver_stats* stats);
+
 /* Measurement entry point: times nrep back-to-back launches of the
  * even/odd hop kernel H_eo (the dominant kernel of the CG; FP64 for
  * precision = LGT_FP64, FP32 otherwise) on links U and input spinor psi,

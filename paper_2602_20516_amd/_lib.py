@@ -73,6 +73,12 @@ PROTOTYPES = {
     "lgt_md_step": (_st, [_vp, _vp, _vp, _vp, _d, _d, _d, _i, ctypes.POINTER(SolverParams),
                           ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
     "lgt_hop_benchmark": (_st, [_vp, _vp, _vp, _i, _i, ctypes.POINTER(_d)]),
+    "lgt_stout_smear": (_st, [_vp, _vp, _vp, _d, _i]),
+    "lgt_stout_backprop": (_st, [_vp, _vp, _vp, _d, _i, _vp]),
+    "lgt_smeared_force": (_st, [_vp, _vp, _vp, _d, _d, _d, _i, ctypes.POINTER(SolverParams), _i, _d, _vp,
+                                ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
+    "lgt_md_step_smeared": (_st, [_vp, _vp, _vp, _vp, _d, _d, _d, _i, _d, _i, ctypes.POINTER(SolverParams),
+                                  ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
 }
 
 _LIB = None

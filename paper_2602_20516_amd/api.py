@@ -224,6 +224,56 @@ class Lattice:
         _check(self.lib, self.ctx, st, stats)
         return dh.value, stats.as_dict()
 
+    def stout_smear(self, U, rho: float, nlevels: int, out=None):
+        """lgt_stout_smear: stout^n(U)."""
+        out = self.empty_gauge() if out is None else out
+        self._bind_stream()
+        st = self.lib.lgt_stout_smear(self.ctx, self._field(U, "gauge", "U"), self._field(out, "gauge", "out"),
+                                      float(rho), int(nlevels))
+        _check(self.lib, self.ctx, st)
+        return out
+
+    def stout_backprop(self, U, G_top, rho: float, nlevels: int, out=None):
+        """lgt_stout_backprop: gradient at U of Re tr(G_top^dag stout^n(U))."""
+        out = self.empty_gauge() if out is None else out
+        self._bind_stream()
+        st = self.lib.lgt_stout_backprop(self.ctx, self._field(U, "gauge", "U"),
+                                         self._field(G_top, "gauge", "G_top"), float(rho), int(nlevels),
+                                         self._field(out, "gauge", "out"))
+        _check(self.lib, self.ctx, st)
+        return out
+
+    def smeared_force(self, U, phi, beta: float, kappa: float, rho: float, nlevels: int,
+                      params: Optional[Params] = None, mode: str = "force", dt: float = 0.0, out=None):
+        """lgt_smeared_force: returns (out, S_F, stats)."""
+        params = params or Params()
+        out = self.empty_gauge() if out is None else out
+        sf = ctypes.c_double()
+        stats = SolverStats()
+        cp = params.to_c()
+        self._bind_stream()
+        st = self.lib.lgt_smeared_force(self.ctx, self._field(U, "gauge", "U"), self._field(phi, "spinor", "phi"),
+                                        float(beta), float(kappa), float(rho), int(nlevels), ctypes.byref(cp),
+                                        _MODES[mode], float(dt), self._field(out, "gauge", "out"),
+                                        ctypes.byref(sf), ctypes.byref(stats))
+        _check(self.lib, self.ctx, st, stats)
+        return out, sf.value, stats.as_dict()
+
+    def md_step_smeared(self, U, P, phi, beta: float, kappa: float, rho: float, nlevels: int, dt: float,
+                        nsteps: int, params: Optional[Params] = None):
+        """lgt_md_step_smeared: leapfrog with the stout-smeared action; returns (dH, stats)."""
+        params = params or Params()
+        dh = ctypes.c_double()
+        stats = SolverStats()
+        cp = params.to_c()
+        self._bind_stream()
+        st = self.lib.lgt_md_step_smeared(self.ctx, self._field(U, "gauge", "U"), self._field(P, "gauge", "P"),
+                                          self._field(phi, "spinor", "phi") if phi is not None else None,
+                                          float(beta), float(kappa), float(rho), int(nlevels), float(dt),
+                                          int(nsteps), ctypes.byref(cp), ctypes.byref(dh), ctypes.byref(stats))
+        _check(self.lib, self.ctx, st, stats)
+        return dh.value, stats.as_dict()
+
     def hop_benchmark(self, U, psi, precision: str = "fp64", nrep: int = 50) -> float:
         """lgt_hop_benchmark: mean duration (ms) of one even/odd hop launch."""
         ms = ctypes.c_double()
@@ -277,3 +327,20 @@ def lgt_md_step(lat: Lattice, U, P, phi, beta, kappa, dt, nsteps, params=None):
 
 def lgt_hop_benchmark(lat: Lattice, U, psi, precision="fp64", nrep=50):
     return lat.hop_benchmark(U, psi, precision, nrep)
+
+
+def lgt_stout_smear(lat: Lattice, U, rho, nlevels, out=None):
+    return lat.stout_smear(U, rho, nlevels, out)
+
+
+def lgt_stout_backprop(lat: Lattice, U, G_top, rho, nlevels, out=None):
+    return lat.stout_backprop(U, G_top, rho, nlevels, out)
+
+
+def lgt_smeared_force(lat: Lattice, U, phi, beta, kappa, rho, nlevels, params=None, mode="force", dt=0.0,
+                      out=None):
+    return lat.smeared_force(U, phi, beta, kappa, rho, nlevels, params, mode, dt, out)
+
+
+def lgt_md_step_smeared(lat: Lattice, U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, params=None):
+    return lat.md_step_smeared(U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, params)

@@ -14,6 +14,8 @@ namespace {
 std::string g_create_error;
 
 enum { kPhi = 0, kX = 1, kY = 2, kStageA = 11, kStageB = 12 };
+// packed gauge scratch used here (see smear.hip): thin links, smeared output, gradient
+enum { kThin = 6, kSmeared = 8, kGradIn = 9 };
 
 template <typename F>
 lgt_status guarded(lgt_ctx* ctx, F&& f) {
@@ -93,8 +95,8 @@ struct Timer {
   }
 };
 
-double gauge_action(lgt_ctx* c, double beta) {
-  LGT_HIP(launch_plaquette(c->g, c->U64, c->red(), 0, c->stream));
+double gauge_action(lgt_ctx* c, double beta, const double2* links = nullptr) {
+  LGT_HIP(launch_plaquette(c->g, links ? links : c->U64, c->red(), 0, c->stream));
   c->read_results(1);
   return beta * (6.0 * (double)c->V - c->host_result[0] / 3.0);
 }
@@ -150,13 +152,11 @@ lgt_status lgt_create(const lgt_geom* geom, void* hip_stream, lgt_ctx** out) {
     LGT_HIP(hipMalloc(&c->U64, (size_t)72 * c->vh * sizeof(double2)));
     LGT_HIP(hipMalloc(&c->state, sizeof(SolverState)));
     LGT_HIP(hipMalloc(&c->partials, (size_t)reduce_capacity(c->vh) * 4 * sizeof(double)));
-    LGT_HIP(hipMalloc(&c->ticket, 64 * sizeof(unsigned)));
     LGT_HIP(hipMalloc(&c->result, 64 * sizeof(double)));
     LGT_HIP(hipMalloc(&c->flags, 16 * sizeof(int)));
     LGT_HIP(hipHostMalloc(&c->host_result, 64 * sizeof(double), hipHostMallocDefault));
     LGT_HIP(hipHostMalloc(&c->host_flags, 16 * sizeof(int), hipHostMallocDefault));
     LGT_HIP(hipHostMalloc(&c->host_state, sizeof(SolverState), hipHostMallocDefault));
-    LGT_HIP(hipMemsetAsync(c->ticket, 0, 64 * sizeof(unsigned), c->stream));
     LGT_HIP(hipMemsetAsync(c->flags, 0, 16 * sizeof(int), c->stream));
     LGT_HIP(hipMemsetAsync(c->state, 0, sizeof(SolverState), c->stream));
     LGT_HIP(hipEventCreate(&c->ev0));
@@ -182,7 +182,6 @@ lgt_status lgt_destroy(lgt_ctx* c) {
   (void)hipFree(c->P64);
   (void)hipFree(c->state);
   (void)hipFree(c->partials);
-  (void)hipFree(c->ticket);
   (void)hipFree(c->result);
   (void)hipFree(c->flags);
   if (c->host_result) (void)hipHostFree(c->host_result);
@@ -342,20 +341,29 @@ lgt_status lgt_kinetic(lgt_ctx* c, const void* P, double* K) {
   });
 }
 
-lgt_status lgt_md_step(lgt_ctx* c, void* U, void* P, const void* phi, double beta, double kappa, double dt,
-                       int32_t nsteps, const lgt_solver_params* params, double* dH, lgt_solver_stats* stats) {
+// Leapfrog with merged half-kicks (Sec. III B), nlevels = 0: plain action,
+// nlevels > 0: stout-smeared fermion action.
+static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double beta, double kappa, double rho,
+                         int32_t nlevels, double dt, int32_t nsteps, const lgt_solver_params* params, double* dH,
+                         lgt_solver_stats* stats) {
   if (!c) return LGT_ERR_INVALID_ARGUMENT;
   bool nc = false;
   lgt_status s = guarded(c, [&] {
     require(U && P, "null field pointer");
     require(nsteps >= 1, "nsteps must be >= 1");
-    require(std::isfinite(dt), "dt must be finite");
+    require(nlevels >= 0, "nlevels must be >= 0");
+    require(std::isfinite(dt) && std::isfinite(rho), "dt and rho must be finite");
     const SolverOpts o = parse(params);
     const bool ferm = phi != nullptr && kappa != 0.0;
     const bool mixed = ferm && o.precision != LGT_FP64;
+    const bool smeared = ferm && nlevels > 0;
     Timer tm(c);
     c->ensure_p64();
-    pack_links(c, U, mixed);
+    // thin links: U64 for the plain action; a separate field when smearing
+    // (U64 then holds the smeared links the solver runs on)
+    double2* thin = smeared ? c->g64(kThin) : c->U64;
+    if (smeared) LGT_HIP(launch_pack(c->g, 36, (const double2*)U, thin, nullptr, c->flags, c->stream));
+    else pack_links(c, U, mixed);
     LGT_HIP(launch_pack(c->g, 36, (const double2*)P, c->P64, nullptr, c->flags, c->stream));
     if (ferm) pack_spinor(c, phi, c->f64(kPhi));
     check_nonfinite(c, "U, P or phi");
@@ -366,33 +374,106 @@ lgt_status lgt_md_step(lgt_ctx* c, void* U, void* P, const void* phi, double bet
     LGT_HIP(launch_kinetic(c->g, c->P64, kPacked, c->red(), 0, c->stream));
     c->read_results(1);
     const double k0 = c->host_result[0];
-    const double sg0 = gauge_action(c, beta);
+    const double sg0 = gauge_action(c, beta, thin);
 
     auto kick = [&](double h, bool first, bool last) {
-      LGT_HIP(launch_gauge_force(c->g, c->U64, beta, LGT_OUT_MOMENTUM, h, c->P64, kPacked, c->stream));
+      double* sfp = first ? &sf0 : (last ? &sf1 : nullptr);
+      if (smeared) {
+        SolveStats st = c->smeared_force(thin, c->f64(kPhi), beta, rho, nlevels, o, LGT_OUT_MOMENTUM, h, c->P64,
+                                         kPacked, sfp);
+        merge(all, st);
+        return;
+      }
+      LGT_HIP(launch_gauge_force(c->g, thin, beta, LGT_OUT_MOMENTUM, h, c->P64, kPacked, c->stream));
       if (!ferm) return;
       SolveStats st = c->solve_ddagd(c->f64(kPhi), c->f64(kX), c->f64(kY), o);
       merge(all, st);
-      if (first) sf0 = c->action_fermion(c->f64(kPhi), c->f64(kX), c->f64(kY));
-      if (last) sf1 = c->action_fermion(c->f64(kPhi), c->f64(kX), c->f64(kY));
-      LGT_HIP(launch_bilinear_force(c->g, c->U64, c->f64(kY), c->f64(kX), kappa, -2.0, LGT_OUT_MOMENTUM, h,
+      if (sfp) *sfp = c->action_fermion(c->f64(kPhi), c->f64(kX), c->f64(kY));
+      LGT_HIP(launch_bilinear_force(c->g, thin, c->f64(kY), c->f64(kX), kappa, -2.0, LGT_OUT_MOMENTUM, h,
                                     c->P64, kPacked, c->stream));
     };
-    kick(0.5 * dt, true, false);
+    kick(0.5 * dt, true, nsteps == 0);
     for (int k = 0; k < nsteps; ++k) {
-      LGT_HIP(launch_link_update(c->g, c->U64, c->P64, dt, kPacked, mixed ? c->U32 : nullptr, c->stream));
+      LGT_HIP(launch_link_update(c->g, thin, c->P64, dt, kPacked, (mixed && !smeared) ? c->U32 : nullptr,
+                                 c->stream));
       const bool last = k == nsteps - 1;
       kick(last ? 0.5 * dt : dt, false, last);
     }
     LGT_HIP(launch_kinetic(c->g, c->P64, kPacked, c->red(), 0, c->stream));
     c->read_results(1);
     const double k1 = c->host_result[0];
-    const double sg1 = gauge_action(c, beta);
+    const double sg1 = gauge_action(c, beta, thin);
     if (dH) *dH = (k1 - k0) + (sg1 - sg0) + (sf1 - sf0);
-    LGT_HIP(launch_unpack(c->g, 36, c->U64, (double2*)U, c->stream));
+    LGT_HIP(launch_unpack(c->g, 36, thin, (double2*)U, c->stream));
     LGT_HIP(launch_unpack(c->g, 36, c->P64, (double2*)P, c->stream));
     fill_stats(stats, all, tm.stop());
     nc = !all.converged;
+  });
+  if (s == LGT_OK && nc) {
+    c->err = "solver did not reach the tolerance";
+    return LGT_ERR_NOT_CONVERGED;
+  }
+  return s;
+}
+
+lgt_status lgt_md_step(lgt_ctx* c, void* U, void* P, const void* phi, double beta, double kappa, double dt,
+                       int32_t nsteps, const lgt_solver_params* params, double* dH, lgt_solver_stats* stats) {
+  return md_run(c, U, P, phi, beta, kappa, 0.0, 0, dt, nsteps, params, dH, stats);
+}
+
+lgt_status lgt_md_step_smeared(lgt_ctx* c, void* U, void* P, const void* phi, double beta, double kappa,
+                               double rho, int32_t nlevels, double dt, int32_t nsteps,
+                               const lgt_solver_params* params, double* dH, lgt_solver_stats* stats) {
+  return md_run(c, U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, params, dH, stats);
+}
+
+lgt_status lgt_stout_smear(lgt_ctx* c, const void* U_in, void* U_out, double rho, int32_t nlevels) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(U_in && U_out, "null field pointer");
+    require(nlevels >= 0 && std::isfinite(rho), "invalid smearing parameters");
+    double2* thin = c->g64(kThin);
+    double2* out = c->g64(kSmeared);
+    LGT_HIP(launch_pack(c->g, 36, (const double2*)U_in, thin, nullptr, c->flags, c->stream));
+    c->smear(thin, nlevels, rho, out);
+    LGT_HIP(launch_unpack(c->g, 36, out, (double2*)U_out, c->stream));
+  });
+}
+
+lgt_status lgt_stout_backprop(lgt_ctx* c, const void* U_in, const void* G_top, double rho, int32_t nlevels,
+                              void* G_out) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(U_in && G_top && G_out, "null field pointer");
+    require(nlevels >= 0 && std::isfinite(rho), "invalid smearing parameters");
+    double2* thin = c->g64(kThin);
+    double2* G = c->g64(kGradIn);
+    LGT_HIP(launch_pack(c->g, 36, (const double2*)U_in, thin, nullptr, c->flags, c->stream));
+    LGT_HIP(launch_pack(c->g, 36, (const double2*)G_top, G, nullptr, c->flags, c->stream));
+    c->stout_backprop(thin, nlevels, rho, G);
+    LGT_HIP(launch_unpack(c->g, 36, G, (double2*)G_out, c->stream));
+  });
+}
+
+lgt_status lgt_smeared_force(lgt_ctx* c, const void* U, const void* phi, double beta, double kappa, double rho,
+                             int32_t nlevels, const lgt_solver_params* params, int32_t mode, double dt, void* out,
+                             double* S_F, lgt_solver_stats* stats) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  bool nc = false;
+  lgt_status s = guarded(c, [&] {
+    require(U && phi && out, "null field pointer");
+    require(mode >= LGT_OUT_FORCE && mode <= LGT_OUT_MOMENTUM, "unknown output mode");
+    require(nlevels >= 0 && std::isfinite(rho), "invalid smearing parameters");
+    const SolverOpts o = parse(params);
+    Timer tm(c);
+    double2* thin = c->g64(kThin);
+    LGT_HIP(launch_pack(c->g, 36, (const double2*)U, thin, nullptr, c->flags, c->stream));
+    pack_spinor(c, phi, c->f64(kPhi));
+    check_nonfinite(c, "U or phi");
+    c->kappa = kappa;
+    SolveStats st = c->smeared_force(thin, c->f64(kPhi), beta, rho, nlevels, o, mode, dt, out, kCanonical, S_F);
+    fill_stats(stats, st, tm.stop());
+    nc = !st.converged;
   });
   if (s == LGT_OK && nc) {
     c->err = "solver did not reach the tolerance";

@@ -6,7 +6,8 @@
 // global writes are unit-stride across a wavefront.
 //
 // Vector kernels work on flat arrays of n complex numbers (grid-stride,
-// unit-stride).  Reductions are deterministic (see grid_sum).
+// unit-stride).  Reductions write block partials; the one-block finalize
+// kernel sums them in a fixed order (deterministic, see block_partials).
 #include "lgt_internal.h"
 
 namespace lgt {
@@ -114,9 +115,7 @@ static inline int vec_blocks(int n) {
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_cg_init(int n, const R2<R>* __restrict__ b, R2<R>* __restrict__ r,
-                                                 R2<R>* __restrict__ p, R2<R>* __restrict__ x,
-                                                 SolverState* st, double* partials, unsigned* ticket,
-                                                 double tol, int max_iter) {
+                                                 R2<R>* __restrict__ p, R2<R>* __restrict__ x, double* partials) {
   double acc = 0.0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const R2<R> v = b[i];
@@ -128,8 +127,32 @@ __global__ __launch_bounds__(256) void k_cg_init(int n, const R2<R>* __restrict_
     x[i] = z;
     acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
   }
-  double v[1] = {acc}, tot[1];
-  if (grid_sum<256, 1>(v, partials, ticket, blockIdx.x, gridDim.x, tot) && threadIdx.x == 0) {
+  double v[1] = {acc};
+  block_partials<256, 1>(v, partials, blockIdx.x);
+}
+
+template <typename R>
+hipError_t launch_cg_init(int n, const R2<R>* b, R2<R>* r, R2<R>* p, R2<R>* x, SolverState* st,
+                          Reduce red, double tol, int max_iter, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  hipLaunchKernelGGL((k_cg_init<R>), dim3(nb), dim3(256), 0, s, n, b, r, p, x, red.partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(kFinCgInit, nb, red, st, 0, tol, max_iter, s);
+}
+
+// One block: sum the partials of the previous launch and act on the totals.
+template <int NV>
+__global__ __launch_bounds__(256) void k_finalize(int mode, int nblk, const double* __restrict__ partials,
+                                                  SolverState* st, double* result, double tol, int max_iter) {
+  if (mode == kFinCgStep && st->done != kDoneRunning) return;  // the iteration was skipped
+  double tot[NV];
+  sum_partials<256, NV>(partials, nblk, tot);
+  if (threadIdx.x != 0) return;
+  if (mode == kFinResult1 || mode == kFinResult2) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) result[k] = tot[k];
+  } else if (mode == kFinCgInit) {
     const double rr = tot[0];
     st->rr = rr;
     st->rr0 = rr;
@@ -141,14 +164,27 @@ __global__ __launch_bounds__(256) void k_cg_init(int n, const R2<R>* __restrict_
     st->beta = 0.0;
     st->pap = 0.0;
     st->done = !isfinite(rr) ? kDoneBreakdown : (rr == 0.0 ? kDoneConverged : kDoneRunning);
+  } else {  // kFinCgStep
+    const double rr = tot[0];
+    st->beta = rr / st->rr;
+    st->rr = rr;
+    st->iter += 1;
+    if (rr > st->rr_max) st->rr_max = rr;
+    if (!isfinite(rr)) st->done = kDoneBreakdown;
+    else if (rr <= st->rr_stop) st->done = kDoneConverged;
+    else if (st->iter >= st->max_iter) st->done = kDoneMaxIter;
   }
 }
 
-template <typename R>
-hipError_t launch_cg_init(int n, const R2<R>* b, R2<R>* r, R2<R>* p, R2<R>* x, SolverState* st,
-                          Reduce red, double tol, int max_iter, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_init<R>), dim3(vec_blocks(n)), dim3(256), 0, s, n, b, r, p, x, st,
-                     red.partials, red.ticket, tol, max_iter);
+hipError_t launch_finalize(int mode, int nblk, Reduce red, SolverState* st, int slot, double tol, int max_iter,
+                           hipStream_t s) {
+  if (nblk > red.capacity) return hipErrorInvalidValue;
+  if (mode == kFinResult2)
+    hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(256), 0, s, mode, nblk, red.partials, st, red.result + slot,
+                       tol, max_iter);
+  else
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(256), 0, s, mode, nblk, red.partials, st, red.result + slot,
+                       tol, max_iter);
   return hipGetLastError();
 }
 
@@ -174,8 +210,7 @@ hipError_t launch_cg_xpay(int n, const R2<R>* r, R2<R>* p, SolverState* st, hipS
 }
 
 __global__ __launch_bounds__(256) void k_norm_dot(int n, const double2* __restrict__ a,
-                                                  const double2* __restrict__ b, double* partials,
-                                                  unsigned* ticket, double* result) {
+                                                  const double2* __restrict__ b, double* partials) {
   double nn = 0.0, dd = 0.0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const double2 av = a[i];
@@ -185,17 +220,16 @@ __global__ __launch_bounds__(256) void k_norm_dot(int n, const double2* __restri
       dd += av.x * bv.x + av.y * bv.y;
     }
   }
-  double v[2] = {nn, dd}, tot[2];
-  if (grid_sum<256, 2>(v, partials, ticket, blockIdx.x, gridDim.x, tot) && threadIdx.x == 0) {
-    result[0] = tot[0];
-    result[1] = tot[1];
-  }
+  double v[2] = {nn, dd};
+  block_partials<256, 2>(v, partials, blockIdx.x);
 }
 
 hipError_t launch_norm_dot(int n, const double2* a, const double2* b, Reduce red, int slot, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_dot, dim3(vec_blocks(n)), dim3(256), 0, s, n, a, b, red.partials, red.ticket,
-                     red.result + slot);
-  return hipGetLastError();
+  const int nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_norm_dot, dim3(nb), dim3(256), 0, s, n, a, b, red.partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(kFinResult2, nb, red, nullptr, slot, 0.0, 0, s);
 }
 
 __global__ __launch_bounds__(256) void k_axpy64(int n, double a, const double2* __restrict__ x,
@@ -243,6 +277,14 @@ hipError_t launch_zero64(int n, double2* y, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_zero32(int n, float2* __restrict__ y) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) y[i] = make_float2(0.f, 0.f);
+}
+hipError_t launch_zero32(int n, float2* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero32, dim3((n + 255) / 256), dim3(256), 0, s, n, y);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_convert_64_32(int n, const double2* __restrict__ x, float2* __restrict__ y) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const double2 v = x[i];
@@ -254,51 +296,44 @@ hipError_t launch_convert_64_32(int n, const double2* x, float2* y, hipStream_t 
   return hipGetLastError();
 }
 
-// x (FP64) += xs (FP32); xs = 0
-__global__ __launch_bounds__(256) void k_mixed_update(int n, float2* xs, double2* __restrict__ x) {
+// x (FP64) += scale * xs (FP32); xs = 0
+__global__ __launch_bounds__(256) void k_mixed_update(int n, float2* xs, double2* __restrict__ x, double scale) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const float2 v = xs[i];
     double2 xv = x[i];
-    xv.x += (double)v.x;
-    xv.y += (double)v.y;
+    xv.x += scale * (double)v.x;
+    xv.y += scale * (double)v.y;
     x[i] = xv;
     xs[i] = make_float2(0.f, 0.f);
   }
 }
-hipError_t launch_mixed_update(int n, float2* xs, double2* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_mixed_update, dim3((n + 255) / 256), dim3(256), 0, s, n, xs, x);
+hipError_t launch_mixed_update(int n, float2* xs, double2* x, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_mixed_update, dim3((n + 255) / 256), dim3(256), 0, s, n, xs, x, scale);
   return hipGetLastError();
 }
 
-// Reliable update: r (low precision) = r64; rr = |r64|^2 (FP64); new beta
-// keeps the search direction: beta = rr_new / rr_old.
-template <typename R>
-__global__ __launch_bounds__(256) void k_cg_reliable(int n, const double2* __restrict__ r64, R2<R>* __restrict__ r,
-                                                     SolverState* st, double* partials, unsigned* ticket) {
-  double acc = 0.0;
+// Reliable update of the FP32 recursion: r = sigma r64 (FP64 residual scaled
+// to unit norm), and the search direction either restarted (p = r) or
+// rescaled to the new units (p *= pscale).
+__global__ __launch_bounds__(256) void k_rescale_residual(int n, const double2* __restrict__ r64, double sigma,
+                                                          float2* __restrict__ r, float2* __restrict__ p,
+                                                          int restart, double pscale) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const double2 v = r64[i];
-    R2<R> w;
-    w.x = R(v.x);
-    w.y = R(v.y);
+    const float2 w = make_float2((float)(sigma * v.x), (float)(sigma * v.y));
     r[i] = w;
-    acc += v.x * v.x + v.y * v.y;
-  }
-  double v[1] = {acc}, tot[1];
-  if (grid_sum<256, 1>(v, partials, ticket, blockIdx.x, gridDim.x, tot) && threadIdx.x == 0) {
-    const double rr = tot[0];
-    st->rr = rr;
-    st->rr_max = rr;
-    if (!isfinite(rr)) st->done = kDoneBreakdown;
-    else if (rr <= st->rr_stop) st->done = kDoneConverged;
-    else if (st->iter >= st->max_iter) st->done = kDoneMaxIter;
-    else st->done = kDoneRunning;
+    if (restart) {
+      p[i] = w;
+    } else {
+      const float2 q = p[i];
+      p[i] = make_float2((float)(pscale * (double)q.x), (float)(pscale * (double)q.y));
+    }
   }
 }
-template <typename R>
-hipError_t launch_cg_reliable(int n, const double2* r64, R2<R>* r, SolverState* st, Reduce red, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_reliable<R>), dim3(vec_blocks(n)), dim3(256), 0, s, n, r64, r, st, red.partials,
-                     red.ticket);
+hipError_t launch_rescale_residual(int n, const double2* r64, double sigma, float2* r, float2* p, int restart,
+                                   double pscale, hipStream_t s) {
+  hipLaunchKernelGGL(k_rescale_residual, dim3((n + 255) / 256), dim3(256), 0, s, n, r64, sigma, r, p, restart,
+                     pscale);
   return hipGetLastError();
 }
 
@@ -308,7 +343,6 @@ template hipError_t launch_cg_init<float>(int, const float2*, float2*, float2*, 
                                           double, int, hipStream_t);
 template hipError_t launch_cg_xpay<double>(int, const double2*, double2*, SolverState*, hipStream_t);
 template hipError_t launch_cg_xpay<float>(int, const float2*, float2*, SolverState*, hipStream_t);
-template hipError_t launch_cg_reliable<float>(int, const double2*, float2*, SolverState*, Reduce, hipStream_t);
-template hipError_t launch_cg_reliable<double>(int, const double2*, double2*, SolverState*, Reduce, hipStream_t);
+
 
 }  // namespace lgt

@@ -133,7 +133,12 @@ struct EpiAxpy {  // out = self + coef * acc
   const R2<R>* self[2];
   R coef;
   int vh;
-  const SolverState* guard;  // if set, the launch is a no-op once the solve has finished
+  SolverState* guard;  // if set, the launch is a no-op once the solve has finished
+  // If set, block 0 also turns the |w|^2 block partials of the previous
+  // launch into pap and alpha = rr / pap (the CG step between the two hops
+  // of Mhat^dag Mhat, which need no scalar).
+  const double* pap_partials;
+  int pap_nblk;
   __device__ bool skip() const { return guard && guard->done != kDoneRunning; }
   __device__ void apply(int p, int cb, int spin, const C<R>* acc, double&) const {
 #pragma unroll
@@ -144,11 +149,25 @@ struct EpiAxpy {  // out = self + coef * acc
       st<R>(out[p] + o, v);
     }
   }
-  __device__ void finalize(const double*) const {}
+  __device__ void tail() const {
+    if (!pap_partials || blockIdx.x != 0) return;
+    double tot[1];
+    sum_partials<256, 1>(pap_partials, pap_nblk, tot);
+    if (threadIdx.x == 0) {
+      const double pap = tot[0];
+      guard->pap = pap;
+      if (!(pap > 0.0) || !isfinite(pap)) {
+        guard->alpha = 0.0;
+        guard->done = kDoneBreakdown;
+      } else {
+        guard->alpha = guard->rr / pap;
+      }
+    }
+  }
 };
 
 template <typename R>
-struct EpiSchurNorm {  // w = x + coef * acc (odd sites), reduce |w|^2 -> pap, alpha
+struct EpiSchurNorm {  // w = x + coef * acc (odd sites), block partials of |w|^2
   static constexpr bool kReduce = true;
   R2<R>* w;
   const R2<R>* x;
@@ -162,23 +181,14 @@ struct EpiSchurNorm {  // w = x + coef * acc (odd sites), reduce |w|^2 -> pap, a
       const size_t o = (size_t)(3 * spin + i) * vh + cb;
       C<R> v = ld<R>(x + o) + coef * acc[i];
       st<R>(w + o, v);
-      red += (double)norm2(v);
+      red += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
     }
   }
-  __device__ void finalize(const double* tot) const {
-    const double pap = tot[0];
-    state->pap = pap;
-    if (!(pap > 0.0) || !isfinite(pap)) {
-      state->alpha = 0.0;
-      state->done = kDoneBreakdown;
-    } else {
-      state->alpha = state->rr / pap;
-    }
-  }
+  __device__ void tail() const {}
 };
 
 template <typename R>
-struct EpiSchurCG {  // q = w + coef * acc; x += alpha p; r -= alpha q; reduce |r|^2
+struct EpiSchurCG {  // q = w + coef * acc; x += alpha p; r -= alpha q; block partials of |r|^2
   static constexpr bool kReduce = true;
   const R2<R>* w;
   R2<R>* x;
@@ -199,29 +209,19 @@ struct EpiSchurCG {  // q = w + coef * acc; x += alpha p; r -= alpha q; reduce |
       C<R> rv = ld<R>(r + o) - alpha * q;
       st<R>(x + o, xv);
       st<R>(r + o, rv);
-      red += (double)norm2(rv);
+      red += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
     }
   }
-  __device__ void finalize(const double* tot) const {
-    const double rr = tot[0];
-    state->beta = rr / state->rr;
-    state->rr = rr;
-    state->iter += 1;
-    if (rr > state->rr_max) state->rr_max = rr;
-    if (!isfinite(rr)) state->done = kDoneBreakdown;
-    else if (rr <= state->rr_stop) state->done = kDoneConverged;
-    else if (state->iter >= state->max_iter) state->done = kDoneMaxIter;
-  }
+  __device__ void tail() const {}
 };
 
-struct EpiResidual {  // r = phi - (self + coef * acc) over both parities, reduce |r|^2
+struct EpiResidual {  // r = phi - (self + coef * acc) over both parities, block partials of |r|^2
   static constexpr bool kReduce = true;
   const double2* self[2];
   const double2* phi[2];
   double2* r[2];
   double coef;
   int vh;
-  double* result;
   __device__ bool skip() const { return false; }
   __device__ void apply(int p, int cb, int spin, const C<double>* acc, double& red) const {
 #pragma unroll
@@ -232,7 +232,7 @@ struct EpiResidual {  // r = phi - (self + coef * acc) over both parities, reduc
       red += norm2(v);
     }
   }
-  __device__ void finalize(const double* tot) const { result[0] = tot[0]; }
+  __device__ void tail() const {}
 };
 
 // ---------------------------------------------------------------------------
@@ -241,7 +241,7 @@ struct EpiResidual {  // r = phi - (self + coef * acc) over both parities, reduc
 // ---------------------------------------------------------------------------
 template <typename R, bool DAG, typename Epi>
 __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, HopIn<R> hin, Epi epi,
-                                             double* partials, unsigned* ticket) {
+                                             double* partials) {
   if (epi.skip()) return;
   __shared__ R2<R> lds[4][12][64];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -286,45 +286,48 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, HopIn
   double red = 0.0;
   if (active) epi.apply(p, cb, spin, out, red);
   if constexpr (Epi::kReduce) {
-    double v[1] = {red}, tot[1];
-    if (grid_sum<256, 1>(v, partials, ticket, lb, gridDim.x, tot) && threadIdx.x == 0)
-      epi.finalize(tot);
+    double v[1] = {red};
+    block_partials<256, 1>(v, partials, lb);
   }
+  epi.tail();
 }
 
 static inline int nblk_parity(const Geom& g) { return (g.vh + 63) / 64; }
 
 template <typename R, bool DAG, typename Epi>
 static hipError_t launch(const Geom& g, int p_out, const HopIn<R>& hin, const Epi& epi, double* partials,
-                         unsigned* ticket, hipStream_t s, int capacity = 0) {
+                         hipStream_t s, int capacity = 0) {
   const int nbp = nblk_parity(g);
   const int nb = p_out >= 0 ? nbp : 2 * nbp;
   if (Epi::kReduce && nb > capacity) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_hop<R, DAG, Epi>), dim3(nb), dim3(256), 0, s, g, nbp, p_out, hin, epi, partials,
-                     ticket);
+  hipLaunchKernelGGL((k_hop<R, DAG, Epi>), dim3(nb), dim3(256), 0, s, g, nbp, p_out, hin, epi, partials);
   return hipGetLastError();
 }
+
+int hop_blocks(const Geom& g, int p_out) { return p_out >= 0 ? nblk_parity(g) : 2 * nblk_parity(g); }
 
 template <typename R, bool DAG>
 hipError_t launch_hop_axpy(const Geom& g, int p_out, HopIn<R> hin, R2<R>* out_even, R2<R>* out_odd,
                            const R2<R>* self_even, const R2<R>* self_odd, double coef, hipStream_t s,
-                           const SolverState* guard) {
+                           SolverState* guard, const double* pap_partials) {
   EpiAxpy<R> e;
   e.guard = guard;
+  e.pap_partials = pap_partials;
+  e.pap_nblk = nblk_parity(g);
   e.out[0] = out_even;
   e.out[1] = out_odd;
   e.self[0] = self_even;
   e.self[1] = self_odd;
   e.coef = R(coef);
   e.vh = g.vh;
-  return launch<R, DAG>(g, p_out, hin, e, nullptr, nullptr, s);
+  return launch<R, DAG>(g, p_out, hin, e, nullptr, s);
 }
 
 template <typename R, bool DAG>
 hipError_t launch_hop_schur_norm(const Geom& g, HopIn<R> hin, R2<R>* w, const R2<R>* x, double coef,
                                  SolverState* st, Reduce red, hipStream_t s) {
   EpiSchurNorm<R> e{w, x, R(coef), g.vh, st};
-  return launch<R, DAG>(g, 1, hin, e, red.partials, red.ticket, s, red.capacity);
+  return launch<R, DAG>(g, 1, hin, e, red.partials, s, red.capacity);
 }
 
 template <typename R, bool DAG>
@@ -332,7 +335,9 @@ hipError_t launch_hop_schur_cg(const Geom& g, HopIn<R> hin, const R2<R>* w, R2<R
                                const R2<R>* p, double coef, SolverState* st, Reduce red,
                                hipStream_t s) {
   EpiSchurCG<R> e{w, x, r, p, R(coef), g.vh, st};
-  return launch<R, DAG>(g, 1, hin, e, red.partials, red.ticket, s, red.capacity);
+  hipError_t err = launch<R, DAG>(g, 1, hin, e, red.partials, s, red.capacity);
+  if (err != hipSuccess) return err;
+  return launch_finalize(kFinCgStep, nblk_parity(g), red, st, 0, 0.0, 0, s);
 }
 
 template <bool DAG>
@@ -349,13 +354,15 @@ hipError_t launch_hop_residual(const Geom& g, HopIn<double> hin, const double2* 
   e.r[1] = r_full + half;
   e.coef = coef;
   e.vh = g.vh;
-  e.result = red.result + slot;
-  return launch<double, DAG>(g, -1, hin, e, red.partials, red.ticket, s, red.capacity);
+  hipError_t err = launch<double, DAG>(g, -1, hin, e, red.partials, s, red.capacity);
+  if (err != hipSuccess) return err;
+  return launch_finalize(kFinResult1, 2 * nblk_parity(g), red, nullptr, slot, 0.0, 0, s);
 }
 
 #define LGT_INST_HOP(R, DAG)                                                                          \
   template hipError_t launch_hop_axpy<R, DAG>(const Geom&, int, HopIn<R>, R2<R>*, R2<R>*, const R2<R>*, \
-                                               const R2<R>*, double, hipStream_t, const SolverState*); \
+                                               const R2<R>*, double, hipStream_t, SolverState*,       \
+                                               const double*);                                        \
   template hipError_t launch_hop_schur_norm<R, DAG>(const Geom&, HopIn<R>, R2<R>*, const R2<R>*,      \
                                                      double, SolverState*, Reduce, hipStream_t);     \
   template hipError_t launch_hop_schur_cg<R, DAG>(const Geom&, HopIn<R>, const R2<R>*, R2<R>*,        \

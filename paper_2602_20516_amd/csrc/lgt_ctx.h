@@ -60,11 +60,12 @@ struct lgt_ctx {
   // spinor workspace: FP64 full fields (24*vh complex each) and FP32 half fields
   std::vector<double2*> full64;
   std::vector<float2*> half32;
+  // packed FP64 gauge-type scratch fields (72*vh complex each)
+  std::vector<double2*> gauge64;
 
   // reductions / solver state
   lgt::SolverState* state = nullptr;
   double* partials = nullptr;
-  unsigned* ticket = nullptr;
   double* result = nullptr;      // device results
   double* host_result = nullptr; // pinned mirror
   int* flags = nullptr;          // device: [0] non-finite input
@@ -74,9 +75,10 @@ struct lgt_ctx {
 
   size_t half_elems() const { return (size_t)12 * vh; }
   size_t full_elems() const { return (size_t)24 * vh; }
-  lgt::Reduce red() const { return lgt::Reduce{partials, ticket, result, lgt::reduce_capacity(vh)}; }
+  lgt::Reduce red() const { return lgt::Reduce{partials, result, lgt::reduce_capacity(vh)}; }
 
   double2* f64(int i);   // full FP64 spinor scratch i (allocated on demand)
+  double2* g64(int i);   // packed FP64 gauge-type scratch i (allocated on demand)
   float2* h32(int i);    // half FP32 spinor scratch i
   void ensure_u32();
   void ensure_p64();
@@ -87,6 +89,13 @@ struct lgt_ctx {
   double action_fermion(const double2* phi, const double2* X, const double2* Y);
   void sync();
   void read_results(int n);
+
+  // stout smearing (smear.hip): U0, G packed FP64
+  void smear(const double2* U0, int nlevels, double rho, double2* dst);
+  void stout_backprop(const double2* U0, int nlevels, double rho, double2* G);
+  lgt::SolveStats smeared_force(const double2* U0, const double2* phi, double beta, double rho, int nlevels,
+                                const lgt::SolverOpts& o, int mode, double dt, void* out, int layout,
+                                double* S_F);
 
   double kappa = 0.0;  // hopping parameter of the current solve
  private:

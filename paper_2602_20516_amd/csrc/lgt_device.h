@@ -232,10 +232,13 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic reduction: wave shuffles, LDS across the block's waves, one
-// partial per block, and the last block to arrive (integer ticket) sums the
-// partials in a fixed order.  No floating-point atomics, so every run gives
-// the same bits.
+// Deterministic reduction in two launches: each block reduces its values
+// (wave shuffles, then LDS across the block's waves, fixed order) and writes
+// one partial per block with a plain store; a later launch -- a one-block
+// finalize kernel, or block 0 of the next kernel -- sums the partials in a
+// fixed order.  Kernel boundaries provide the visibility, so no block
+// executes an atomic or a device-scope fence, and every run gives the same
+// bits.
 // ---------------------------------------------------------------------------
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -253,35 +256,28 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;  // valid in thread 0
 }
 
-// Reduce NV values per thread.  Block partials go to partials[blk*NV + k];
-// returns true in the whole last block, whose thread 0 then holds the totals
-// in out[k].
+// Write this block's sums of NV values to partials[blk*NV + k].
 template <int NT, int NV>
-__device__ __forceinline__ bool grid_sum(const double (&v)[NV], double* partials, unsigned* ticket,
-                                         int blk, int nblk, double (&out)[NV]) {
+__device__ __forceinline__ void block_partials(const double (&v)[NV], double* partials, int blk) {
   __shared__ double sh[NT / 64];
-  __shared__ bool last;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double t = block_sum<NT>(v[k], sh);
-    if (threadIdx.x == 0)
-      __hip_atomic_store(partials + (size_t)blk * NV + k, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double t = block_sum<NT>(v[k], sh);
+    if (threadIdx.x == 0) partials[(size_t)blk * NV + k] = t;
   }
-  if (threadIdx.x == 0) {
-    unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == (unsigned)(nblk - 1));
-  }
-  __syncthreads();
-  if (!last) return false;
+}
+
+// Sum the partials of nblk blocks (written by an earlier launch) in a fixed
+// order; the result is valid in thread 0.  All NT threads must call it.
+template <int NT, int NV>
+__device__ __forceinline__ void sum_partials(const double* partials, int nblk, double (&out)[NV]) {
+  __shared__ double sh[NT / 64];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += NT)
-      s += __hip_atomic_load(partials + (size_t)i * NV + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = threadIdx.x; i < nblk; i += NT) s += partials[(size_t)i * NV + k];
     out[k] = block_sum<NT>(s, sh);
   }
-  if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return true;
 }
 
 }  // namespace lgt

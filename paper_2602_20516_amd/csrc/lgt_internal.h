@@ -45,11 +45,22 @@ struct HopIn {
 
 // Workspace scalars used by reductions.
 struct Reduce {
-  double* partials;   // capacity * 4 doubles
-  unsigned* ticket;   // one counter, reset by the last block
+  double* partials;   // capacity * 4 doubles: one slot per block of the reducing launch
   double* result;     // small array of results read by the host
   int capacity;       // largest grid a reduction kernel may use
 };
+
+// What the one-block finalize kernel does with the summed partials.
+enum FinalizeMode {
+  kFinResult1 = 0,   // result[slot] = sum (1 value per block)
+  kFinResult2 = 1,   // result[slot], result[slot+1] = sums (2 values per block)
+  kFinCgInit = 2,    // start a CG: rr = |b|^2, rr_stop = tol^2 |b|^2, ...
+  kFinCgStep = 3,    // end of a CG iteration: rr, beta, iteration count, convergence
+};
+hipError_t launch_finalize(int mode, int nblk, Reduce red, SolverState* st, int slot, double tol, int max_iter,
+                           hipStream_t s);
+// number of blocks of a hop launch (p_out >= 0: one parity, -1: both)
+int hop_blocks(const Geom& g, int p_out);
 
 // Reduction capacity needed for a lattice with vh sites per parity: the
 // largest reducing grid is the both-parity hop (2 * ceil(vh/64) blocks).
@@ -69,15 +80,17 @@ hipError_t launch_unpack(const Geom& g, int nc, const double2* packed, double2* 
 
 // Hop variants (kernels_hop.hip).  p_out in {0,1}: one parity; -1: both.
 // out = self + coef * H in   (self may be null)
+// guard: skip once the solve has finished; pap_partials: block 0 also forms
+// pap and alpha from the previous launch's partials (see EpiAxpy::tail)
 template <typename R, bool DAG>
 hipError_t launch_hop_axpy(const Geom& g, int p_out, HopIn<R> hin, R2<R>* out_even, R2<R>* out_odd,
                            const R2<R>* self_even, const R2<R>* self_odd, double coef, hipStream_t s,
-                           const SolverState* guard = nullptr);
-// Schur step of CG: w = x + coef * H in on parity 1, pap = |w|^2, alpha = rr / pap
+                           SolverState* guard = nullptr, const double* pap_partials = nullptr);
+// Schur step of CG: w = x + coef * H in on parity 1, block partials of |w|^2
 template <typename R, bool DAG>
 hipError_t launch_hop_schur_norm(const Geom& g, HopIn<R> hin, R2<R>* w, const R2<R>* x, double coef,
                                  SolverState* st, Reduce red, hipStream_t s);
-// Schur dagger step fused with the CG update:
+// Schur dagger step fused with the CG update, then the finalize launch:
 // q = w + coef * H in;  x += alpha p;  r -= alpha q;  rr = |r|^2; beta, convergence
 template <typename R, bool DAG>
 hipError_t launch_hop_schur_cg(const Geom& g, HopIn<R> hin, const R2<R>* w, R2<R>* x, R2<R>* r,
@@ -103,12 +116,13 @@ hipError_t launch_axpy64(int n, double a, const double2* x, double2* y, hipStrea
 hipError_t launch_copy64(int n, const double2* x, double2* y, hipStream_t s);
 hipError_t launch_xmy64(int n, const double2* x, double2* y, hipStream_t s);             // y = x - y
 hipError_t launch_zero64(int n, double2* y, hipStream_t s);
+hipError_t launch_zero32(int n, float2* y, hipStream_t s);
 hipError_t launch_convert_64_32(int n, const double2* x, float2* y, hipStream_t s);
 // mixed precision helpers
-hipError_t launch_mixed_update(int n, float2* xs, double2* x, hipStream_t s);  // x += xs; xs = 0
-template <typename R>
-hipError_t launch_cg_reliable(int n, const double2* r64, R2<R>* r, SolverState* st, Reduce red,
-                              hipStream_t s);
+hipError_t launch_mixed_update(int n, float2* xs, double2* x, double scale, hipStream_t s);  // x += scale xs; xs = 0
+// reliable update of the FP32 recursion: r = (float)(sigma r64); p = r (restart) or p *= pscale
+hipError_t launch_rescale_residual(int n, const double2* r64, double sigma, float2* r, float2* p, int restart,
+                                   double pscale, hipStream_t s);
 
 // Forces / gauge kernels (kernels_force.hip).  Gauge-type outputs: layout
 // kCanonical -> [V][4][3][3] complex128, kPacked -> [2][4][9][vh].
@@ -126,5 +140,14 @@ hipError_t launch_kinetic(const Geom& g, const double2* P, int layout, Reduce re
 // U <- reunit(exp(dt P) U), both in `layout`; U32 (packed FP32 copy) refreshed if non-null
 hipError_t launch_link_update(const Geom& g, double2* U, const double2* P, double dt, int layout,
                               float2* U32, hipStream_t s);
+
+// Stout smearing (kernels_stout.hip), packed FP64 gauge fields.
+hipError_t launch_stout_fwd(const Geom& g, const double2* U, double2* Uo, double rho, hipStream_t s);
+// Adjoint of one level at input links U: Go = gradient at U given Gp at the output.
+hipError_t launch_stout_adjoint(const Geom& g, const double2* U, const double2* Gp, double rho, double2* Lam,
+                                double2* Gpart, double2* Go, hipStream_t s);
+// mode 0: out += F, 1: out += G, 2: out -= dt F, with F = -1/2 P[U G^dag]
+hipError_t launch_grad_to_force(const Geom& g, const double2* U, const double2* G, int mode, double dt, void* out,
+                                int layout, hipStream_t s);
 
 }  // namespace lgt

@@ -79,7 +79,7 @@ void lgt_ctx::dslash_full(const double2* in, double2* out, double k, bool dag) {
 
 template <typename R, bool DAG>
 static void hop(const Geom& g, int p_out, const R2<R>* gauge, const R2<R>* in, R2<R>* out, const R2<R>* self,
-                double coef, hipStream_t s, const SolverState* guard = nullptr) {
+                double coef, hipStream_t s, SolverState* guard = nullptr) {
   HopIn<R> hin{gauge, in, in};
   LGT_HIP((launch_hop_axpy<R, DAG>(g, p_out, hin, out, out, self, self, coef, s, guard)));
 }
@@ -120,8 +120,8 @@ static void cg_iteration(const Geom& g, const R2<R>* gauge, double kappa, R2<R>*
   LGT_HIP((launch_hop_axpy<R, DAG>(g, 0, h1, t, t, nullptr, nullptr, 1.0, s, st)));
   HopIn<R> h2{gauge, t, t};
   LGT_HIP((launch_hop_schur_norm<R, DAG>(g, h2, w, p, k2, st, red, s)));
-  HopIn<R> h3{gauge, w, w};
-  LGT_HIP((launch_hop_axpy<R, !DAG>(g, 0, h3, t, t, nullptr, nullptr, 1.0, s, st)));
+  HopIn<R> h3{gauge, w, w};  // block 0 also forms alpha from the |w|^2 partials
+  LGT_HIP((launch_hop_axpy<R, !DAG>(g, 0, h3, t, t, nullptr, nullptr, 1.0, s, st, red.partials)));
   HopIn<R> h4{gauge, t, t};
   LGT_HIP((launch_hop_schur_cg<R, !DAG>(g, h4, w, x, r, p, k2, st, red, s)));
   LGT_HIP((launch_cg_xpay<R>(n, r, p, st, s)));
@@ -157,6 +157,13 @@ int lgt_ctx::cg_normal64(bool dag, double2* z, const double2* rhs, double tol, i
 }
 
 // Mixed-precision CG with reliable updates.  z, rhs: FP64 odd halves.
+// The FP32 recursion always works on the current FP64 residual scaled to
+// unit norm (sigma = 1/||r||), so its values stay well inside the FP32 range
+// whatever the absolute size of the system (defect-correction passes solve
+// for residuals many orders below ||phi||).  At every reliable update the
+// FP32 solution, in units of 1/sigma, is folded into the FP64 one, the FP64
+// residual is recomputed, and the search direction is rescaled to the new
+// units (or restarted when the recursion had stopped).
 int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double tol, int max_iter, double delta,
                              SolveStats& stt) {
   const int n = (int)half_elems();
@@ -168,22 +175,29 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
   float2* ps = h32(4);
   double2* r64 = f64(kW2) + half_elems();
   LGT_HIP(launch_zero64(n, z, stream));
-  LGT_HIP(launch_convert_64_32(n, rhs, ts, stream));
-  LGT_HIP(launch_cg_init<float>(n, ts, rs, ps, xs, state, red(), tol, max_iter, stream));
-  // the stopping threshold refers to the FP64 right-hand side
   LGT_HIP(launch_norm_dot(n, rhs, nullptr, red(), 0, stream));
-  read_results(1);
+  read_results(2);
   const double bb = host_result[0];
-  {
-    SolverState s;
-    LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
-    sync();
-    s = *host_state;
-    s.rr_stop = tol * tol * bb;
-    if (s.done == kDoneConverged && bb > 0.0) s.done = kDoneRunning;
+  if (!std::isfinite(bb)) return kDoneBreakdown;
+  if (bb == 0.0) return kDoneConverged;
+  const double rr_target = tol * tol * bb;
+  double sigma = 1.0 / std::sqrt(bb);
+  LGT_HIP(launch_zero32(n, xs, stream));
+  LGT_HIP(launch_rescale_residual(n, rhs, sigma, rs, ps, 1, 1.0, stream));
+  SolverState s{};
+  auto write_state = [&](int iter) {
+    s = SolverState{};
+    s.rr = 1.0;
+    s.rr0 = 1.0;
+    s.rr_max = 1.0;
+    s.rr_stop = rr_target * sigma * sigma;
+    s.iter = iter;
+    s.max_iter = max_iter;
+    s.done = kDoneRunning;
     *host_state = s;
     LGT_HIP(hipMemcpyAsync(state, host_state, sizeof(SolverState), hipMemcpyHostToDevice, stream));
-  }
+  };
+  write_state(0);
   const double d2 = delta * delta;
   int it_prev = 0;
   double rr_prev = 0.0;
@@ -195,22 +209,36 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
     }
     LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
     sync();
-    SolverState s = *host_state;
-    const bool trigger = s.done != kDoneRunning || s.rr <= d2 * s.rr_max;
-    if (trigger && s.done != kDoneBreakdown) {
-      // fold the FP32 solution into FP64 and recompute the residual in FP64
-      LGT_HIP(launch_mixed_update(n, xs, z, stream));
-      apply_mhat_dag_mhat64(dag, z, r64);             // r64 = A z
-      LGT_HIP(launch_xmy64(n, rhs, r64, stream));     // r64 = rhs - A z
-      LGT_HIP(launch_cg_reliable<float>(n, r64, rs, state, red(), stream));
-      stt.reliable += 1;
-      LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
-      sync();
-      s = *host_state;
-    }
-    if (s.done != kDoneRunning) {
+    s = *host_state;
+    if (s.done == kDoneMaxIter) {
+      LGT_HIP(launch_mixed_update(n, xs, z, 1.0 / sigma, stream));
       stt.iters += s.iter;
-      return s.done;
+      return kDoneMaxIter;
+    }
+    if (s.done != kDoneRunning || s.rr <= d2 * s.rr_max) {
+      // the recursion stopped (converged in FP32, or broke down in FP32):
+      // its last direction update did not happen, so restart the direction
+      const int restart = s.done != kDoneRunning ? 1 : 0;
+      LGT_HIP(launch_mixed_update(n, xs, z, 1.0 / sigma, stream));
+      apply_mhat_dag_mhat64(dag, z, r64);          // r64 = A z
+      LGT_HIP(launch_xmy64(n, rhs, r64, stream));  // r64 = rhs - A z
+      LGT_HIP(launch_norm_dot(n, r64, nullptr, red(), 0, stream));
+      read_results(2);
+      const double rr64 = host_result[0];
+      stt.reliable += 1;
+      if (!std::isfinite(rr64)) return kDoneBreakdown;
+      if (rr64 <= rr_target) {
+        stt.iters += s.iter;
+        return kDoneConverged;
+      }
+      const double sigma_new = 1.0 / std::sqrt(rr64);
+      LGT_HIP(launch_rescale_residual(n, r64, sigma_new, rs, ps, restart, sigma_new / sigma, stream));
+      sigma = sigma_new;
+      write_state(s.iter);
+      it_prev = 0;
+      rr_prev = 0.0;
+      chunk = 16;
+      continue;
     }
     chunk = next_chunk(s.iter, s.rr, s.rr_stop, it_prev, rr_prev);
     chunk = std::min(chunk, 64);
