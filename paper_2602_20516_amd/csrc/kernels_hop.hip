@@ -15,6 +15,8 @@
 // component w of the 64 output sites for the epilogue, so every global load
 // and store is a unit-stride 64-lane access in the [12][vh] SoA layout.
 // Blocks are numbered XCD-contiguously (see xcd_block).
+#include <cstdlib>
+
 #include "lgt_internal.h"
 
 namespace lgt {
@@ -149,10 +151,17 @@ struct EpiAxpy {  // out = self + coef * acc
       st<R>(out[p] + o, v);
     }
   }
+  __device__ void apply1(int p, int cb, int k, C<R> a, double&) const {
+    const size_t o = (size_t)k * vh + cb;
+    C<R> v = coef * a;
+    if (self[p]) v += ld<R>(self[p] + o);
+    st<R>(out[p] + o, v);
+  }
+  template <int NT>
   __device__ void tail() const {
     if (!pap_partials || blockIdx.x != 0) return;
     double tot[1];
-    sum_partials<256, 1>(pap_partials, pap_nblk, tot);
+    sum_partials<NT, 1>(pap_partials, pap_nblk, tot);
     if (threadIdx.x == 0) {
       const double pap = tot[0];
       guard->pap = pap;
@@ -184,6 +193,13 @@ struct EpiSchurNorm {  // w = x + coef * acc (odd sites), block partials of |w|^
       red += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
     }
   }
+  __device__ void apply1(int, int cb, int k, C<R> a, double& red) const {
+    const size_t o = (size_t)k * vh + cb;
+    C<R> v = ld<R>(x + o) + coef * a;
+    st<R>(w + o, v);
+    red += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+  }
+  template <int NT>
   __device__ void tail() const {}
 };
 
@@ -212,6 +228,17 @@ struct EpiSchurCG {  // q = w + coef * acc; x += alpha p; r -= alpha q; block pa
       red += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
     }
   }
+  __device__ void apply1(int, int cb, int k, C<R> a, double& red) const {
+    const R alpha = R(state->alpha);
+    const size_t o = (size_t)k * vh + cb;
+    const C<R> q = ld<R>(w + o) + coef * a;
+    C<R> xv = ld<R>(x + o) + alpha * ld<R>(p + o);
+    C<R> rv = ld<R>(r + o) - alpha * q;
+    st<R>(x + o, xv);
+    st<R>(r + o, rv);
+    red += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+  }
+  template <int NT>
   __device__ void tail() const {}
 };
 
@@ -232,6 +259,13 @@ struct EpiResidual {  // r = phi - (self + coef * acc) over both parities, block
       red += norm2(v);
     }
   }
+  __device__ void apply1(int p, int cb, int k, C<double> a, double& red) const {
+    const size_t o = (size_t)k * vh + cb;
+    C<double> v = ld<double>(phi[p] + o) - (ld<double>(self[p] + o) + coef * a);
+    st<double>(r[p] + o, v);
+    red += norm2(v);
+  }
+  template <int NT>
   __device__ void tail() const {}
 };
 
@@ -289,10 +323,155 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, HopIn
     double v[1] = {red};
     block_partials<256, 1>(v, partials, lb);
   }
-  epi.tail();
+  epi.template tail<256>();
+}
+
+// ---------------------------------------------------------------------------
+// Eight-wave variant: wave w = (mu = w/2, a = w%2) computes, for 64 sites,
+// both hops along mu for projected spin component a only.  In the chiral
+// basis B_mu has one non-zero per row, (B_mu d)_a = f_{mu,a} d_{b(a)} with
+// b = swap (mu = 0, 1) or identity (mu = 2, 3) and f in {+-1, +-i}, so a
+// thread needs half of each neighbour spinor, and its W_a = U h_a feeds
+// exactly two output spin components: up_a and dn_{b(a)} (with factor
+// S conj(f)).  Twice as many threads per site as k_hop, same LDS footprint.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ C<R> phase_mul(int f, C<R> v) {  // f: 0 -> 1, 1 -> -1, 2 -> i, 3 -> -i
+  return f == 0 ? v : (f == 1 ? -v : (f == 2 ? itimes(v) : -itimes(v)));
+}
+// f_{mu,a} as a phase code and b(a)
+__device__ __forceinline__ void bmap(int mu, int a, int& f, int& b) {
+  // mu 0: (Bd) = (-i d1, -i d0); mu 1: (-d1, d0); mu 2: (-i d0, i d1); mu 3: (d0, d1)
+  const int tab_f[4][2] = {{3, 3}, {1, 0}, {3, 2}, {0, 0}};
+  f = tab_f[mu][a];
+  b = mu < 2 ? 1 - a : a;
+}
+__device__ __forceinline__ int conj_phase(int f) { return f < 2 ? f : (f == 2 ? 3 : 2); }
+
+template <typename R, int MU, bool DAG>
+__device__ __forceinline__ void hop_dir_half(const Geom& g, const R2<R>* __restrict__ gauge,
+                                             const R2<R>* __restrict__ in, int p, int cb, const int c[4], int a,
+                                             C<R>* up, C<R>* dn) {
+  constexpr int SF = DAG ? +1 : -1;
+  const int vh = g.vh;
+  int f, b;
+  bmap(MU, a, f, b);
+  const int fr = conj_phase(f);  // reconstruction factor conj(f)
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {
+    const int S = dir == 0 ? SF : -SF;
+    const int n = cb_shift(g, c, MU, dir == 0 ? +1 : -1);
+    C<R> h[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const C<R> u = ld<R>(in + (size_t)(3 * a + i) * vh + n);
+      const C<R> d = ld<R>(in + (size_t)(6 + 3 * b + i) * vh + n);
+      const C<R> bd = phase_mul<R>(f, d);
+      h[i] = S > 0 ? u + bd : u - bd;
+    }
+    const M3<R> U = load_m3<R>(gptr<R>(gauge, g, dir == 0 ? p : 1 - p, MU), vh, dir == 0 ? cb : n);
+    C<R> w[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      C<R> sacc;
+      if (dir == 0) {
+        sacc = U.m[3 * i] * h[0];
+        sacc += U.m[3 * i + 1] * h[1];
+        sacc += U.m[3 * i + 2] * h[2];
+      } else {
+        sacc = cjmul(U.m[i], h[0]);
+        sacc += cjmul(U.m[3 + i], h[1]);
+        sacc += cjmul(U.m[6 + i], h[2]);
+      }
+      w[i] = sacc;
+    }
+    const bool edge = MU == 3 && (dir == 0 ? c[3] == g.L[3] - 1 : c[3] == 0);
+    const R sg = edge ? R(g.bc) : R(1);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const C<R> wv = sg * w[i];
+      up[i] += wv;
+      const C<R> t = phase_mul<R>(fr, wv);
+      if (S > 0) dn[i] += t;
+      else dn[i] -= t;
+    }
+  }
+}
+
+template <typename R, bool DAG, typename Epi>
+__global__ __launch_bounds__(512) void k_hop8(Geom g, int nbp, int p_fixed, HopIn<R> hin, Epi epi,
+                                              double* partials) {
+  if (epi.skip()) return;
+  __shared__ R2<R> lds[8][6][64];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int p = p_fixed >= 0 ? p_fixed : lb / nbp;
+  const int blk = p_fixed >= 0 ? lb : lb % nbp;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int mu = w >> 1, a = w & 1;
+  const int cb = blk * 64 + lane;
+  const bool active = cb < g.vh;
+  C<R> up[3], dn[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) up[i] = dn[i] = czero<R>();
+  if (active) {
+    int c[4];
+    cb_coords(g, p, cb, c);
+    const R2<R>* in = p ? hin.in_even : hin.in_odd;
+    switch (mu) {
+      case 0: hop_dir_half<R, 0, DAG>(g, hin.gauge, in, p, cb, c, a, up, dn); break;
+      case 1: hop_dir_half<R, 1, DAG>(g, hin.gauge, in, p, cb, c, a, up, dn); break;
+      case 2: hop_dir_half<R, 2, DAG>(g, hin.gauge, in, p, cb, c, a, up, dn); break;
+      default: hop_dir_half<R, 3, DAG>(g, hin.gauge, in, p, cb, c, a, up, dn); break;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    R2<R> v;
+    v.x = up[i].re;
+    v.y = up[i].im;
+    lds[w][i][lane] = v;
+    v.x = dn[i].re;
+    v.y = dn[i].im;
+    lds[w][3 + i][lane] = v;
+  }
+  __syncthreads();
+  double red = 0.0;
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk) {
+    const int k = w + 8 * kk;  // output component 3*spin + colour
+    if (k >= 12) break;
+    const int sp = k / 3, i = k % 3;
+    R re = R(0), im = R(0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      // up spin sp comes from wave (m, a = sp); dn spin c = sp-2 from (m, a = b_m^{-1}(c))
+      const int src = sp < 2 ? 2 * m + sp : 2 * m + (m < 2 ? 1 - (sp - 2) : sp - 2);
+      const R2<R> v = lds[src][sp < 2 ? i : 3 + i][lane];
+      re += v.x;
+      im += v.y;
+    }
+    if (active) epi.apply1(p, cb, k, cmk<R>(re, im), red);
+  }
+  if constexpr (Epi::kReduce) {
+    double v[1] = {red};
+    block_partials<512, 1>(v, partials, lb);
+  }
+  epi.template tail<512>();
 }
 
 static inline int nblk_parity(const Geom& g) { return (g.vh + 63) / 64; }
+
+// Hop decomposition: 4 waves (one per direction, the default: faster on
+// MI355X at 16^4 and above) or 8 waves (direction x projected spin
+// component) per 64-site block; LGT_HOP_WAVES=8 selects the latter.
+static int hop_waves() {
+  static int w = [] {
+    const char* e = getenv("LGT_HOP_WAVES");
+    return (e && atoi(e) == 8) ? 8 : 4;
+  }();
+  return w;
+}
 
 template <typename R, bool DAG, typename Epi>
 static hipError_t launch(const Geom& g, int p_out, const HopIn<R>& hin, const Epi& epi, double* partials,
@@ -300,7 +479,10 @@ static hipError_t launch(const Geom& g, int p_out, const HopIn<R>& hin, const Ep
   const int nbp = nblk_parity(g);
   const int nb = p_out >= 0 ? nbp : 2 * nbp;
   if (Epi::kReduce && nb > capacity) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_hop<R, DAG, Epi>), dim3(nb), dim3(256), 0, s, g, nbp, p_out, hin, epi, partials);
+  if (hop_waves() == 8)
+    hipLaunchKernelGGL((k_hop8<R, DAG, Epi>), dim3(nb), dim3(512), 0, s, g, nbp, p_out, hin, epi, partials);
+  else
+    hipLaunchKernelGGL((k_hop<R, DAG, Epi>), dim3(nb), dim3(256), 0, s, g, nbp, p_out, hin, epi, partials);
   return hipGetLastError();
 }
 
