@@ -118,7 +118,9 @@ typedef struct lgt_solver_params {
   double tol;            /* stop when ||phi - D^dag D X|| / ||phi|| <= tol (FP64, recomputed) */
   int32_t max_iter;      /* cap on inner CG iterations per solve (<= 0: 20000) */
   double reliable_delta; /* mixed precision: FP64 residual update when the inner
-                            residual drops by this factor (<= 0: 0.1) */
+                            residual norm drops by this factor; the FP32
+                            recursion stays accurate over a drop of 1e-2
+                            (outside (0, 1): 0.01) */
 } lgt_solver_params;
 
 typedef struct lgt_solver_stats {
@@ -252,6 +254,24 @@ LGT_API lgt_status lgt_md_step_smeared(lgt_ctx* ctx, void* U, void* P, const voi
                                        double kappa, double rho, int32_t nlevels, double dt, int32_t nsteps,
                                        const lgt_solver_params* params, double* dH_or_null,
                                        lgt_solver_stats* stats);
+
+/* One right-hand side of a batched solve. */
+typedef struct lgt_batch_item {
+  const void* phi; /* spinor (input) */
+  void* X;         /* spinor (output): (D^dag D)^-1 phi at this item's kappa */
+  void* Y_or_null; /* spinor (output) D X, or NULL */
+  double kappa;    /* hopping parameter of this item */
+} lgt_batch_item;
+
+/* Batched solve of n (1..16) pseudofermion fields on one lattice, each with
+ * its own kappa: every item gets the result lgt_cg_solve would give it (same
+ * method and stopping rule), but all right-hand sides run through the same
+ * launches, so each link load serves all of them and each keeps its own CG
+ * scalars, stopping once converged.  stats_per_item (may be NULL) receives n
+ * entries; ms is the time of the whole batch.  NOT_CONVERGED if any item
+ * missed the tolerance (all outputs are written). */
+LGT_API lgt_status lgt_cg_solve_batch(lgt_ctx* ctx, const void* U, int32_t n, const lgt_batch_item* items,
+                                      const lgt_solver_params* params, lgt_solver_stats* stats_per_item);
 
 /* Measurement entry point: times nrep back-to-back launches of the
  * even/odd hop kernel H_eo (the dominant kernel of the CG; FP64 for

@@ -38,6 +38,11 @@ class SolverParams(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("reliable_delta", ctypes.c_double)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("phi", ctypes.c_void_p), ("X", ctypes.c_void_p), ("Y_or_null", ctypes.c_void_p),
+                ("kappa", ctypes.c_double)]
+
+
 class SolverStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
                 ("true_rel_residual", ctypes.c_double), ("ms", ctypes.c_double)]
@@ -73,6 +78,8 @@ PROTOTYPES = {
     "lgt_md_step": (_st, [_vp, _vp, _vp, _vp, _d, _d, _d, _i, ctypes.POINTER(SolverParams),
                           ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
     "lgt_hop_benchmark": (_st, [_vp, _vp, _vp, _i, _i, ctypes.POINTER(_d)]),
+    "lgt_cg_solve_batch": (_st, [_vp, _vp, _i, ctypes.POINTER(BatchItem), ctypes.POINTER(SolverParams),
+                                 ctypes.POINTER(SolverStats)]),
     "lgt_stout_smear": (_st, [_vp, _vp, _vp, _d, _i]),
     "lgt_stout_backprop": (_st, [_vp, _vp, _vp, _d, _i, _vp]),
     "lgt_smeared_force": (_st, [_vp, _vp, _vp, _d, _d, _d, _i, ctypes.POINTER(SolverParams), _i, _d, _vp,

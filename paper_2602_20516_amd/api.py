@@ -43,7 +43,7 @@ class Params:
     precision: str = "fp64"
     tol: float = 1e-10
     max_iter: int = 20000
-    reliable_delta: float = 0.1
+    reliable_delta: float = 0.01
     even_odd: int = 1
 
     def to_c(self) -> SolverParams:
@@ -141,6 +141,30 @@ class Lattice:
                                    float(kappa), ctypes.byref(cp), ctypes.byref(stats))
         _check(self.lib, self.ctx, st, stats)
         return X, Y, stats.as_dict()
+
+    def cg_solve_batch(self, U, phis, kappas, params: Optional[Params] = None, want_y: bool = True):
+        """lgt_cg_solve_batch: one solve per (phi_n, kappa_n) through shared launches.
+
+        Returns (Xs, Ys, stats) with one entry per right-hand side.
+        """
+        params = params or Params()
+        n = len(phis)
+        if len(kappas) != n:
+            raise ValueError("one kappa per right-hand side")
+        Xs = [self.empty_spinor() for _ in range(n)]
+        Ys = [self.empty_spinor() for _ in range(n)] if want_y else [None] * n
+        items = (_lib.BatchItem * n)()
+        for k in range(n):
+            items[k].phi = self._field(phis[k], "spinor", f"phi[{k}]")
+            items[k].X = self._field(Xs[k], "spinor", f"X[{k}]")
+            items[k].Y_or_null = self._field(Ys[k], "spinor", f"Y[{k}]") if want_y else None
+            items[k].kappa = float(kappas[k])
+        stats = (SolverStats * n)()
+        cp = params.to_c()
+        self._bind_stream()
+        st = self.lib.lgt_cg_solve_batch(self.ctx, self._field(U, "gauge", "U"), n, items, ctypes.byref(cp), stats)
+        _check(self.lib, self.ctx, st, stats[0] if n else None)
+        return Xs, Ys, [stats[k].as_dict() for k in range(n)]
 
     def action(self, U, phi, beta: float, kappa: float, params: Optional[Params] = None,
                gauge: bool = True, fermion: bool = True):
@@ -295,6 +319,10 @@ def lgt_dslash(lat: Lattice, U, psi, kappa, dagger=False, out=None):
 
 def lgt_cg_solve(lat: Lattice, U, phi, kappa, params=None, want_y=True):
     return lat.cg_solve(U, phi, kappa, params, want_y)
+
+
+def lgt_cg_solve_batch(lat: Lattice, U, phis, kappas, params=None, want_y=True):
+    return lat.cg_solve_batch(U, phis, kappas, params, want_y)
 
 
 def lgt_action(lat: Lattice, U, phi, beta, kappa, params=None, gauge=True, fermion=True):

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "lgt_ctx.h"
 
@@ -53,7 +54,7 @@ SolverOpts parse(const lgt_solver_params* p) {
   o.precision = p->precision;
   o.tol = p->tol;
   o.max_iter = p->max_iter > 0 ? p->max_iter : 20000;
-  o.delta = p->reliable_delta > 0.0 && p->reliable_delta < 1.0 ? p->reliable_delta : 0.1;
+  o.delta = p->reliable_delta > 0.0 && p->reliable_delta < 1.0 ? p->reliable_delta : 0.01;
   return o;
 }
 
@@ -157,6 +158,9 @@ lgt_status lgt_create(const lgt_geom* geom, void* hip_stream, lgt_ctx** out) {
     LGT_HIP(hipHostMalloc(&c->host_result, 64 * sizeof(double), hipHostMallocDefault));
     LGT_HIP(hipHostMalloc(&c->host_flags, 16 * sizeof(int), hipHostMallocDefault));
     LGT_HIP(hipHostMalloc(&c->host_state, sizeof(SolverState), hipHostMallocDefault));
+    LGT_HIP(hipHostMalloc(&c->mbox_host, sizeof(Mailbox), hipHostMallocCoherent | hipHostMallocMapped));
+    LGT_HIP(hipHostGetDevicePointer((void**)&c->mbox_dev, c->mbox_host, 0));
+    c->mbox_host->word = 0;
     LGT_HIP(hipMemsetAsync(c->flags, 0, 16 * sizeof(int), c->stream));
     LGT_HIP(hipMemsetAsync(c->state, 0, sizeof(SolverState), c->stream));
     LGT_HIP(hipEventCreate(&c->ev0));
@@ -175,6 +179,7 @@ lgt_status lgt_create(const lgt_geom* geom, void* hip_stream, lgt_ctx** out) {
 lgt_status lgt_destroy(lgt_ctx* c) {
   if (!c) return LGT_OK;
   if (c->stream || c->U64) (void)hipStreamSynchronize(c->stream);
+  lgt_ctx_free_batch(c);
   for (auto* p : c->full64) (void)hipFree(p);
   for (auto* p : c->half32) (void)hipFree(p);
   (void)hipFree(c->U64);
@@ -187,6 +192,7 @@ lgt_status lgt_destroy(lgt_ctx* c) {
   if (c->host_result) (void)hipHostFree(c->host_result);
   if (c->host_flags) (void)hipHostFree(c->host_flags);
   if (c->host_state) (void)hipHostFree(c->host_state);
+  if (c->mbox_host) (void)hipHostFree(c->mbox_host);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;
@@ -477,6 +483,42 @@ lgt_status lgt_smeared_force(lgt_ctx* c, const void* U, const void* phi, double 
   });
   if (s == LGT_OK && nc) {
     c->err = "solver did not reach the tolerance";
+    return LGT_ERR_NOT_CONVERGED;
+  }
+  return s;
+}
+
+lgt_status lgt_cg_solve_batch(lgt_ctx* c, const void* U, int32_t n, const lgt_batch_item* items,
+                              const lgt_solver_params* params, lgt_solver_stats* stats) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  bool nc = false;
+  lgt_status s = guarded(c, [&] {
+    require(U && items, "null pointer");
+    require(n >= 1 && n <= 16, "a batch holds 1 to 16 right-hand sides");
+    std::vector<double> kap(n);
+    std::vector<const void*> phis(n);
+    std::vector<void*> xs(n), ys(n);
+    for (int k = 0; k < n; ++k) {
+      require(items[k].phi && items[k].X, "null field pointer in a batch item");
+      require(std::isfinite(items[k].kappa), "kappa must be finite");
+      kap[k] = items[k].kappa;
+      phis[k] = items[k].phi;
+      xs[k] = items[k].X;
+      ys[k] = items[k].Y_or_null;
+    }
+    const SolverOpts o = parse(params);
+    Timer tm(c);
+    pack_links(c, U, o.precision != LGT_FP64);
+    check_nonfinite(c, "U");
+    std::vector<SolveStats> st = c->solve_batch(n, kap.data(), phis.data(), xs.data(), ys.data(), o);
+    const double ms = tm.stop();
+    for (int k = 0; k < n; ++k) {
+      fill_stats(stats ? stats + k : nullptr, st[k], ms);
+      nc = nc || !st[k].converged;
+    }
+  });
+  if (s == LGT_OK && nc) {
+    c->err = "solver did not reach the tolerance for every right-hand side";
     return LGT_ERR_NOT_CONVERGED;
   }
   return s;

@@ -1,0 +1,370 @@
+// Batched solver: nr right-hand sides phi_n on one lattice, each with its own
+// kappa_n, solved together for X_n = (D_n^dag D_n)^-1 phi_n, Y_n = D_n X_n.
+// Same method as the single solve (two even/odd Schur CGNR solves, FP64
+// residual, defect correction), with every launch covering all nr fields:
+// one link load serves all right-hand sides, and each right-hand side has its
+// own CG scalars and stops updating once converged.  Mixed precision: FP32
+// recursion per right-hand side on its residual scaled to unit norm; each
+// recursion stops itself on the device at its reliable-update threshold
+// (as in the single solve), and once half of them have stopped the host
+// updates every right-hand side in FP64.
+#include <algorithm>
+#include <cmath>
+
+#include "lgt_ctx.h"
+#include "lgt_mrhs.h"
+
+using namespace lgt;
+
+namespace {
+enum { bPhi = 0, bX = 1, bY = 2, bRes = 3, bE = 4, bYtmp = 5, bW0 = 6, bW1 = 7, bW2 = 8, bW3 = 9, bW4 = 10,
+       bStage = 11 };
+}  // namespace
+
+struct BatchWork {
+  int nr = 0;
+  std::vector<double2*> f;  // multi-RHS FP64 full fields
+  std::vector<float2*> h;   // multi-RHS FP32 half fields
+  BatchState* st = nullptr;
+  BatchState* hst = nullptr;  // pinned
+  double* partials = nullptr;
+  size_t npart = 0;
+  double* dvec = nullptr;   // device per-RHS arrays: 8 x kMaxRhs doubles
+  double* hvec = nullptr;   // pinned mirror
+  int* dint = nullptr;      // device restart flags
+  int* hint = nullptr;
+};
+
+static void free_batch(BatchWork* w) {
+  if (!w) return;
+  for (auto* p : w->f) (void)hipFree(p);
+  for (auto* p : w->h) (void)hipFree(p);
+  (void)hipFree(w->st);
+  (void)hipFree(w->partials);
+  (void)hipFree(w->dvec);
+  (void)hipFree(w->dint);
+  if (w->hst) (void)hipHostFree(w->hst);
+  if (w->hvec) (void)hipHostFree(w->hvec);
+  if (w->hint) (void)hipHostFree(w->hint);
+  delete w;
+}
+
+void lgt_ctx_free_batch(lgt_ctx* c) {
+  free_batch(c->batch);
+  c->batch = nullptr;
+}
+
+// per-RHS device arrays (slots of kMaxRhs doubles)
+enum { vOne = 0, vKap = 1, vMKap = 2, vMK2 = 3, vSigma = 4, vPscale = 5, vScale = 6 };
+
+static BatchWork* batch_work(lgt_ctx* c, int nr) {
+  if (c->batch && c->batch->nr >= nr) return c->batch;
+  lgt_ctx_free_batch(c);
+  BatchWork* w = new BatchWork();
+  c->batch = w;
+  w->nr = nr;
+  const size_t full = (size_t)24 * c->vh * nr, half = (size_t)12 * c->vh * nr;
+  w->f.assign(12, nullptr);
+  for (auto& p : w->f) {
+    LGT_HIP(hipMalloc(&p, full * sizeof(double2)));
+    LGT_HIP(hipMemsetAsync(p, 0, full * sizeof(double2), c->stream));
+  }
+  w->h.assign(5, nullptr);
+  for (auto& p : w->h) {
+    LGT_HIP(hipMalloc(&p, half * sizeof(float2)));
+    LGT_HIP(hipMemsetAsync(p, 0, half * sizeof(float2), c->stream));
+  }
+  LGT_HIP(hipMalloc(&w->st, sizeof(BatchState)));
+  LGT_HIP(hipHostMalloc(&w->hst, sizeof(BatchState), hipHostMallocDefault));
+  w->npart = (size_t)mrhs_hop_blocks(c->g, nr, -1) * kMaxRhs + 1024 * kMaxRhs;
+  LGT_HIP(hipMalloc(&w->partials, w->npart * sizeof(double)));
+  LGT_HIP(hipMalloc(&w->dvec, 8 * kMaxRhs * sizeof(double)));
+  LGT_HIP(hipHostMalloc(&w->hvec, 8 * kMaxRhs * sizeof(double), hipHostMallocDefault));
+  LGT_HIP(hipMalloc(&w->dint, kMaxRhs * sizeof(int)));
+  LGT_HIP(hipHostMalloc(&w->hint, kMaxRhs * sizeof(int), hipHostMallocDefault));
+  return w;
+}
+
+namespace {
+
+struct BatchSolver {
+  lgt_ctx* c;
+  BatchWork* w;
+  int nr;
+  const SolverOpts& o;
+  std::vector<double> kap;
+  std::vector<SolveStats> st;  // per right-hand side
+
+  Reduce red() const { return Reduce{w->partials, c->result, 0, w->npart, c->mbox_dev}; }
+  size_t halfn() const { return (size_t)12 * c->vh * nr; }
+  double* vec(int slot) const { return w->dvec + slot * kMaxRhs; }
+  double2* F(int i) const { return w->f[i]; }
+
+  void upload_vecs() {
+    LGT_HIP(hipMemcpyAsync(w->dvec, w->hvec, 8 * kMaxRhs * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  }
+  void read_results(int n) {
+    LGT_HIP(hipMemcpyAsync(c->host_result, c->result, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+  }
+  void read_state() {
+    LGT_HIP(hipMemcpyAsync(w->hst, w->st, sizeof(BatchState), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+  }
+  void write_state() {
+    LGT_HIP(hipMemcpyAsync(w->st, w->hst, sizeof(BatchState), hipMemcpyHostToDevice, c->stream));
+  }
+
+  template <typename R, bool DAG>
+  void mhop(int p_out, const R2<R>* gauge, const R2<R>* in, R2<R>* out, const R2<R>* self, const double* coef,
+            BatchState* guard = nullptr, const double* pap = nullptr) {
+    HopIn<R> hin{gauge, in, in};
+    LGT_HIP((launch_mhop_axpy<R, DAG>(c->g, nr, p_out, hin, out, out, self, self, coef, c->stream, guard, pap,
+                                       red())));
+  }
+
+  // out = Mhat^dag Mhat x (FP64), scratch: even half of bW0, odd half of bW4
+  void apply_normal64(bool dag, const double2* x, double2* out) {
+    double2* t = F(bW0);
+    double2* wv = F(bW4) + halfn();
+    if (!dag) {
+      mhop<double, false>(0, c->U64, x, t, nullptr, vec(vOne));
+      mhop<double, false>(1, c->U64, t, wv, x, vec(vMK2));
+      mhop<double, true>(0, c->U64, wv, t, nullptr, vec(vOne));
+      mhop<double, true>(1, c->U64, t, out, wv, vec(vMK2));
+    } else {
+      mhop<double, true>(0, c->U64, x, t, nullptr, vec(vOne));
+      mhop<double, true>(1, c->U64, t, wv, x, vec(vMK2));
+      mhop<double, false>(0, c->U64, wv, t, nullptr, vec(vOne));
+      mhop<double, false>(1, c->U64, t, out, wv, vec(vMK2));
+    }
+  }
+
+  template <typename R, bool DAG>
+  void iteration(const R2<R>* gauge, R2<R>* t, R2<R>* wv, R2<R>* x, R2<R>* r, R2<R>* p) {
+    const size_t n = halfn();
+    mhop<R, DAG>(0, gauge, p, t, nullptr, vec(vOne), w->st);
+    HopIn<R> h2{gauge, t, t};
+    LGT_HIP((launch_mhop_schur_norm<R, DAG>(c->g, nr, h2, wv, p, vec(vMK2), w->st, red(), c->stream)));
+    mhop<R, !DAG>(0, gauge, wv, t, nullptr, vec(vOne), w->st, w->partials);
+    HopIn<R> h4{gauge, t, t};
+    LGT_HIP((launch_mhop_schur_cg<R, !DAG>(c->g, nr, h4, wv, x, r, p, vec(vMK2), w->st, red(), c->stream)));
+    LGT_HIP(launch_mxpay<R>(n, nr, r, p, w->st, c->stream));
+  }
+
+  void cg64(bool dag, double2* z, const double2* rhs, double tol) {
+    const size_t n = halfn();
+    double2* t = F(bW0);
+    double2* r = F(bW2) + n;
+    double2* p = F(bW3) + n;
+    double2* wv = F(bW4) + n;
+    LGT_HIP(launch_mcg_init64(n, nr, rhs, r, p, z, w->st, red(), tol, o.max_iter, c->stream));
+    for (int iter0 = 0;;) {
+      c->drive(iter0, [&] {
+        if (dag) iteration<double, true>(c->U64, t, wv, z, r, p);
+        else iteration<double, false>(c->U64, t, wv, z, r, p);
+      });
+      read_state();
+      if (w->hst->all_done) break;
+      iter0 = w->hst->iter;
+    }
+    for (int k = 0; k < nr; ++k) {
+      st[k].iters += w->hst->conv_iter[k];
+      if (w->hst->done[k] == kDoneBreakdown) throw Error(LGT_ERR_NONFINITE, "batched CG breakdown");
+      if (w->hst->done[k] == kDoneMaxIter) st[k].converged = false;
+    }
+  }
+
+  void cg_mixed(bool dag, double2* z, const double2* rhs, double tol) {
+    const size_t n = halfn();
+    c->ensure_u32();
+    float2* ts = w->h[0];
+    float2* ws = w->h[1];
+    float2* xs = w->h[2];
+    float2* rs = w->h[3];
+    float2* ps = w->h[4];
+    double2* r64 = F(bW2) + n;
+    LGT_HIP(launch_zero64((int)n, z, c->stream));
+    LGT_HIP(launch_zero32((int)n, xs, c->stream));
+    LGT_HIP(launch_mnorm<double>(n, nr, rhs, red(), c->stream));
+    read_results(nr);
+    std::vector<double> target(nr), sigma(nr);
+    std::vector<int> verified(nr, 0), iters(nr, 0);
+    for (int k = 0; k < nr; ++k) {
+      const double bb = c->host_result[k];
+      if (!std::isfinite(bb)) throw Error(LGT_ERR_NONFINITE, "right-hand side holds NaN or Inf");
+      target[k] = tol * tol * bb;
+      sigma[k] = bb > 0.0 ? 1.0 / std::sqrt(bb) : 1.0;
+      verified[k] = bb == 0.0;
+    }
+    BatchState& s = *w->hst;
+    s = BatchState{};
+    s.nr = nr;
+    s.max_iter = o.max_iter;
+    s.delta2 = o.delta * o.delta;
+    for (int k = 0; k < nr; ++k) {
+      s.rr[k] = s.rr_max[k] = 1.0;
+      s.rr_stop[k] = tol * tol;
+      s.done[k] = verified[k] ? kDoneConverged : kDoneRunning;
+      w->hvec[vSigma * kMaxRhs + k] = sigma[k];
+      w->hvec[vPscale * kMaxRhs + k] = 1.0;
+      w->hint[k] = 1;
+    }
+    s.all_done = std::all_of(verified.begin(), verified.end(), [](int v) { return v != 0; });
+    upload_vecs();
+    LGT_HIP(hipMemcpyAsync(w->dint, w->hint, kMaxRhs * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    LGT_HIP(launch_mrescale(n, nr, rhs, vec(vSigma), rs, ps, w->dint, vec(vPscale), c->stream));
+    write_state();
+    while (!s.all_done) {
+      c->drive(s.iter, [&] {
+        if (dag) iteration<float, true>(c->U32, ts, ws, xs, rs, ps);
+        else iteration<float, false>(c->U32, ts, ws, xs, rs, ps);
+      });
+      read_state();
+      // the device asks for the update once half of the unverified right-hand
+      // sides have stopped (a stopped one idles until then)
+      int active = 0, stopped = 0;
+      for (int k = 0; k < nr; ++k) {
+        if (verified[k]) continue;
+        ++active;
+        stopped += s.done[k] != kDoneRunning;
+      }
+      if (!s.all_done && 2 * stopped < active) continue;  // nothing posted for long (see drive)
+      // reliable update for every right-hand side
+      for (int k = 0; k < nr; ++k) w->hvec[vScale * kMaxRhs + k] = 1.0 / sigma[k];
+      upload_vecs();
+      LGT_HIP(launch_mmixed_update(n, nr, xs, z, vec(vScale), c->stream));
+      apply_normal64(dag, z, r64);
+      LGT_HIP(launch_xmy64((int)n, rhs, r64, c->stream));
+      LGT_HIP(launch_mnorm<double>(n, nr, r64, red(), c->stream));
+      read_results(nr);
+      bool all = true;
+      for (int k = 0; k < nr; ++k) {
+        const double rr64 = c->host_result[k];
+        if (!std::isfinite(rr64)) throw Error(LGT_ERR_NONFINITE, "non-finite residual in the batched solve");
+        st[k].reliable += verified[k] ? 0 : 1;
+        if (!verified[k] && rr64 <= target[k]) {
+          verified[k] = 1;
+          iters[k] = s.iter;
+        }
+        if (verified[k]) {
+          s.done[k] = kDoneConverged;
+          w->hint[k] = 0;
+          w->hvec[vPscale * kMaxRhs + k] = 1.0;
+          w->hvec[vSigma * kMaxRhs + k] = sigma[k];
+          continue;
+        }
+        all = false;
+        const double sn = 1.0 / std::sqrt(rr64);
+        w->hint[k] = s.done[k] == kDoneBreakdown ? 1 : 0;  // its last direction update did not happen
+        w->hvec[vPscale * kMaxRhs + k] = sn / sigma[k];
+        w->hvec[vSigma * kMaxRhs + k] = sn;
+        sigma[k] = sn;
+        s.rr[k] = s.rr_max[k] = 1.0;
+        s.rr_stop[k] = target[k] * sn * sn;
+        s.done[k] = s.iter >= o.max_iter ? kDoneMaxIter : kDoneRunning;
+        if (s.done[k] == kDoneMaxIter) {
+          verified[k] = 1;
+          iters[k] = s.iter;
+          st[k].converged = false;
+        }
+      }
+      s.all_done = all || std::all_of(verified.begin(), verified.end(), [](int v) { return v != 0; });
+      s.any_update = 0;
+      if (s.all_done) break;
+      upload_vecs();
+      LGT_HIP(hipMemcpyAsync(w->dint, w->hint, kMaxRhs * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      LGT_HIP(launch_mrescale(n, nr, r64, vec(vSigma), rs, ps, w->dint, vec(vPscale), c->stream));
+      write_state();
+    }
+    for (int k = 0; k < nr; ++k) st[k].iters += iters[k];
+  }
+
+  void solve_M(bool dag, double2* z, const double2* b, double tol) {
+    const size_t h = halfn();
+    const double2* be = b;
+    const double2* bo = b + h;
+    double2* bp = F(bW0) + h;
+    double2* te = F(bW0);
+    double2* rhs = F(bW1) + h;
+    if (dag) {
+      mhop<double, true>(1, c->U64, be, bp, bo, vec(vKap));
+      mhop<double, false>(0, c->U64, bp, te, nullptr, vec(vOne));
+      mhop<double, false>(1, c->U64, te, rhs, bp, vec(vMK2));
+    } else {
+      mhop<double, false>(1, c->U64, be, bp, bo, vec(vKap));
+      mhop<double, true>(0, c->U64, bp, te, nullptr, vec(vOne));
+      mhop<double, true>(1, c->U64, te, rhs, bp, vec(vMK2));
+    }
+    double2* zo = z + h;
+    if (o.precision == LGT_FP64) cg64(dag, zo, rhs, tol);
+    else cg_mixed(dag, zo, rhs, tol);
+    if (dag) mhop<double, true>(0, c->U64, zo, z, be, vec(vKap));
+    else mhop<double, false>(0, c->U64, zo, z, be, vec(vKap));
+  }
+
+  void dslash_full(const double2* in, double2* out, bool dag) {
+    const size_t h = halfn();
+    HopIn<double> hin{c->U64, in, in + h};
+    if (dag)
+      LGT_HIP((launch_mhop_axpy<double, true>(c->g, nr, -1, hin, out, out + h, in, in + h, vec(vMKap), c->stream,
+                                               nullptr, nullptr, red())));
+    else
+      LGT_HIP((launch_mhop_axpy<double, false>(c->g, nr, -1, hin, out, out + h, in, in + h, vec(vMKap), c->stream,
+                                                nullptr, nullptr, red())));
+  }
+
+  void run() {
+    const size_t nfull = 2 * halfn();
+    for (int k = 0; k < kMaxRhs; ++k) {
+      const double kk = k < nr ? kap[k] : 0.0;
+      w->hvec[vOne * kMaxRhs + k] = 1.0;
+      w->hvec[vKap * kMaxRhs + k] = kk;
+      w->hvec[vMKap * kMaxRhs + k] = -kk;
+      w->hvec[vMK2 * kMaxRhs + k] = -kk * kk;
+    }
+    upload_vecs();
+    const double2* phi = F(bPhi);
+    LGT_HIP(launch_mnorm<double>(nfull, nr, phi, red(), c->stream));
+    read_results(nr);
+    std::vector<double> pp(c->host_result, c->host_result + nr);
+    for (double v : pp)
+      if (!std::isfinite(v)) throw Error(LGT_ERR_NONFINITE, "phi holds NaN or Inf");
+    const double tol_in = o.tol * 0.25;
+    solve_M(true, F(bY), phi, tol_in);
+    solve_M(false, F(bX), F(bY), tol_in);
+    for (int pass = 0;; ++pass) {
+      dslash_full(F(bX), F(bY), false);
+      HopIn<double> hin{c->U64, F(bY), F(bY) + halfn()};
+      LGT_HIP(launch_mhop_residual<true>(c->g, nr, hin, F(bY), phi, F(bRes), vec(vMKap), red(), c->stream));
+      read_results(nr);
+      bool ok = true;
+      for (int k = 0; k < nr; ++k) {
+        st[k].true_res = pp[k] > 0.0 ? std::sqrt(c->host_result[k] / pp[k]) : 0.0;
+        if (!std::isfinite(st[k].true_res)) throw Error(LGT_ERR_NONFINITE, "non-finite residual");
+        ok = ok && (st[k].true_res <= o.tol || !st[k].converged);
+      }
+      if (ok || pass >= 4) break;
+      solve_M(true, F(bYtmp), F(bRes), tol_in);
+      solve_M(false, F(bE), F(bYtmp), tol_in);
+      LGT_HIP(launch_axpy64((int)nfull, 1.0, F(bE), F(bX), c->stream));
+    }
+    for (int k = 0; k < nr; ++k)
+      if (st[k].true_res > o.tol) st[k].converged = false;
+  }
+};
+
+}  // namespace
+
+std::vector<SolveStats> lgt_ctx::solve_batch(int nr, const double* kappas, const void* const* phis,
+                                             void* const* Xs, void* const* Ys, const SolverOpts& o) {
+  BatchWork* w = batch_work(this, nr);
+  BatchSolver b{this, w, nr, o, std::vector<double>(kappas, kappas + nr), std::vector<SolveStats>(nr)};
+  for (int k = 0; k < nr; ++k) LGT_HIP(launch_mpack(g, nr, k, (const double2*)phis[k], w->f[bPhi], stream));
+  b.run();
+  for (int k = 0; k < nr; ++k) {
+    LGT_HIP(launch_munpack(g, nr, k, w->f[bX], (double2*)Xs[k], stream));
+    if (Ys && Ys[k]) LGT_HIP(launch_munpack(g, nr, k, w->f[bY], (double2*)Ys[k], stream));
+  }
+  return b.st;
+}

@@ -144,8 +144,15 @@ hipError_t launch_cg_init(int n, const R2<R>* b, R2<R>* r, R2<R>* p, R2<R>* x, S
 // One block: sum the partials of the previous launch and act on the totals.
 template <int NV>
 __global__ __launch_bounds__(256) void k_finalize(int mode, int nblk, const double* __restrict__ partials,
-                                                  SolverState* st, double* result, double tol, int max_iter) {
-  if (mode == kFinCgStep && st->done != kDoneRunning) return;  // the iteration was skipped
+                                                  SolverState* st, double* result, double tol, int max_iter,
+                                                  Mailbox* mb) {
+  if (mode == kFinCgStep && st->done != kDoneRunning) {  // the iteration was skipped
+    if (threadIdx.x == 0) {
+      if (st->done == kDoneUpdate) st->done = kDoneUpdateHeld;
+      post_progress(mb, st->iter, 1);
+    }
+    return;
+  }
   double tot[NV];
   sum_partials<256, NV>(partials, nblk, tot);
   if (threadIdx.x != 0) return;
@@ -163,6 +170,7 @@ __global__ __launch_bounds__(256) void k_finalize(int mode, int nblk, const doub
     st->alpha = 0.0;
     st->beta = 0.0;
     st->pap = 0.0;
+    st->delta2 = 0.0;
     st->done = !isfinite(rr) ? kDoneBreakdown : (rr == 0.0 ? kDoneConverged : kDoneRunning);
   } else {  // kFinCgStep
     const double rr = tot[0];
@@ -171,8 +179,10 @@ __global__ __launch_bounds__(256) void k_finalize(int mode, int nblk, const doub
     st->iter += 1;
     if (rr > st->rr_max) st->rr_max = rr;
     if (!isfinite(rr)) st->done = kDoneBreakdown;
-    else if (rr <= st->rr_stop) st->done = kDoneConverged;
+    else if (rr <= st->rr_stop) st->done = st->delta2 > 0.0 ? kDoneUpdate : kDoneConverged;
+    else if (rr <= st->delta2 * st->rr_max) st->done = kDoneUpdate;
     else if (st->iter >= st->max_iter) st->done = kDoneMaxIter;
+    post_progress(mb, st->iter, st->done != kDoneRunning);
   }
 }
 
@@ -181,17 +191,17 @@ hipError_t launch_finalize(int mode, int nblk, Reduce red, SolverState* st, int 
   if (nblk > red.capacity) return hipErrorInvalidValue;
   if (mode == kFinResult2)
     hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(256), 0, s, mode, nblk, red.partials, st, red.result + slot,
-                       tol, max_iter);
+                       tol, max_iter, red.mbox);
   else
     hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(256), 0, s, mode, nblk, red.partials, st, red.result + slot,
-                       tol, max_iter);
+                       tol, max_iter, red.mbox);
   return hipGetLastError();
 }
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_cg_xpay(int n, const R2<R>* __restrict__ r, R2<R>* __restrict__ p,
                                                  const SolverState* st) {
-  if (st->done != kDoneRunning) return;
+  if (st->done != kDoneRunning && st->done != kDoneUpdate) return;
   const R beta = R(st->beta);
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const R2<R> rv = r[i];

@@ -18,111 +18,9 @@
 #include <cstdlib>
 
 #include "lgt_internal.h"
+#include "lgt_hop.h"
 
 namespace lgt {
-
-// h = u + S * B_mu d  for one spinor (comp = 3*spin + colour); S = +-1.
-template <typename R, int MU, int S>
-__device__ __forceinline__ void project(const C<R>* psi, C<R>* h) {
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const C<R> u0 = psi[i], u1 = psi[3 + i], d0 = psi[6 + i], d1 = psi[9 + i];
-    const R s = R(S);
-    if constexpr (MU == 0) {         // B = -i sigma_1: B d = (-i d1, -i d0)
-      h[i] = u0 - s * itimes(d1);
-      h[3 + i] = u1 - s * itimes(d0);
-    } else if constexpr (MU == 1) {  // B = -i sigma_2: B d = (-d1, d0)
-      h[i] = u0 - s * d1;
-      h[3 + i] = u1 + s * d0;
-    } else if constexpr (MU == 2) {  // B = -i sigma_3: B d = (-i d0, i d1)
-      h[i] = u0 - s * itimes(d0);
-      h[3 + i] = u1 + s * itimes(d1);
-    } else {                         // B = 1
-      h[i] = u0 + s * d0;
-      h[3 + i] = u1 + s * d1;
-    }
-  }
-}
-
-// acc_up += w ; acc_dn += S * B_mu^dag w
-template <typename R, int MU, int S>
-__device__ __forceinline__ void reconstruct(const C<R>* w, C<R>* acc) {
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const C<R> w0 = w[i], w1 = w[3 + i];
-    const R s = R(S);
-    acc[i] += w0;
-    acc[3 + i] += w1;
-    if constexpr (MU == 0) {         // B^dag = i sigma_1: (i w1, i w0)
-      acc[6 + i] += s * itimes(w1);
-      acc[9 + i] += s * itimes(w0);
-    } else if constexpr (MU == 1) {  // B^dag = i sigma_2: (w1, -w0)
-      acc[6 + i] += s * w1;
-      acc[9 + i] -= s * w0;
-    } else if constexpr (MU == 2) {  // B^dag = i sigma_3: (i w0, -i w1)
-      acc[6 + i] += s * itimes(w0);
-      acc[9 + i] -= s * itimes(w1);
-    } else {
-      acc[6 + i] += s * w0;
-      acc[9 + i] += s * w1;
-    }
-  }
-}
-
-// Both hops along MU for output site (p, cb) with coordinates c.
-template <typename R, int MU, bool DAG>
-__device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__ gauge,
-                                        const R2<R>* __restrict__ in, int p, int cb, const int c[4],
-                                        C<R>* acc) {
-  constexpr int SF = DAG ? +1 : -1;  // forward projector 1 + SF gamma
-  constexpr int SB = -SF;
-  const int vh = g.vh;
-  C<R> psi[12], h[6], w[6];
-  {  // forward: (1 + SF gamma) U_mu(x) psi(x + mu)
-    const int nf = cb_shift(g, c, MU, +1);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k] = ld<R>(in + (size_t)k * vh + nf);
-    project<R, MU, SF>(psi, h);
-    const M3<R> U = load_m3<R>(gptr<R>(gauge, g, p, MU), vh, cb);
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        C<R> s = U.m[3 * i] * h[3 * a];
-        s += U.m[3 * i + 1] * h[3 * a + 1];
-        s += U.m[3 * i + 2] * h[3 * a + 2];
-        w[3 * a + i] = s;
-      }
-    if (MU == 3 && c[3] == g.L[3] - 1) {
-      const R b = R(g.bc);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) w[k] = b * w[k];
-    }
-    reconstruct<R, MU, SF>(w, acc);
-  }
-  {  // backward: (1 + SB gamma) U_mu(x - mu)^dag psi(x - mu)
-    const int nb = cb_shift(g, c, MU, -1);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k] = ld<R>(in + (size_t)k * vh + nb);
-    project<R, MU, SB>(psi, h);
-    const M3<R> U = load_m3<R>(gptr<R>(gauge, g, 1 - p, MU), vh, nb);
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        C<R> s = cjmul(U.m[i], h[3 * a]);
-        s += cjmul(U.m[3 + i], h[3 * a + 1]);
-        s += cjmul(U.m[6 + i], h[3 * a + 2]);
-        w[3 * a + i] = s;
-      }
-    if (MU == 3 && c[3] == 0) {
-      const R b = R(g.bc);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) w[k] = b * w[k];
-    }
-    reconstruct<R, MU, SB>(w, acc);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Epilogues.  apply() gets the 3 colour components of spin `spin` of the hop
@@ -294,10 +192,10 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, HopIn
     cb_coords(g, p, cb, c);
     const R2<R>* in = p ? hin.in_even : hin.in_odd;
     switch (mu) {
-      case 0: hop_dir<R, 0, DAG>(g, hin.gauge, in, p, cb, c, acc); break;
-      case 1: hop_dir<R, 1, DAG>(g, hin.gauge, in, p, cb, c, acc); break;
-      case 2: hop_dir<R, 2, DAG>(g, hin.gauge, in, p, cb, c, acc); break;
-      default: hop_dir<R, 3, DAG>(g, hin.gauge, in, p, cb, c, acc); break;
+      case 0: hop_dir<R, 0, DAG>(g, hin.gauge, in, p, cb, c, acc, 1, 0); break;
+      case 1: hop_dir<R, 1, DAG>(g, hin.gauge, in, p, cb, c, acc, 1, 0); break;
+      case 2: hop_dir<R, 2, DAG>(g, hin.gauge, in, p, cb, c, acc, 1, 0); break;
+      default: hop_dir<R, 3, DAG>(g, hin.gauge, in, p, cb, c, acc, 1, 0); break;
     }
   }
 #pragma unroll

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -43,6 +44,10 @@ struct SolverOpts {
 
 }  // namespace lgt
 
+struct BatchWork;  // batched-solver workspace (batch.hip)
+struct lgt_ctx;
+void lgt_ctx_free_batch(lgt_ctx* c);
+
 struct lgt_ctx {
   lgt::Geom g{};
   int64_t V = 0;
@@ -71,11 +76,15 @@ struct lgt_ctx {
   int* flags = nullptr;          // device: [0] non-finite input
   int* host_flags = nullptr;     // pinned
   lgt::SolverState* host_state = nullptr;  // pinned
+  lgt::Mailbox* mbox_host = nullptr;        // pinned, coherent: progress posted by CG steps
+  lgt::Mailbox* mbox_dev = nullptr;         // its device address
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   size_t half_elems() const { return (size_t)12 * vh; }
   size_t full_elems() const { return (size_t)24 * vh; }
-  lgt::Reduce red() const { return lgt::Reduce{partials, result, lgt::reduce_capacity(vh)}; }
+  lgt::Reduce red() const {
+    return lgt::Reduce{partials, result, lgt::reduce_capacity(vh), (size_t)lgt::reduce_capacity(vh) * 4, mbox_dev};
+  }
 
   double2* f64(int i);   // full FP64 spinor scratch i (allocated on demand)
   double2* g64(int i);   // packed FP64 gauge-type scratch i (allocated on demand)
@@ -90,12 +99,51 @@ struct lgt_ctx {
   void sync();
   void read_results(int n);
 
+  // Enqueues step() -- one CG iteration, ending in a finalize that posts to
+  // the mailbox -- until the device posts that the host has to act, keeping
+  // kQueueAhead iterations queued beyond the last one the device finished
+  // (the surplus ones see the stopped state and return at once).  iter0 is
+  // the device's iteration count before the first step; no unfinished CG
+  // step may be on the stream.  Returns after synchronising the stream.
+  static constexpr int kQueueAhead = 3;
+  template <typename Step>
+  void drive(int iter0, Step&& step) {
+    unsigned long long* w = &mbox_host->word;
+    __atomic_store_n(w, (unsigned long long)(unsigned)iter0, __ATOMIC_RELEASE);
+    int queued = iter0, seen_prev = iter0;
+    auto t_prev = std::chrono::steady_clock::now();
+    for (;;) {
+      const unsigned long long v = __atomic_load_n(w, __ATOMIC_ACQUIRE);
+      if (v >> 32) break;
+      const int seen = (int)(unsigned)v;
+      if (queued - seen < kQueueAhead) {
+        step();
+        ++queued;
+        continue;
+      }
+      const auto now = std::chrono::steady_clock::now();
+      if (seen != seen_prev) {
+        seen_prev = seen;
+        t_prev = now;
+      } else if (now - t_prev > std::chrono::seconds(30)) {
+        break;  // nothing posted for long: let the caller read the state after the sync
+      }
+      __builtin_ia32_pause();
+    }
+    sync();
+  }
+
   // stout smearing (smear.hip): U0, G packed FP64
   void smear(const double2* U0, int nlevels, double rho, double2* dst);
   void stout_backprop(const double2* U0, int nlevels, double rho, double2* G);
   lgt::SolveStats smeared_force(const double2* U0, const double2* phi, double beta, double rho, int nlevels,
                                 const lgt::SolverOpts& o, int mode, double dt, void* out, int layout,
                                 double* S_F);
+
+  // batched solves (batch.hip): nr right-hand sides with their own kappa
+  BatchWork* batch = nullptr;
+  std::vector<lgt::SolveStats> solve_batch(int nr, const double* kappas, const void* const* phis, void* const* Xs,
+                                           void* const* Ys, const lgt::SolverOpts& o);
 
   double kappa = 0.0;  // hopping parameter of the current solve
  private:

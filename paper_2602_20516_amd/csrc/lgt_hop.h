@@ -1,0 +1,118 @@
+// The spin-projected Wilson hop along one direction, shared by the single-
+// and multi-right-hand-side hop kernels.
+//
+//   (1 + s gamma_mu) psi = (h ; s B_mu^dag h),  h = psi_up + s B_mu psi_dn,
+// chiral basis: gamma_mu = [[0, B_mu], [B_mu^dag, 0]], B_0 = -i sigma_1,
+// B_1 = -i sigma_2, B_2 = -i sigma_3, B_3 = 1; spinor component = 3*spin + colour.
+#pragma once
+
+#include "lgt_internal.h"
+
+namespace lgt {
+
+// h = u + S * B_mu d  for one spinor (comp = 3*spin + colour); S = +-1.
+template <typename R, int MU, int S>
+__device__ __forceinline__ void project(const C<R>* psi, C<R>* h) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const C<R> u0 = psi[i], u1 = psi[3 + i], d0 = psi[6 + i], d1 = psi[9 + i];
+    const R s = R(S);
+    if constexpr (MU == 0) {         // B = -i sigma_1: B d = (-i d1, -i d0)
+      h[i] = u0 - s * itimes(d1);
+      h[3 + i] = u1 - s * itimes(d0);
+    } else if constexpr (MU == 1) {  // B = -i sigma_2: B d = (-d1, d0)
+      h[i] = u0 - s * d1;
+      h[3 + i] = u1 + s * d0;
+    } else if constexpr (MU == 2) {  // B = -i sigma_3: B d = (-i d0, i d1)
+      h[i] = u0 - s * itimes(d0);
+      h[3 + i] = u1 + s * itimes(d1);
+    } else {                         // B = 1
+      h[i] = u0 + s * d0;
+      h[3 + i] = u1 + s * d1;
+    }
+  }
+}
+
+// acc_up += w ; acc_dn += S * B_mu^dag w
+template <typename R, int MU, int S>
+__device__ __forceinline__ void reconstruct(const C<R>* w, C<R>* acc) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const C<R> w0 = w[i], w1 = w[3 + i];
+    const R s = R(S);
+    acc[i] += w0;
+    acc[3 + i] += w1;
+    if constexpr (MU == 0) {         // B^dag = i sigma_1: (i w1, i w0)
+      acc[6 + i] += s * itimes(w1);
+      acc[9 + i] += s * itimes(w0);
+    } else if constexpr (MU == 1) {  // B^dag = i sigma_2: (w1, -w0)
+      acc[6 + i] += s * w1;
+      acc[9 + i] -= s * w0;
+    } else if constexpr (MU == 2) {  // B^dag = i sigma_3: (i w0, -i w1)
+      acc[6 + i] += s * itimes(w0);
+      acc[9 + i] -= s * itimes(w1);
+    } else {
+      acc[6 + i] += s * w0;
+      acc[9 + i] += s * w1;
+    }
+  }
+}
+
+// Both hops along MU for output site (p, cb) with coordinates c.  Spinor
+// element (k, site) of right-hand side n sits at (k*vh + site)*nr + n
+// (nr = 1, n = 0 for a single field).
+template <typename R, int MU, bool DAG>
+__device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__ gauge,
+                                        const R2<R>* __restrict__ in, int p, int cb, const int c[4],
+                                        C<R>* acc, int nr, int n) {
+  constexpr int SF = DAG ? +1 : -1;  // forward projector 1 + SF gamma
+  constexpr int SB = -SF;
+  const int vh = g.vh;
+  C<R> psi[12], h[6], w[6];
+  {  // forward: (1 + SF gamma) U_mu(x) psi(x + mu)
+    const int nf = cb_shift(g, c, MU, +1);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = ld<R>(in + ((size_t)k * vh + nf) * nr + n);
+    project<R, MU, SF>(psi, h);
+    const M3<R> U = load_m3<R>(gptr<R>(gauge, g, p, MU), vh, cb);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        C<R> s = U.m[3 * i] * h[3 * a];
+        s += U.m[3 * i + 1] * h[3 * a + 1];
+        s += U.m[3 * i + 2] * h[3 * a + 2];
+        w[3 * a + i] = s;
+      }
+    if (MU == 3 && c[3] == g.L[3] - 1) {
+      const R b = R(g.bc);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) w[k] = b * w[k];
+    }
+    reconstruct<R, MU, SF>(w, acc);
+  }
+  {  // backward: (1 + SB gamma) U_mu(x - mu)^dag psi(x - mu)
+    const int nb = cb_shift(g, c, MU, -1);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = ld<R>(in + ((size_t)k * vh + nb) * nr + n);
+    project<R, MU, SB>(psi, h);
+    const M3<R> U = load_m3<R>(gptr<R>(gauge, g, 1 - p, MU), vh, nb);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        C<R> s = cjmul(U.m[i], h[3 * a]);
+        s += cjmul(U.m[3 + i], h[3 * a + 1]);
+        s += cjmul(U.m[6 + i], h[3 * a + 2]);
+        w[3 * a + i] = s;
+      }
+    if (MU == 3 && c[3] == 0) {
+      const R b = R(g.bc);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) w[k] = b * w[k];
+    }
+    reconstruct<R, MU, SB>(w, acc);
+  }
+}
+
+}  // namespace lgt

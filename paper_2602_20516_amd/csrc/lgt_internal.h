@@ -22,14 +22,19 @@ struct SolverState {
   double rr_stop;   // stop when rr <= rr_stop
   double rr0;       // |b|^2
   double rr_max;    // mixed precision: largest |r|^2 since the last FP64 update
-  double pad0;
+  double delta2;    // mixed precision: stop for an FP64 update once rr <= delta2 * rr_max (0: never)
   int iter;
   int max_iter;
-  int done;         // 0 running, 1 converged, 2 iteration cap, 3 breakdown / non-finite
+  int done;         // a kDone* code
   int pad1;
 };
 
-enum { kDoneRunning = 0, kDoneConverged = 1, kDoneMaxIter = 2, kDoneBreakdown = 3 };
+// kDoneUpdate: the recursion stopped for an FP64 (reliable) update in this
+// iteration, whose final direction update p = r + beta p still runs, so the
+// search direction stays consistent with the residual; the next finalize
+// turns it into kDoneUpdateHeld, which no kernel touches.
+enum { kDoneRunning = 0, kDoneConverged = 1, kDoneMaxIter = 2, kDoneBreakdown = 3, kDoneUpdate = 4,
+       kDoneUpdateHeld = 5 };
 
 // Output layout of the gauge-type kernels (forces, link update).
 enum Layout { kCanonical = 0, kPacked = 1 };
@@ -43,11 +48,29 @@ struct HopIn {
   const R2<R>* in_odd;
 };
 
+// Host-visible progress of an iterative solve, in pinned host memory: the
+// finalize kernel of every CG step posts the device's iteration count (low
+// 32 bits) and whether the host has to act (high 32 bits: the recursion
+// stopped, converged, or the batch wants an update), so the host can keep a
+// few iterations queued ahead of the GPU instead of synchronising.  One
+// 64-bit store, so the host never sees a torn pair.
+struct Mailbox {
+  unsigned long long word;
+};
+
+__device__ __forceinline__ void post_progress(Mailbox* mb, int iter, int action) {
+  if (!mb) return;
+  const unsigned long long v = ((unsigned long long)(unsigned)action << 32) | (unsigned)iter;
+  __hip_atomic_store(&mb->word, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Workspace scalars used by reductions.
 struct Reduce {
-  double* partials;   // capacity * 4 doubles: one slot per block of the reducing launch
+  double* partials;   // one slot per block (per value) of the reducing launch
   double* result;     // small array of results read by the host
-  int capacity;       // largest grid a reduction kernel may use
+  int capacity;       // largest single-RHS reducing grid (partials hold >= 4 * capacity doubles)
+  size_t ndoubles;    // size of partials
+  Mailbox* mbox;      // device address of the progress mailbox (CG steps post to it; may be null)
 };
 
 // What the one-block finalize kernel does with the summed partials.

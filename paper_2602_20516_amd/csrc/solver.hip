@@ -102,16 +102,6 @@ void lgt_ctx::apply_mhat_dag_mhat64(bool dag, const double2* x, double2* out) {
   }
 }
 
-// Next chunk length from the convergence history.
-static int next_chunk(int iter, double rr, double rr_stop, int it_prev, double rr_prev) {
-  if (iter <= it_prev || rr_prev <= 0.0 || rr <= 0.0) return 32;
-  const double rate = (std::log(rr) - std::log(rr_prev)) / double(iter - it_prev);
-  if (!(rate < 0.0)) return 32;
-  const double left = (std::log(rr_stop) - std::log(rr)) / rate;
-  int n = (int)std::ceil(left * 1.02) + 1;
-  return std::min(std::max(n, 4), 512);
-}
-
 template <typename R, bool DAG>
 static void cg_iteration(const Geom& g, const R2<R>* gauge, double kappa, R2<R>* t, R2<R>* w, R2<R>* x,
                          R2<R>* r, R2<R>* p, SolverState* st, Reduce red, hipStream_t s, int n) {
@@ -135,14 +125,11 @@ int lgt_ctx::cg_normal64(bool dag, double2* z, const double2* rhs, double tol, i
   double2* p = f64(kW3) + half_elems();
   double2* w = f64(kW4) + half_elems();
   LGT_HIP(launch_cg_init<double>(n, rhs, r, p, z, state, red(), tol, max_iter, stream));
-  int it_prev = 0;
-  double rr_prev = 0.0;
-  int chunk = 32;
-  for (;;) {
-    for (int j = 0; j < chunk; ++j) {
+  for (int iter0 = 0;;) {
+    drive(iter0, [&] {
       if (dag) cg_iteration<double, true>(g, U64, kappa, t, w, z, r, p, state, red(), stream, n);
       else cg_iteration<double, false>(g, U64, kappa, t, w, z, r, p, state, red(), stream, n);
-    }
+    });
     LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
     sync();
     const SolverState s = *host_state;
@@ -150,9 +137,7 @@ int lgt_ctx::cg_normal64(bool dag, double2* z, const double2* rhs, double tol, i
       stt.iters += s.iter;
       return s.done;
     }
-    chunk = next_chunk(s.iter, s.rr, s.rr_stop, it_prev, rr_prev);
-    it_prev = s.iter;
-    rr_prev = s.rr;
+    iter0 = s.iter;
   }
 }
 
@@ -163,7 +148,14 @@ int lgt_ctx::cg_normal64(bool dag, double2* z, const double2* rhs, double tol, i
 // for residuals many orders below ||phi||).  At every reliable update the
 // FP32 solution, in units of 1/sigma, is folded into the FP64 one, the FP64
 // residual is recomputed, and the search direction is rescaled to the new
-// units (or restarted when the recursion had stopped).
+// units.  The recursion stops itself on the device, in the iteration where
+// |r|^2 first falls below delta^2 times its largest value since the last
+// update (or below the target), after that iteration's direction update,
+// and posts the stop to the host (see drive).  Letting it run on until the
+// host looks would let a fast-converging recursion go orders of magnitude
+// past the accuracy FP32 can hold, after which the kept direction no longer
+// matches the true residual and CG diverges.  After a breakdown the
+// direction is restarted.
 int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double tol, int max_iter, double delta,
                              SolveStats& stt) {
   const int n = (int)half_elems();
@@ -191,6 +183,7 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
     s.rr0 = 1.0;
     s.rr_max = 1.0;
     s.rr_stop = rr_target * sigma * sigma;
+    s.delta2 = delta * delta;
     s.iter = iter;
     s.max_iter = max_iter;
     s.done = kDoneRunning;
@@ -198,52 +191,39 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
     LGT_HIP(hipMemcpyAsync(state, host_state, sizeof(SolverState), hipMemcpyHostToDevice, stream));
   };
   write_state(0);
-  const double d2 = delta * delta;
-  int it_prev = 0;
-  double rr_prev = 0.0;
-  int chunk = 16;
   for (;;) {
-    for (int j = 0; j < chunk; ++j) {
+    drive(s.iter, [&] {
       if (dag) cg_iteration<float, true>(g, U32, kappa, ts, ws, xs, rs, ps, state, red(), stream, n);
       else cg_iteration<float, false>(g, U32, kappa, ts, ws, xs, rs, ps, state, red(), stream, n);
-    }
+    });
     LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
     sync();
     s = *host_state;
+    if (s.done == kDoneRunning) continue;  // nothing posted for long (see drive)
     if (s.done == kDoneMaxIter) {
       LGT_HIP(launch_mixed_update(n, xs, z, 1.0 / sigma, stream));
       stt.iters += s.iter;
       return kDoneMaxIter;
     }
-    if (s.done != kDoneRunning || s.rr <= d2 * s.rr_max) {
-      // the recursion stopped (converged in FP32, or broke down in FP32):
-      // its last direction update did not happen, so restart the direction
-      const int restart = s.done != kDoneRunning ? 1 : 0;
-      LGT_HIP(launch_mixed_update(n, xs, z, 1.0 / sigma, stream));
-      apply_mhat_dag_mhat64(dag, z, r64);          // r64 = A z
-      LGT_HIP(launch_xmy64(n, rhs, r64, stream));  // r64 = rhs - A z
-      LGT_HIP(launch_norm_dot(n, r64, nullptr, red(), 0, stream));
-      read_results(2);
-      const double rr64 = host_result[0];
-      stt.reliable += 1;
-      if (!std::isfinite(rr64)) return kDoneBreakdown;
-      if (rr64 <= rr_target) {
-        stt.iters += s.iter;
-        return kDoneConverged;
-      }
-      const double sigma_new = 1.0 / std::sqrt(rr64);
-      LGT_HIP(launch_rescale_residual(n, r64, sigma_new, rs, ps, restart, sigma_new / sigma, stream));
-      sigma = sigma_new;
-      write_state(s.iter);
-      it_prev = 0;
-      rr_prev = 0.0;
-      chunk = 16;
-      continue;
+    // the recursion stopped for an update (or broke down): fold, recompute
+    // the FP64 residual, rescale
+    const int restart = s.done == kDoneBreakdown ? 1 : 0;  // its last direction update did not happen
+    LGT_HIP(launch_mixed_update(n, xs, z, 1.0 / sigma, stream));
+    apply_mhat_dag_mhat64(dag, z, r64);          // r64 = A z
+    LGT_HIP(launch_xmy64(n, rhs, r64, stream));  // r64 = rhs - A z
+    LGT_HIP(launch_norm_dot(n, r64, nullptr, red(), 0, stream));
+    read_results(2);
+    const double rr64 = host_result[0];
+    stt.reliable += 1;
+    if (!std::isfinite(rr64)) return kDoneBreakdown;
+    if (rr64 <= rr_target) {
+      stt.iters += s.iter;
+      return kDoneConverged;
     }
-    chunk = next_chunk(s.iter, s.rr, s.rr_stop, it_prev, rr_prev);
-    chunk = std::min(chunk, 64);
-    it_prev = s.iter;
-    rr_prev = s.rr;
+    const double sigma_new = 1.0 / std::sqrt(rr64);
+    LGT_HIP(launch_rescale_residual(n, r64, sigma_new, rs, ps, restart, sigma_new / sigma, stream));
+    sigma = sigma_new;
+    write_state(s.iter);
   }
 }
 

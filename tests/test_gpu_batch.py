@@ -1,0 +1,86 @@
+"""GPU parity of the batched multi-right-hand-side solve (12 pseudofermions:
+6 kappa values x 2 Gaussian seeds on one lattice) against the oracle and
+against the single-field solves."""
+import sys
+
+import numpy as np
+import pytest
+
+import lgt_inputs as li
+from oracle import dirac, solver
+
+from gpu_common import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+KAPPAS = (0.10, 0.11, 0.12, 0.125, 0.13, 0.135)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lgt():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2602_20516_amd as m
+    return m
+
+
+def workload(dims, seeds=(402, 403)):
+    u = li.random_links(dims, 0.3, 401)
+    etas = [li.gaussian_spinor(dims, s) for s in seeds]
+    items = [(k, eta) for k in KAPPAS for eta in etas]
+    return u, items
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_batch_vs_oracle_4x4(lgt, precision):
+    dims = (4, 4, 4, 4)
+    u, items = workload(dims)
+    phis = [dirac.dslash_dag(u, eta, k) for k, eta in items]
+    lat = lgt.Lattice(dims)
+    Xs, Ys, st = lat.cg_solve_batch(to_dev(u), [to_dev(p) for p in phis], [k for k, _ in items],
+                                    lgt.Params(precision=precision, tol=1e-12))
+    say("batch", precision, [s["iters"] for s in st], max(s["true_rel_residual"] for s in st))
+    for (k, eta), phi, X, Y, s in zip(items, phis, Xs, Ys, st):
+        assert s["true_rel_residual"] <= 1e-12
+        x_ref, y_ref, _, _ = solver.solve_ddag_d(u, phi, k, tol=1e-14)
+        assert rel_err(to_host(X), x_ref) < 1e-9
+        assert rel_err(to_host(Y), eta) < 1e-9
+
+
+def test_batch_ragged_and_small(lgt):
+    """Ragged tail (V/2 * nr not a multiple of 64), a batch of one, and five items."""
+    for dims, n in (((6, 6, 6, 6), 5), ((2, 2, 2, 4), 1), ((6, 4, 4, 8), 7)):
+        u, items = workload(dims)
+        items = items[:n]
+        phis = [dirac.dslash_dag(u, eta, k) for k, eta in items]
+        lat = lgt.Lattice(dims)
+        Xs, Ys, st = lat.cg_solve_batch(to_dev(u), [to_dev(p) for p in phis], [k for k, _ in items],
+                                        lgt.Params(tol=1e-12))
+        for (k, eta), Y, s in zip(items, Ys, st):
+            assert s["true_rel_residual"] <= 1e-12
+            assert rel_err(to_host(Y), eta) < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_batch_matches_single_solves_16(lgt, precision):
+    """16^4 with the 12 right-hand sides: each item equals its own single solve."""
+    import torch
+    dims = (16, 16, 16, 16)
+    u, items = workload(dims)
+    lat = lgt.Lattice(dims)
+    U = to_dev(u)
+    phis = [lat.dslash(U, to_dev(eta), k, dagger=True) for k, eta in items]
+    prm = lgt.Params(precision=precision, tol=1e-10)
+    torch.cuda.synchronize()
+    Xs, Ys, st = lat.cg_solve_batch(U, phis, [k for k, _ in items], prm)
+    say("batch16", precision, st[0]["ms"], [s["iters"] for s in st])
+    for i in (0, 5, 11):
+        k = items[i][0]
+        X1, Y1, s1 = lat.cg_solve(U, phis[i], k, prm)
+        assert st[i]["true_rel_residual"] <= 1e-10
+        assert rel_err(to_host(Xs[i]), to_host(X1)) < 1e-8
+        assert rel_err(to_host(Ys[i]), items[i][1]) < 1e-8
