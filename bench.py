@@ -12,7 +12,16 @@ Also reported: the roofline of the CG's dominant kernel (the even/odd hop),
 timed with HIP events on the library's stream, and the FP64 CPU oracle timed
 on a bounded sample of the same call on this host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Other workloads (each prints its own JSON line; none is the headline):
+  --config 3  24^3x48, kappa 0.13: force call, mixed (FP32 and BF16-stored
+              inner vectors) against FP64, force difference, hop roofline
+  --config 4  8^4, 12^4, 16^4 with 12 right-hand sides each (6 kappa x 2
+              eta): 36 mixed solves batched per lattice against 36
+              sequential solves, batched-hop roofline
+  --config 5  32^3x64, kappa 0.135, 2 stout levels rho 0.1: one leapfrog
+              trajectory (10 steps, tau 1), dH, reversibility
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--config 2|3|4|5]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -95,11 +104,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4, 5))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path here is single-GPU (no collectives); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.config != 2:
+        rec = {3: bench_c3, 4: bench_c4, 5: bench_c5}[args.config](args)
+        print(json.dumps(rec), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -206,6 +220,207 @@ def main():
         log("bench: cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(u, eta, kappa, tol, args.cpu_budget)
     print(json.dumps(rec), flush=True)
+
+
+def _traffic(name):
+    """HBM bytes per launch from the committed counter passes of a kernel."""
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        with open(path) as f:
+            return json.load(f).get("bytes_per_launch")
+    except (OSError, ValueError):
+        return None
+
+
+def _rel(a, b):
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def bench_c3(args):
+    """24^3x48 force call: mixed FP32, mixed with BF16-stored vectors, FP64."""
+    import numpy as np
+    import torch
+
+    import lgt_inputs as li
+    import paper_2602_20516_amd as lgt
+
+    c = li.config(3)
+    dims, kappa, tol = c["dims"], c["kappa"], c["tol"]
+    V = int(np.prod(dims))
+    log("bench c3: generating inputs")
+    U = torch.from_numpy(li.random_links(dims, c["eps"], c["seeds"]["links"])).to("cuda")
+    E = torch.from_numpy(li.gaussian_spinor(dims, c["seeds"]["eta"])).to("cuda")
+    lat = lgt.Lattice(dims)
+    phi = lat.dslash(U, E, kappa, dagger=True)
+    steps = max(1, min(args.steps, 5))
+    res, forces = {}, {}
+    for prec in ("mixed_fp32", "mixed_bf16", "fp64"):
+        prm = lgt.Params(precision=prec, tol=tol)
+        out = lat.empty_gauge()
+        try:
+            for _ in range(max(1, min(args.warmup, 2))):
+                lat.fermion_force(U, phi, kappa, prm, out=out)
+        except lgt.LGTError as e:
+            res[prec] = {"unsupported": str(e)}
+            continue
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st = lat.fermion_force(U, phi, kappa, prm, out=out)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        forces[prec] = out.clone()
+        p = 8 if prec == "fp64" else 4
+        res[prec] = {"ms_per_call": round(t * 1e3, 3), "iters": st["iters"],
+                     "reliable_updates": st["reliable_updates"], "true_rel_residual": st["true_rel_residual"],
+                     "effective_GBs": round((st["iters"] * 516 * p * V + 192 * 8 * V) / t / 1e9, 1)}
+        log(f"bench c3: {prec} {res[prec]}")
+    for prec in ("mixed_fp32", "mixed_bf16"):
+        if prec in forces:
+            res[prec]["force_rel_diff_vs_fp64"] = _rel(forces[prec], forces["fp64"])
+    hop_ms = lat.hop_benchmark(U, E, "mixed_fp32", 100)
+    hop_bytes = 96 * 4 * V
+    gbs = hop_bytes / (hop_ms * 1e-3) / 1e9
+    t_mixed = res["mixed_fp32"]["ms_per_call"]
+    return {
+        "metric": "fermion force (CG+adjoint) ms/call at 24^3x48, mixed vs FP64", "value": t_mixed,
+        "unit": "ms/call", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 2), "ms_per_step": t_mixed,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64 (FP32 inner CG, FP64 residual/force)", "data": "synthetic (seeded SU(3) links eps=0.2, "
+        "Gaussian eta)",
+        "config": {"workload": "24^3x48 Wilson-fermion force, kappa 0.13, FP64 true residual 1e-10",
+                   "dims": list(dims), "kappa": kappa, "tol": tol},
+        "results": res,
+        "speedup_mixed_vs_fp64": round(res["fp64"]["ms_per_call"] / t_mixed, 3),
+        "roofline": {"kernel": "even/odd hop H_eo, FP32", "bound": "hbm", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": _traffic("hop_fp32_24x24x24x48_traffic.json"),
+                     "avg_launch_us": round(hop_ms * 1e3, 3), "algorithmic_bytes_per_launch": hop_bytes},
+    }
+
+
+def bench_c4(args):
+    """36 mixed solves over 3 lattices x 12 right-hand sides: batched vs sequential."""
+    import numpy as np
+    import torch
+
+    import lgt_inputs as li
+    import paper_2602_20516_amd as lgt
+
+    c = li.config(4)
+    prm = lgt.Params(precision=c["precision"], tol=c["tol"])
+    lats = []
+    for dims in c["dims_list"]:
+        U = torch.from_numpy(li.random_links(dims, c["eps"], c["seeds"]["links"])).to("cuda")
+        lat = lgt.Lattice(dims)
+        items = [(k, s) for k in c["kappas"] for s in c["eta_seeds"]]
+        phis = [lat.dslash(U, torch.from_numpy(li.gaussian_spinor(dims, s)).to("cuda"), k, dagger=True)
+                for k, s in items]
+        lats.append((dims, lat, U, [k for k, _ in items], phis))
+
+    def batched():
+        out = []
+        for dims, lat, U, ks, phis in lats:
+            out.append(lat.cg_solve_batch(U, phis, ks, prm)[2])
+        return out
+
+    def sequential():
+        out = []
+        for dims, lat, U, ks, phis in lats:
+            out.append([lat.cg_solve(U, phi, k, prm)[2] for k, phi in zip(ks, phis)])
+        return out
+
+    steps = max(1, min(args.steps, 5))
+    timing = {}
+    for name, fn in (("batched", batched), ("sequential", sequential)):
+        for _ in range(max(1, min(args.warmup, 2))):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = fn()
+        torch.cuda.synchronize()
+        timing[name] = ((time.perf_counter() - t0) / steps, st)
+        log(f"bench c4: {name} {timing[name][0] * 1e3:.2f} ms")
+    tb, stb = timing["batched"]
+    ts, sts = timing["sequential"]
+    per_lat = []
+    for (dims, *_), sb, ss in zip(lats, stb, sts):
+        per_lat.append({"dims": list(dims), "batched_iters": [s["iters"] for s in sb],
+                        "sequential_iters": [s["iters"] for s in ss],
+                        "max_true_rel_residual": max(s["true_rel_residual"] for s in sb)})
+    dims16, lat16, U16, _, _ = lats[-1]
+    E16 = torch.from_numpy(li.gaussian_spinor(dims16, c["eta_seeds"][0])).to("cuda")
+    V16 = int(np.prod(dims16))
+    nr = 2 * len(c["kappas"])
+    hop_ms = lat16.hop_benchmark_mrhs(U16, E16, nr, "mixed_fp32", 100)
+    hop_bytes = (72 + 24 * nr) * 4 * V16
+    gbs = hop_bytes / (hop_ms * 1e-3) / 1e9
+    return {
+        "metric": "36 mixed solves (3 lattices x 12 RHS) total ms, batched vs sequential", "value": round(tb * 1e3, 3),
+        "unit": "ms", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 2), "ms_per_step": round(tb * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64 (FP32 inner CG, FP64 residual)", "data": "synthetic (seeded SU(3) links eps=0.3, "
+        "Gaussian eta seeds 402/403)",
+        "config": {"workload": "8^4, 12^4, 16^4; kappa 0.10-0.135 x 2 eta per lattice; X = (D^dag D)^-1 phi to FP64 "
+                               "true residual 1e-10", "tol": c["tol"]},
+        "batched_ms": round(tb * 1e3, 3), "sequential_ms": round(ts * 1e3, 3),
+        "speedup_batched_vs_sequential": round(ts / tb, 3), "lattices": per_lat,
+        "roofline": {"kernel": f"batched even/odd hop H_eo, FP32, {nr} right-hand sides, 16^4", "bound": "hbm",
+                     "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": _traffic("mhop_fp32_16x16x16x16_traffic.json"),
+                     "avg_launch_us": round(hop_ms * 1e3, 3), "algorithmic_bytes_per_launch": hop_bytes},
+    }
+
+
+def bench_c5(args):
+    """One smeared leapfrog trajectory at 32^3x64, its dH and reversibility."""
+    import numpy as np
+    import torch
+
+    import lgt_inputs as li
+    import paper_2602_20516_amd as lgt
+
+    c = li.config(5)
+    dims = c["dims"]
+    log("bench c5: generating inputs")
+    u = li.random_links(dims, c["eps"], c["seeds"]["links"])
+    U0 = torch.from_numpy(u).to("cuda")
+    del u
+    E = torch.from_numpy(li.gaussian_spinor(dims, c["seeds"]["eta"])).to("cuda")
+    P0 = torch.from_numpy(li.random_momenta(dims, c["seeds"]["mom"])).to("cuda")
+    lat = lgt.Lattice(dims)
+    phi = lat.dslash(lat.stout_smear(U0, c["rho"], c["nstout"]), E, c["kappa"], dagger=True)
+    prm = lgt.Params(precision=c["precision"], tol=c["tol"])
+    nsteps = c["nsteps"]
+    dt = c["tau"] / nsteps
+    U, P = U0.clone(), P0.clone()
+    torch.cuda.synchronize()
+    log("bench c5: trajectory")
+    t0 = time.perf_counter()
+    dh, st = lat.md_step_smeared(U, P, phi, c["beta"], c["kappa"], c["rho"], c["nstout"], dt, nsteps, prm)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    log(f"bench c5: {t:.2f} s dH {dh} {st}")
+    P.neg_()
+    dh_back, st_back = lat.md_step_smeared(U, P, phi, c["beta"], c["kappa"], c["rho"], c["nstout"], dt, nsteps,
+                                           prm)
+    rev_u = _rel(U, U0)
+    rev_p = _rel(-P, P0)
+    log(f"bench c5: reversed dH {dh_back}; |U-U0|/|U0| {rev_u:.3e}, |P-P0|/|P0| {rev_p:.3e}")
+    return {
+        "metric": "smeared HMC trajectory ms at 32^3x64 (10 leapfrog steps, 2 stout levels)",
+        "value": round(t * 1e3, 1), "unit": "ms/trajectory", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(t * 1e3, 1), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64 (FP32 inner CG, FP64 forces, smearing, integrator)",
+        "data": "synthetic (seeded SU(3) links eps=0.2, Gaussian eta and momenta)",
+        "config": {"workload": "32^3x64, beta 6.0, kappa 0.135, stout rho 0.1 x 2, tau 1, 10 steps, FP64 true "
+                               "residual 1e-10", "dims": list(dims)},
+        "dH": dh, "dH_reversed": dh_back, "reversibility_rel_U": rev_u, "reversibility_rel_P": rev_p,
+        "iters": st["iters"], "reliable_updates": st["reliable_updates"],
+        "max_true_rel_residual": st["true_rel_residual"], "V": int(np.prod(dims)),
+    }
 
 
 if __name__ == "__main__":

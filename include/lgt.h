@@ -88,8 +88,11 @@ typedef enum lgt_status {
  * FP64.  LGT_MIXED_FP32: inner CG with FP32 links, spinors and hops inside
  * an FP64 reliable-update loop that recomputes the residual in FP64 and
  * accumulates the solution in FP64; the stopping test is on the FP64
- * residual.  LGT_MIXED_BF16: as LGT_MIXED_FP32 with the hop input spinors
- * stored in bfloat16 (FP32 arithmetic). */
+ * residual.  LGT_MIXED_BF16: as LGT_MIXED_FP32 with the spinors the inner
+ * recursion passes between its hop kernels (search direction and the two
+ * Schur intermediates) stored in bfloat16, rounded to nearest even; FP32
+ * arithmetic, FP32 solution and residual, FP32 links.  Single-field solves
+ * only (lgt_cg_solve_batch returns UNSUPPORTED for it). */
 typedef enum lgt_precision {
   LGT_FP64 = 0,
   LGT_MIXED_FP32 = 1,
@@ -136,8 +139,9 @@ typedef struct lgt_ctx lgt_ctx;
  * hip_stream: a hipStream_t (NULL = the default stream).  The context owns
  * its device workspace (packed link copies, solver vectors), allocated here;
  * it grows on first use of the mixed-precision and MD paths.
- * Errors: INVALID_ARGUMENT (odd or < 2 extent, bc not +-1, null out),
- * OUT_OF_MEMORY, DEVICE. */
+ * Errors: INVALID_ARGUMENT (odd or < 2 extent, bc not +-1, null out, or a
+ * lattice whose FP64 half-lattice spinor reaches 4 GiB: V < 44.7M sites,
+ * since kernels address fields with 32-bit offsets), OUT_OF_MEMORY, DEVICE. */
 LGT_API lgt_status lgt_create(const lgt_geom* geom, void* hip_stream, lgt_ctx** out);
 
 /* Release the context and its workspace (synchronises its stream). */
@@ -269,7 +273,8 @@ typedef struct lgt_batch_item {
  * launches, so each link load serves all of them and each keeps its own CG
  * scalars, stopping once converged.  stats_per_item (may be NULL) receives n
  * entries; ms is the time of the whole batch.  NOT_CONVERGED if any item
- * missed the tolerance (all outputs are written). */
+ * missed the tolerance (all outputs are written).  INVALID_ARGUMENT also
+ * when the batched FP64 field (12 * V/2 * n complex) reaches 4 GiB. */
 LGT_API lgt_status lgt_cg_solve_batch(lgt_ctx* ctx, const void* U, int32_t n, const lgt_batch_item* items,
                                       const lgt_solver_params* params, lgt_solver_stats* stats_per_item);
 
@@ -282,6 +287,14 @@ LGT_API lgt_status lgt_cg_solve_batch(lgt_ctx* ctx, const void* U, int32_t n, co
  * spinors). */
 LGT_API lgt_status lgt_hop_benchmark(lgt_ctx* ctx, const void* U, const void* psi, int32_t precision,
                                      int32_t nrep, double* avg_ms);
+
+/* The same for the batched multi-right-hand-side hop of lgt_cg_solve_batch:
+ * psi (canonical spinor, device) is copied into all nrhs (1..16) slots of
+ * the batched layout, and nrep launches of H_eo over the nrhs fields are
+ * timed.  One launch reads all 4V links once for every right-hand side, so
+ * its algorithmic traffic is 72 + 24 * nrhs reals per lattice site. */
+LGT_API lgt_status lgt_hop_benchmark_mrhs(lgt_ctx* ctx, const void* U, const void* psi, int32_t nrhs,
+                                          int32_t precision, int32_t nrep, double* avg_ms);
 
 #ifdef __cplusplus
 }

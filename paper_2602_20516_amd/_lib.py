@@ -78,6 +78,7 @@ PROTOTYPES = {
     "lgt_md_step": (_st, [_vp, _vp, _vp, _vp, _d, _d, _d, _i, ctypes.POINTER(SolverParams),
                           ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
     "lgt_hop_benchmark": (_st, [_vp, _vp, _vp, _i, _i, ctypes.POINTER(_d)]),
+    "lgt_hop_benchmark_mrhs": (_st, [_vp, _vp, _vp, _i, _i, _i, ctypes.POINTER(_d)]),
     "lgt_cg_solve_batch": (_st, [_vp, _vp, _i, ctypes.POINTER(BatchItem), ctypes.POINTER(SolverParams),
                                  ctypes.POINTER(SolverStats)]),
     "lgt_stout_smear": (_st, [_vp, _vp, _vp, _d, _i]),

@@ -307,6 +307,16 @@ class Lattice:
         _check(self.lib, self.ctx, st)
         return ms.value
 
+    def hop_benchmark_mrhs(self, U, psi, nrhs: int, precision: str = "mixed_fp32", nrep: int = 50) -> float:
+        """lgt_hop_benchmark_mrhs: mean duration (ms) of one batched hop over nrhs fields."""
+        ms = ctypes.c_double()
+        self._bind_stream()
+        st = self.lib.lgt_hop_benchmark_mrhs(self.ctx, self._field(U, "gauge", "U"),
+                                             self._field(psi, "spinor", "psi"), int(nrhs),
+                                             _PRECISIONS[precision], int(nrep), ctypes.byref(ms))
+        _check(self.lib, self.ctx, st)
+        return ms.value
+
 
 # Module-level functions with the ABI's names.
 def lgt_create(dims, fermion_bc: int = -1) -> Lattice:
@@ -355,6 +365,10 @@ def lgt_md_step(lat: Lattice, U, P, phi, beta, kappa, dt, nsteps, params=None):
 
 def lgt_hop_benchmark(lat: Lattice, U, psi, precision="fp64", nrep=50):
     return lat.hop_benchmark(U, psi, precision, nrep)
+
+
+def lgt_hop_benchmark_mrhs(lat: Lattice, U, psi, nrhs, precision="mixed_fp32", nrep=50):
+    return lat.hop_benchmark_mrhs(U, psi, nrhs, precision, nrep)
 
 
 def lgt_stout_smear(lat: Lattice, U, rho, nlevels, out=None):

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "lgt_ctx.h"
+#include "lgt_mrhs.h"
 
 using namespace lgt;
 
@@ -49,7 +50,6 @@ SolverOpts parse(const lgt_solver_params* p) {
   require(p->precision >= LGT_FP64 && p->precision <= LGT_MIXED_BF16, "unknown precision");
   require(p->even_odd == 1 || p->even_odd == 0, "even_odd must be 0 or 1");
   if (p->even_odd == 0) throw Error(LGT_ERR_UNSUPPORTED, "only the even/odd solver is implemented");
-  if (p->precision == LGT_MIXED_BF16) throw Error(LGT_ERR_UNSUPPORTED, "bfloat16 spinor storage is not implemented");
   require(std::isfinite(p->tol) && p->tol > 0.0, "tol must be positive");
   o.precision = p->precision;
   o.tol = p->tol;
@@ -131,9 +131,10 @@ lgt_status lgt_create(const lgt_geom* geom, void* hip_stream, lgt_ctx** out) {
     return LGT_ERR_INVALID_ARGUMENT;
   }
   const int64_t V = (int64_t)geom->dims[0] * geom->dims[1] * geom->dims[2] * geom->dims[3];
-  // 72 complex per site (links) must index within int32 in the kernels
-  if (V > (int64_t)1 << 26) {
-    g_create_error = "lattice too large (V > 2^26)";
+  // kernels address a field with 32-bit byte offsets: an FP64 half-lattice
+  // spinor (12 complex per site) must stay below 4 GiB
+  if (V <= 0 || (int64_t)12 * (V / 2) * (int64_t)sizeof(double2) >= ((int64_t)1 << 32)) {
+    g_create_error = "lattice too large (a spinor field must stay below 4 GiB: V < 44.7M sites)";
     return LGT_ERR_INVALID_ARGUMENT;
   }
   lgt_ctx* c = new (std::nothrow) lgt_ctx();
@@ -495,6 +496,10 @@ lgt_status lgt_cg_solve_batch(lgt_ctx* c, const void* U, int32_t n, const lgt_ba
   lgt_status s = guarded(c, [&] {
     require(U && items, "null pointer");
     require(n >= 1 && n <= 16, "a batch holds 1 to 16 right-hand sides");
+    if (params && params->precision == LGT_MIXED_BF16)
+      throw Error(LGT_ERR_UNSUPPORTED, "the batched solve has no BF16-storage variant (use LGT_MIXED_FP32)");
+    require((size_t)12 * c->vh * n * sizeof(double2) < ((size_t)1 << 32),
+            "batch too large: the batched spinor field must stay below 4 GiB (use fewer right-hand sides)");
     std::vector<double> kap(n);
     std::vector<const void*> phis(n);
     std::vector<void*> xs(n), ys(n);
@@ -555,6 +560,19 @@ lgt_status lgt_hop_benchmark(lgt_ctx* c, const void* U, const void* psi, int32_t
     Timer tm(c);
     for (int i = 0; i < nrep; ++i) once();
     *avg_ms = tm.stop() / nrep;
+  });
+}
+
+lgt_status lgt_hop_benchmark_mrhs(lgt_ctx* c, const void* U, const void* psi, int32_t nrhs, int32_t precision,
+                                  int32_t nrep, double* avg_ms) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(U && psi && avg_ms && nrep >= 1, "invalid argument");
+    require(nrhs >= 1 && nrhs <= kMaxRhs, "nrhs must be in [1, 16]");
+    require((size_t)12 * c->vh * nrhs * sizeof(double2) < ((size_t)1 << 32), "batched field above 4 GiB");
+    const bool f32 = precision != LGT_FP64;
+    pack_links(c, U, f32);
+    *avg_ms = c->bench_mhop(nrhs, f32, psi, nrep);
   });
 }
 

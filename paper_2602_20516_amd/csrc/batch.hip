@@ -368,3 +368,33 @@ std::vector<SolveStats> lgt_ctx::solve_batch(int nr, const double* kappas, const
   }
   return b.st;
 }
+
+double lgt_ctx::bench_mhop(int nr, bool f32, const void* psi, int nrep) {
+  BatchWork* w = batch_work(this, nr);
+  for (int k = 0; k < nr; ++k) LGT_HIP(launch_mpack(g, nr, k, (const double2*)psi, w->f[bPhi], stream));
+  const size_t h = (size_t)12 * vh * nr;
+  for (int k = 0; k < kMaxRhs; ++k) w->hvec[vOne * kMaxRhs + k] = 1.0;
+  LGT_HIP(hipMemcpyAsync(w->dvec, w->hvec, 8 * kMaxRhs * sizeof(double), hipMemcpyHostToDevice, stream));
+  const double* one = w->dvec + vOne * kMaxRhs;
+  if (f32) LGT_HIP(launch_convert_64_32((int)h, w->f[bPhi] + h, w->h[0], stream));
+  const Reduce red{w->partials, result, 0, w->npart, nullptr};
+  auto once = [&] {
+    if (f32) {
+      HopIn<float> hin{U32, w->h[0], w->h[0]};
+      LGT_HIP((launch_mhop_axpy<float, false>(g, nr, 0, hin, w->h[1], w->h[1], nullptr, nullptr, one, stream,
+                                               nullptr, nullptr, red)));
+    } else {
+      HopIn<double> hin{U64, w->f[bPhi] + h, w->f[bPhi] + h};
+      LGT_HIP((launch_mhop_axpy<double, false>(g, nr, 0, hin, w->f[bX], w->f[bX], nullptr, nullptr, one, stream,
+                                                nullptr, nullptr, red)));
+    }
+  };
+  once();  // warm-up
+  LGT_HIP(hipEventRecord(ev0, stream));
+  for (int i = 0; i < nrep; ++i) once();
+  LGT_HIP(hipEventRecord(ev1, stream));
+  LGT_HIP(hipEventSynchronize(ev1));
+  float ms = 0.f;
+  LGT_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+  return (double)ms / nrep;
+}

@@ -198,26 +198,27 @@ hipError_t launch_finalize(int mode, int nblk, Reduce red, SolverState* st, int 
   return hipGetLastError();
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_cg_xpay(int n, const R2<R>* __restrict__ r, R2<R>* __restrict__ p,
+template <typename R, typename T>
+__global__ __launch_bounds__(256) void k_cg_xpay(int n, const R2<R>* __restrict__ r, T* __restrict__ p,
                                                  const SolverState* st) {
-  if (st->done != kDoneRunning && st->done != kDoneUpdate) return;
+  if (st->done != kDoneRunning) return;
   const R beta = R(st->beta);
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const R2<R> rv = r[i];
-    R2<R> pv = p[i];
-    pv.x = rv.x + beta * pv.x;
-    pv.y = rv.y + beta * pv.y;
-    p[i] = pv;
+    const C<R> rv = ld<R>(r + i);
+    const C<R> pv = Store<R, T>::ld(p + i);
+    Store<R, T>::st(p + i, C<R>{rv.re + beta * pv.re, rv.im + beta * pv.im});
   }
 }
 
-template <typename R>
-hipError_t launch_cg_xpay(int n, const R2<R>* r, R2<R>* p, SolverState* st, hipStream_t s) {
+template <typename R, typename T>
+hipError_t launch_cg_xpay(int n, const R2<R>* r, T* p, SolverState* st, hipStream_t s) {
   const int nb = (n + 255) / 256;
-  hipLaunchKernelGGL((k_cg_xpay<R>), dim3(nb), dim3(256), 0, s, n, r, p, st);
+  hipLaunchKernelGGL((k_cg_xpay<R, T>), dim3(nb), dim3(256), 0, s, n, r, p, st);
   return hipGetLastError();
 }
+template hipError_t launch_cg_xpay<double, double2>(int, const double2*, double2*, SolverState*, hipStream_t);
+template hipError_t launch_cg_xpay<float, float2>(int, const float2*, float2*, SolverState*, hipStream_t);
+template hipError_t launch_cg_xpay<float, Bf16c>(int, const float2*, Bf16c*, SolverState*, hipStream_t);
 
 __global__ __launch_bounds__(256) void k_norm_dot(int n, const double2* __restrict__ a,
                                                   const double2* __restrict__ b, double* partials) {
@@ -325,34 +326,38 @@ hipError_t launch_mixed_update(int n, float2* xs, double2* x, double scale, hipS
 // Reliable update of the FP32 recursion: r = sigma r64 (FP64 residual scaled
 // to unit norm), and the search direction either restarted (p = r) or
 // rescaled to the new units (p *= pscale).
+template <typename T>
 __global__ __launch_bounds__(256) void k_rescale_residual(int n, const double2* __restrict__ r64, double sigma,
-                                                          float2* __restrict__ r, float2* __restrict__ p,
-                                                          int restart, double pscale) {
+                                                          float2* __restrict__ r, T* __restrict__ p, int restart,
+                                                          double bscale) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const double2 v = r64[i];
-    const float2 w = make_float2((float)(sigma * v.x), (float)(sigma * v.y));
-    r[i] = w;
+    const double rx = sigma * v.x, ry = sigma * v.y;
+    st<float>(r + i, C<float>{(float)rx, (float)ry});
     if (restart) {
-      p[i] = w;
+      Store<float, T>::st(p + i, C<float>{(float)rx, (float)ry});
     } else {
-      const float2 q = p[i];
-      p[i] = make_float2((float)(pscale * (double)q.x), (float)(pscale * (double)q.y));
+      const C<float> q = Store<float, T>::ld(p + i);
+      Store<float, T>::st(p + i, C<float>{(float)(rx + bscale * (double)q.re), (float)(ry + bscale * (double)q.im)});
     }
   }
 }
-hipError_t launch_rescale_residual(int n, const double2* r64, double sigma, float2* r, float2* p, int restart,
-                                   double pscale, hipStream_t s) {
-  hipLaunchKernelGGL(k_rescale_residual, dim3((n + 255) / 256), dim3(256), 0, s, n, r64, sigma, r, p, restart,
-                     pscale);
+template <typename T>
+hipError_t launch_rescale_residual(int n, const double2* r64, double sigma, float2* r, T* p, int restart,
+                                   double bscale, hipStream_t s) {
+  hipLaunchKernelGGL((k_rescale_residual<T>), dim3((n + 255) / 256), dim3(256), 0, s, n, r64, sigma, r, p, restart,
+                     bscale);
   return hipGetLastError();
 }
+template hipError_t launch_rescale_residual<float2>(int, const double2*, double, float2*, float2*, int, double,
+                                                    hipStream_t);
+template hipError_t launch_rescale_residual<Bf16c>(int, const double2*, double, float2*, Bf16c*, int, double,
+                                                   hipStream_t);
 
 template hipError_t launch_cg_init<double>(int, const double2*, double2*, double2*, double2*, SolverState*,
                                            Reduce, double, int, hipStream_t);
 template hipError_t launch_cg_init<float>(int, const float2*, float2*, float2*, float2*, SolverState*, Reduce,
                                           double, int, hipStream_t);
-template hipError_t launch_cg_xpay<double>(int, const double2*, double2*, SolverState*, hipStream_t);
-template hipError_t launch_cg_xpay<float>(int, const float2*, float2*, SolverState*, hipStream_t);
 
 
 }  // namespace lgt

@@ -152,12 +152,12 @@ __global__ __launch_bounds__(256) void k_hop_mrhs(Geom g, int nr, int nbp, int p
   if (active) {
     int c[4];
     cb_coords(g, p, cb, c);
-    const R2<R>* in = p ? hin.in_even : hin.in_odd;
+    const auto in = make_loader<R>(hin, g, p, nr);
     switch (mu) {
-      case 0: hop_dir<R, 0, DAG>(g, hin.gauge, in, p, cb, c, acc, nr, n); break;
-      case 1: hop_dir<R, 1, DAG>(g, hin.gauge, in, p, cb, c, acc, nr, n); break;
-      case 2: hop_dir<R, 2, DAG>(g, hin.gauge, in, p, cb, c, acc, nr, n); break;
-      default: hop_dir<R, 3, DAG>(g, hin.gauge, in, p, cb, c, acc, nr, n); break;
+      case 0: hop_dir<R, 0, DAG>(g, hin.gauge, in, p, cb, c, acc, n); break;
+      case 1: hop_dir<R, 1, DAG>(g, hin.gauge, in, p, cb, c, acc, n); break;
+      case 2: hop_dir<R, 2, DAG>(g, hin.gauge, in, p, cb, c, acc, n); break;
+      default: hop_dir<R, 3, DAG>(g, hin.gauge, in, p, cb, c, acc, n); break;
     }
   }
 #pragma unroll

@@ -142,15 +142,18 @@ struct lgt_ctx {
 
   // batched solves (batch.hip): nr right-hand sides with their own kappa
   BatchWork* batch = nullptr;
+  double bench_mhop(int nr, bool f32, const void* psi, int nrep);  // ms per multi-RHS hop launch
   std::vector<lgt::SolveStats> solve_batch(int nr, const double* kappas, const void* const* phis, void* const* Xs,
                                            void* const* Ys, const lgt::SolverOpts& o);
 
   double kappa = 0.0;  // hopping parameter of the current solve
  private:
-  void solve_M(bool dag, double2* z, const double2* b, double tol, int max_iter, bool mixed,
+  // precision: an lgt_precision value
+  void solve_M(bool dag, double2* z, const double2* b, double tol, int max_iter, int precision,
                double delta, lgt::SolveStats& st);
   int cg_normal64(bool dag, double2* z, const double2* rhs, double tol, int max_iter,
                   lgt::SolveStats& st);
+  template <typename T>  // storage of the FP32 recursion's t, w, p: float2 or lgt::Bf16c
   int cg_normal_mixed(bool dag, double2* z, const double2* rhs, double tol, int max_iter, double delta,
                       lgt::SolveStats& st);
   void apply_mhat_dag_mhat64(bool dag, const double2* x, double2* out);

@@ -52,6 +52,77 @@ template <typename R> __device__ __forceinline__ void st(R2<R>* p, C<R> a) {
   v.y = a.im;
   *p = v;
 }
+// Raw buffer resource over [base, base + bytes) (gfx9-family descriptor):
+// loads through it take a 32-bit per-lane offset plus a 32-bit uniform
+// offset and need no 64-bit address arithmetic; reads past the end return
+// zero rather than faulting.
+typedef __amdgpu_buffer_rsrc_t BufRsrc;
+__device__ __forceinline__ BufRsrc make_rsrc(const void* base, size_t bytes) {
+  const unsigned n = bytes < 0xffffffffull ? (unsigned)bytes : 0xffffffffu;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n, 0x00020000);
+}
+template <typename R> __device__ __forceinline__ C<R> ld_buf(BufRsrc r, unsigned voff, unsigned soff);
+template <> __device__ __forceinline__ C<float> ld_buf<float>(BufRsrc r, unsigned voff, unsigned soff) {
+  const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  return {v.x, v.y};
+}
+template <> __device__ __forceinline__ C<double> ld_buf<double>(BufRsrc r, unsigned voff, unsigned soff) {
+  const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  return {v.x, v.y};
+}
+
+// ---------------------------------------------------------------------------
+// Storage types.  A spinor element lives in HBM as R2<R> (the arithmetic
+// precision) or, for the inner solve with BF16-stored spinors, as Bf16c: a
+// complex number held as two bfloat16 values (the upper 16 bits of an IEEE
+// binary32), computed on in FP32.  Store<R, T> converts between the two.
+// ---------------------------------------------------------------------------
+struct Bf16c {
+  unsigned short re, im;
+};
+
+__device__ __forceinline__ float bf16_to_f32(unsigned h) { return __uint_as_float(h << 16); }
+// binary32 -> bfloat16 with round-to-nearest-even (NaN stays NaN)
+__device__ __forceinline__ unsigned f32_to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+template <typename R, typename T> struct Store;
+template <> struct Store<double, double2> {
+  static __device__ __forceinline__ C<double> ld(const double2* p) { return lgt::ld<double>(p); }
+  static __device__ __forceinline__ void st(double2* p, C<double> v) { lgt::st<double>(p, v); }
+  static __device__ __forceinline__ C<double> round(C<double> v) { return v; }
+  static __device__ __forceinline__ C<double> ld_buf(BufRsrc r, unsigned vo, unsigned so) {
+    return lgt::ld_buf<double>(r, vo, so);
+  }
+};
+template <> struct Store<float, float2> {
+  static __device__ __forceinline__ C<float> ld(const float2* p) { return lgt::ld<float>(p); }
+  static __device__ __forceinline__ void st(float2* p, C<float> v) { lgt::st<float>(p, v); }
+  static __device__ __forceinline__ C<float> round(C<float> v) { return v; }
+  static __device__ __forceinline__ C<float> ld_buf(BufRsrc r, unsigned vo, unsigned so) {
+    return lgt::ld_buf<float>(r, vo, so);
+  }
+};
+template <> struct Store<float, Bf16c> {
+  static __device__ __forceinline__ C<float> unpack(unsigned w) {
+    return {bf16_to_f32(w & 0xffffu), bf16_to_f32(w >> 16)};
+  }
+  static __device__ __forceinline__ C<float> ld(const Bf16c* p) { return unpack(*(const unsigned*)p); }
+  static __device__ __forceinline__ void st(Bf16c* p, C<float> v) {
+    *(unsigned*)p = f32_to_bf16(v.re) | (f32_to_bf16(v.im) << 16);
+  }
+  static __device__ __forceinline__ C<float> round(C<float> v) {
+    return {bf16_to_f32(f32_to_bf16(v.re)), bf16_to_f32(f32_to_bf16(v.im))};
+  }
+  static __device__ __forceinline__ C<float> ld_buf(BufRsrc r, unsigned vo, unsigned so) {
+    return unpack((unsigned)__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+  }
+};
+
 // Non-temporal store: output streams that are not re-read by this kernel.
 template <typename R> __device__ __forceinline__ void st_nt(R2<R>* p, C<R> a) {
   R2<R> v;

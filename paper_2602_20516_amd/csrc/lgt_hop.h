@@ -58,23 +58,49 @@ __device__ __forceinline__ void reconstruct(const C<R>* w, C<R>* acc) {
   }
 }
 
-// Both hops along MU for output site (p, cb) with coordinates c.  Spinor
-// element (k, site) of right-hand side n sits at (k*vh + site)*nr + n
-// (nr = 1, n = 0 for a single field).
-template <typename R, int MU, bool DAG>
-__device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__ gauge,
-                                        const R2<R>* __restrict__ in, int p, int cb, const int c[4],
-                                        C<R>* acc, int nr, int n) {
+// Input loaders: off(site, n) gives the per-lane byte offset of (site, rhs n)
+// once per neighbour, ld(off, k) spinor component k there (as C<R>).  All
+// loads go through buffer resources with 32-bit offsets, so a field must
+// stay below 4 GiB (the host checks 12 * vh * nr * 16 < 2^32).
+//
+// A plain stored field, element (k, site, n) at (k*vh + site)*nr + n.
+template <typename R, typename T>
+struct SpinorIn {
+  BufRsrc rs;
+  unsigned ks;  // component stride in bytes
+  unsigned nr;
+  __device__ __forceinline__ unsigned off(int site, int n) const {
+    return ((unsigned)site * nr + (unsigned)n) * (unsigned)sizeof(T);
+  }
+  __device__ __forceinline__ C<R> ld(unsigned o, int k) const { return Store<R, T>::ld_buf(rs, o, k * ks); }
+};
+
+// loader for the input parity of output parity p
+template <typename R, typename T>
+__device__ __forceinline__ SpinorIn<R, T> make_loader(const HopIn<R, T>& h, const Geom& g, int p, int nr) {
+  const unsigned ks = (unsigned)g.vh * (unsigned)nr * (unsigned)sizeof(T);
+  return SpinorIn<R, T>{make_rsrc(p ? h.in_even : h.in_odd, (size_t)12 * ks), ks, (unsigned)nr};
+}
+
+// Both hops along MU for output site (p, cb) with coordinates c, right-hand
+// side n of the loader's field.
+template <typename R, int MU, bool DAG, typename L>
+__device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__ gauge, const L& in, int p, int cb,
+                                        const int c[4], C<R>* acc, int n) {
   constexpr int SF = DAG ? +1 : -1;  // forward projector 1 + SF gamma
   constexpr int SB = -SF;
-  const int vh = g.vh;
+  constexpr unsigned E = sizeof(R2<R>);
+  const unsigned gs = (unsigned)g.vh * E;  // link element stride in bytes (uniform)
   C<R> psi[12], h[6], w[6];
   {  // forward: (1 + SF gamma) U_mu(x) psi(x + mu)
-    const int nf = cb_shift(g, c, MU, +1);
+    const unsigned of = in.off(cb_shift(g, c, MU, +1), n);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k] = ld<R>(in + ((size_t)k * vh + nf) * nr + n);
+    for (int k = 0; k < 12; ++k) psi[k] = in.ld(of, k);
     project<R, MU, SF>(psi, h);
-    const M3<R> U = load_m3<R>(gptr<R>(gauge, g, p, MU), vh, cb);
+    const BufRsrc ru = make_rsrc(gptr<R>(gauge, g, p, MU), (size_t)9 * gs);
+    M3<R> U;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) U.m[k] = ld_buf<R>(ru, (unsigned)cb * E, k * gs);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -93,10 +119,14 @@ __device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__
   }
   {  // backward: (1 + SB gamma) U_mu(x - mu)^dag psi(x - mu)
     const int nb = cb_shift(g, c, MU, -1);
+    const unsigned ob = in.off(nb, n);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k] = ld<R>(in + ((size_t)k * vh + nb) * nr + n);
+    for (int k = 0; k < 12; ++k) psi[k] = in.ld(ob, k);
     project<R, MU, SB>(psi, h);
-    const M3<R> U = load_m3<R>(gptr<R>(gauge, g, 1 - p, MU), vh, nb);
+    const BufRsrc ru = make_rsrc(gptr<R>(gauge, g, 1 - p, MU), (size_t)9 * gs);
+    M3<R> U;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) U.m[k] = ld_buf<R>(ru, (unsigned)nb * E, k * gs);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll

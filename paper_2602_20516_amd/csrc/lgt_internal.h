@@ -40,12 +40,13 @@ enum { kDoneRunning = 0, kDoneConverged = 1, kDoneMaxIter = 2, kDoneBreakdown = 
 enum Layout { kCanonical = 0, kPacked = 1 };
 
 // Arguments of a hop launch.  Half-fields are [12][vh] complex; a "full"
-// spinor is even half followed by odd half.
-template <typename R>
+// spinor is even half followed by odd half.  T is the storage type of the
+// input spinor (R2<R>, or Bf16c for BF16-stored spinors).
+template <typename R, typename T = R2<R>>
 struct HopIn {
   const R2<R>* gauge;  // packed links [2][4][9][vh]
-  const R2<R>* in_even;
-  const R2<R>* in_odd;
+  const T* in_even;
+  const T* in_odd;
 };
 
 // Host-visible progress of an iterative solve, in pinned host memory: the
@@ -102,23 +103,31 @@ hipError_t launch_pack(const Geom& g, int nc, const double2* canon, double2* out
 hipError_t launch_unpack(const Geom& g, int nc, const double2* packed, double2* canon, hipStream_t s);
 
 // Hop variants (kernels_hop.hip).  p_out in {0,1}: one parity; -1: both.
-// out = self + coef * H in   (self may be null)
-// guard: skip once the solve has finished; pap_partials: block 0 also forms
+// out = self + coef * H in   (self may be null); T: spinor storage type
+// guard: skip once the solve has stopped; pap_partials: block 0 also forms
 // pap and alpha from the previous launch's partials (see EpiAxpy::tail)
-template <typename R, bool DAG>
-hipError_t launch_hop_axpy(const Geom& g, int p_out, HopIn<R> hin, R2<R>* out_even, R2<R>* out_odd,
-                           const R2<R>* self_even, const R2<R>* self_odd, double coef, hipStream_t s,
-                           SolverState* guard = nullptr, const double* pap_partials = nullptr);
-// Schur step of CG: w = x + coef * H in on parity 1, block partials of |w|^2
-template <typename R, bool DAG>
-hipError_t launch_hop_schur_norm(const Geom& g, HopIn<R> hin, R2<R>* w, const R2<R>* x, double coef,
-                                 SolverState* st, Reduce red, hipStream_t s);
-// Schur dagger step fused with the CG update, then the finalize launch:
-// q = w + coef * H in;  x += alpha p;  r -= alpha q;  rr = |r|^2; beta, convergence
-template <typename R, bool DAG>
-hipError_t launch_hop_schur_cg(const Geom& g, HopIn<R> hin, const R2<R>* w, R2<R>* x, R2<R>* r,
-                               const R2<R>* p, double coef, SolverState* st, Reduce red,
-                               hipStream_t s);
+template <typename T> struct NoDeduce { using type = T; };  // keeps nullptr arguments out of deduction
+template <typename R, bool DAG, typename T = R2<R>>
+hipError_t launch_hop_axpy(const Geom& g, int p_out, HopIn<R, T> hin, T* out_even, T* out_odd,
+                           const typename NoDeduce<T>::type* self_even, const typename NoDeduce<T>::type* self_odd,
+                           double coef, hipStream_t s, SolverState* guard = nullptr,
+                           const double* pap_partials = nullptr);
+// One CG iteration on Mhat^dag Mhat (Mhat = 1 - kappa^2 H_oe H_eo, odd sites)
+// is four hop launches, the finalize and the direction update:
+//  (1) t = H p                                      launch_hop_axpy (guard)
+//  (2) w = p + coef H t, |w|^2 partials             launch_hop_schur_norm
+//  (3) t = H^dag w; block 0: alpha = rr / |w|^2    launch_hop_axpy with pap_partials
+//  (4) q = w + coef H^dag t; x += alpha p; r -= alpha q; |r|^2; finalize (rr,
+//      beta, stop)                                  launch_hop_schur_cg
+//  (5) p = r + beta p                               launch_cg_xpay
+// (for the dagger operator the roles of H and H^dag swap).  t, w, p are
+// stored as T; x and r as R2<R>.
+template <typename R, typename T, bool DAG>
+hipError_t launch_hop_schur_norm(const Geom& g, HopIn<R, T> hin, T* w, const T* x, double coef, SolverState* st,
+                                 Reduce red, hipStream_t s);
+template <typename R, typename T, bool DAG>
+hipError_t launch_hop_schur_cg(const Geom& g, HopIn<R, T> hin, const T* w, R2<R>* x, R2<R>* r, const T* p,
+                               double coef, SolverState* st, Reduce red, hipStream_t s);
 // Residual of the full operator: r = phi - (self + coef * H in) over both parities,
 // result[slot] = |r|^2
 template <bool DAG>
@@ -127,11 +136,14 @@ hipError_t launch_hop_residual(const Geom& g, HopIn<double> hin, const double2* 
                                int slot, hipStream_t s);
 
 // Vector kernels (kernels_field.hip).  n = number of complex elements.
+// p = r + beta p (p stored as T) while the solve runs; the iteration whose
+// finalize stopped the recursion leaves p alone (the reliable update forms
+// the next direction, see launch_rescale_residual)
+template <typename R, typename T>
+hipError_t launch_cg_xpay(int n, const R2<R>* r, T* p, SolverState* st, hipStream_t s);
 template <typename R>
 hipError_t launch_cg_init(int n, const R2<R>* b, R2<R>* r, R2<R>* p, R2<R>* x, SolverState* st,
                           Reduce red, double tol, int max_iter, hipStream_t s);
-template <typename R>
-hipError_t launch_cg_xpay(int n, const R2<R>* r, R2<R>* p, SolverState* st, hipStream_t s);
 // result[slot] = |a|^2 (and result[slot+1] = Re <a,b> if b != null)
 hipError_t launch_norm_dot(int n, const double2* a, const double2* b, Reduce red, int slot,
                            hipStream_t s);
@@ -143,9 +155,13 @@ hipError_t launch_zero32(int n, float2* y, hipStream_t s);
 hipError_t launch_convert_64_32(int n, const double2* x, float2* y, hipStream_t s);
 // mixed precision helpers
 hipError_t launch_mixed_update(int n, float2* xs, double2* x, double scale, hipStream_t s);  // x += scale xs; xs = 0
-// reliable update of the FP32 recursion: r = (float)(sigma r64); p = r (restart) or p *= pscale
-hipError_t launch_rescale_residual(int n, const double2* r64, double sigma, float2* r, float2* p, int restart,
-                                   double pscale, hipStream_t s);
+// reliable update of the FP32 recursion: r = (float)(sigma r64); then the
+// next search direction p = r (restart) or p = r + bscale p (bscale = beta
+// of the stopping iteration times the change of units), p stored as T
+// (float2 or Bf16c)
+template <typename T>
+hipError_t launch_rescale_residual(int n, const double2* r64, double sigma, float2* r, T* p, int restart,
+                                   double bscale, hipStream_t s);
 
 // Forces / gauge kernels (kernels_force.hip).  Gauge-type outputs: layout
 // kCanonical -> [V][4][3][3] complex128, kPacked -> [2][4][9][vh].

@@ -102,19 +102,19 @@ void lgt_ctx::apply_mhat_dag_mhat64(bool dag, const double2* x, double2* out) {
   }
 }
 
-template <typename R, bool DAG>
-static void cg_iteration(const Geom& g, const R2<R>* gauge, double kappa, R2<R>* t, R2<R>* w, R2<R>* x,
-                         R2<R>* r, R2<R>* p, SolverState* st, Reduce red, hipStream_t s, int n) {
+// One CG iteration on Mhat^dag Mhat: four hop launches, the finalize and
+// the direction update.  t, w, p stored as T; x, r as R2<R>.
+template <typename R, typename T, bool DAG>
+static void cg_iteration(const Geom& g, const R2<R>* gauge, double kappa, T* t, T* w, R2<R>* x, R2<R>* r, T* p,
+                         SolverState* st, Reduce red, hipStream_t s, int n) {
   const double k2 = -kappa * kappa;
-  HopIn<R> h1{gauge, p, p};
-  LGT_HIP((launch_hop_axpy<R, DAG>(g, 0, h1, t, t, nullptr, nullptr, 1.0, s, st)));
-  HopIn<R> h2{gauge, t, t};
-  LGT_HIP((launch_hop_schur_norm<R, DAG>(g, h2, w, p, k2, st, red, s)));
-  HopIn<R> h3{gauge, w, w};  // block 0 also forms alpha from the |w|^2 partials
-  LGT_HIP((launch_hop_axpy<R, !DAG>(g, 0, h3, t, t, nullptr, nullptr, 1.0, s, st, red.partials)));
-  HopIn<R> h4{gauge, t, t};
-  LGT_HIP((launch_hop_schur_cg<R, !DAG>(g, h4, w, x, r, p, k2, st, red, s)));
-  LGT_HIP((launch_cg_xpay<R>(n, r, p, st, s)));
+  LGT_HIP((launch_hop_axpy<R, DAG, T>(g, 0, HopIn<R, T>{gauge, p, p}, t, t, nullptr, nullptr, 1.0, s, st)));
+  LGT_HIP((launch_hop_schur_norm<R, T, DAG>(g, HopIn<R, T>{gauge, t, t}, w, p, k2, st, red, s)));
+  // block 0 also forms alpha from the |w|^2 partials
+  LGT_HIP((launch_hop_axpy<R, !DAG, T>(g, 0, HopIn<R, T>{gauge, w, w}, t, t, nullptr, nullptr, 1.0, s, st,
+                                         red.partials)));
+  LGT_HIP((launch_hop_schur_cg<R, T, !DAG>(g, HopIn<R, T>{gauge, t, t}, w, x, r, p, k2, st, red, s)));
+  LGT_HIP((launch_cg_xpay<R, T>(n, r, p, st, s)));
 }
 
 // CG on Mhat^dag Mhat z = rhs (odd half fields), FP64.  Returns the state's done code.
@@ -127,8 +127,8 @@ int lgt_ctx::cg_normal64(bool dag, double2* z, const double2* rhs, double tol, i
   LGT_HIP(launch_cg_init<double>(n, rhs, r, p, z, state, red(), tol, max_iter, stream));
   for (int iter0 = 0;;) {
     drive(iter0, [&] {
-      if (dag) cg_iteration<double, true>(g, U64, kappa, t, w, z, r, p, state, red(), stream, n);
-      else cg_iteration<double, false>(g, U64, kappa, t, w, z, r, p, state, red(), stream, n);
+      if (dag) cg_iteration<double, double2, true>(g, U64, kappa, t, w, z, r, p, state, red(), stream, n);
+      else cg_iteration<double, double2, false>(g, U64, kappa, t, w, z, r, p, state, red(), stream, n);
     });
     LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
     sync();
@@ -154,17 +154,24 @@ int lgt_ctx::cg_normal64(bool dag, double2* z, const double2* rhs, double tol, i
 // and posts the stop to the host (see drive).  Letting it run on until the
 // host looks would let a fast-converging recursion go orders of magnitude
 // past the accuracy FP32 can hold, after which the kept direction no longer
-// matches the true residual and CG diverges.  After a breakdown the
-// direction is restarted.
+// matches the true residual and CG diverges.  The stopping iteration skips
+// its direction update; the update forms it from the true residual,
+// p = r_new + beta p_old (beta of that iteration, p_old rescaled to the new
+// units), which keeps the direction consistent even when the recursion's
+// own residual has drifted (BF16-stored intermediates drift by ~2^-9 per
+// iteration).  After a breakdown the direction is restarted, p = r_new.
+// T: storage of the recursion's spinors t, w, p (float2, or Bf16c for the
+// BF16-storage variant); x and r stay FP32.
+template <typename T>
 int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double tol, int max_iter, double delta,
                              SolveStats& stt) {
   const int n = (int)half_elems();
   ensure_u32();
-  float2* ts = h32(0);
-  float2* ws = h32(1);
+  T* ts = reinterpret_cast<T*>(h32(0));  // h32 buffers hold float2; Bf16c uses half of each
+  T* ws = reinterpret_cast<T*>(h32(1));
   float2* xs = h32(2);
   float2* rs = h32(3);
-  float2* ps = h32(4);
+  T* ps = reinterpret_cast<T*>(h32(4));
   double2* r64 = f64(kW2) + half_elems();
   LGT_HIP(launch_zero64(n, z, stream));
   LGT_HIP(launch_norm_dot(n, rhs, nullptr, red(), 0, stream));
@@ -175,7 +182,7 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
   const double rr_target = tol * tol * bb;
   double sigma = 1.0 / std::sqrt(bb);
   LGT_HIP(launch_zero32(n, xs, stream));
-  LGT_HIP(launch_rescale_residual(n, rhs, sigma, rs, ps, 1, 1.0, stream));
+  LGT_HIP(launch_rescale_residual(n, rhs, sigma, rs, ps, 1, 0.0, stream));
   SolverState s{};
   auto write_state = [&](int iter) {
     s = SolverState{};
@@ -193,8 +200,8 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
   write_state(0);
   for (;;) {
     drive(s.iter, [&] {
-      if (dag) cg_iteration<float, true>(g, U32, kappa, ts, ws, xs, rs, ps, state, red(), stream, n);
-      else cg_iteration<float, false>(g, U32, kappa, ts, ws, xs, rs, ps, state, red(), stream, n);
+      if (dag) cg_iteration<float, T, true>(g, U32, kappa, ts, ws, xs, rs, ps, state, red(), stream, n);
+      else cg_iteration<float, T, false>(g, U32, kappa, ts, ws, xs, rs, ps, state, red(), stream, n);
     });
     LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
     sync();
@@ -207,7 +214,7 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
     }
     // the recursion stopped for an update (or broke down): fold, recompute
     // the FP64 residual, rescale
-    const int restart = s.done == kDoneBreakdown ? 1 : 0;  // its last direction update did not happen
+    const int restart = s.done == kDoneBreakdown ? 1 : 0;
     LGT_HIP(launch_mixed_update(n, xs, z, 1.0 / sigma, stream));
     apply_mhat_dag_mhat64(dag, z, r64);          // r64 = A z
     LGT_HIP(launch_xmy64(n, rhs, r64, stream));  // r64 = rhs - A z
@@ -221,13 +228,13 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
       return kDoneConverged;
     }
     const double sigma_new = 1.0 / std::sqrt(rr64);
-    LGT_HIP(launch_rescale_residual(n, r64, sigma_new, rs, ps, restart, sigma_new / sigma, stream));
+    LGT_HIP(launch_rescale_residual(n, r64, sigma_new, rs, ps, restart, s.beta * sigma_new / sigma, stream));
     sigma = sigma_new;
     write_state(s.iter);
   }
 }
 
-void lgt_ctx::solve_M(bool dag, double2* z, const double2* b, double tol, int max_iter, bool mixed,
+void lgt_ctx::solve_M(bool dag, double2* z, const double2* b, double tol, int max_iter, int precision,
                       double delta, SolveStats& stt) {
   const size_t h = half_elems();
   const double2* be = b;
@@ -246,8 +253,9 @@ void lgt_ctx::solve_M(bool dag, double2* z, const double2* b, double tol, int ma
     hop<double, true>(g, 1, U64, te, rhs, bp, -k * k, stream);
   }
   double2* zo = z + h;
-  const int code = mixed ? cg_normal_mixed(dag, zo, rhs, tol, max_iter, delta, stt)
-                         : cg_normal64(dag, zo, rhs, tol, max_iter, stt);
+  const int code = precision == LGT_MIXED_FP32   ? cg_normal_mixed<float2>(dag, zo, rhs, tol, max_iter, delta, stt)
+                   : precision == LGT_MIXED_BF16 ? cg_normal_mixed<Bf16c>(dag, zo, rhs, tol, max_iter, delta, stt)
+                                                 : cg_normal64(dag, zo, rhs, tol, max_iter, stt);
   if (code == kDoneBreakdown) throw Error(LGT_ERR_NONFINITE, "CG breakdown (non-finite or zero curvature)");
   if (code == kDoneMaxIter) stt.converged = false;
   if (dag) hop<double, true>(g, 0, U64, zo, z, be, k, stream);
@@ -267,12 +275,11 @@ SolveStats lgt_ctx::solve_ddagd(const double2* phi, double2* X, double2* Y, cons
     st.true_res = 0.0;
     return st;
   }
-  const bool mixed = o.precision != LGT_FP64;
   // inner tolerance: the two Schur solves and D^dag D compound their
   // residuals, so each aims a little below the requested true residual
   const double tol_in = o.tol * 0.25;
-  solve_M(true, Y, phi, tol_in, o.max_iter, mixed, o.delta, st);
-  solve_M(false, X, Y, tol_in, o.max_iter, mixed, o.delta, st);
+  solve_M(true, Y, phi, tol_in, o.max_iter, o.precision, o.delta, st);
+  solve_M(false, X, Y, tol_in, o.max_iter, o.precision, o.delta, st);
   double2* r = f64(kRes);
   HopIn<double> hin{U64, nullptr, nullptr};
   const size_t h = half_elems();
@@ -288,8 +295,8 @@ SolveStats lgt_ctx::solve_ddagd(const double2* phi, double2* X, double2* Y, cons
     // defect correction: D^dag D e = r, X += e
     double2* ytmp = f64(kYtmp);
     double2* e = f64(kE);
-    solve_M(true, ytmp, r, tol_in, o.max_iter, mixed, o.delta, st);
-    solve_M(false, e, ytmp, tol_in, o.max_iter, mixed, o.delta, st);
+    solve_M(true, ytmp, r, tol_in, o.max_iter, o.precision, o.delta, st);
+    solve_M(false, e, ytmp, tol_in, o.max_iter, o.precision, o.delta, st);
     LGT_HIP(launch_axpy64(nf, 1.0, e, X, stream));
   }
   if (st.true_res > o.tol) st.converged = false;

@@ -50,7 +50,9 @@ def test_struct_layout_matches_c(tmp_path):
 
 
 @pytest.mark.parametrize("dims,bc", [((4, 4, 3, 4), -1), ((0, 4, 4, 4), -1), ((4, 4, 4, 4), 0),
-                                     ((4, 4, 4, 1), 1)])
+                                     ((4, 4, 4, 1), 1),
+                                     # FP64 half-lattice spinor of 4 GiB or more (32-bit field offsets)
+                                     ((64, 64, 64, 172), -1)])
 def test_create_rejects_bad_geometry_before_touching_the_device(dims, bc):
     from paper_2602_20516_amd import _lib
     lib = _lib.load()

@@ -84,3 +84,12 @@ def test_batch_matches_single_solves_16(lgt, precision):
         assert st[i]["true_rel_residual"] <= 1e-10
         assert rel_err(to_host(Xs[i]), to_host(X1)) < 1e-8
         assert rel_err(to_host(Ys[i]), items[i][1]) < 1e-8
+
+
+def test_batch_rejects_bf16_storage(lgt):
+    dims = (4, 4, 4, 4)
+    u, items = workload(dims)
+    lat = lgt.Lattice(dims)
+    with pytest.raises(lgt.LGTError):
+        lat.cg_solve_batch(to_dev(u), [to_dev(e) for _, e in items[:2]], [k for k, _ in items[:2]],
+                           lgt.Params(precision="mixed_bf16"))

@@ -89,6 +89,7 @@ def test_bilinear_adjoint_full(c2):
     ("mixed_fp32", 1e-13, 1e-11),  # mixed precision reaches the same FP64 residual
     ("fp64", 1e-10, 1e-8),         # at the workload's own tolerance (solver-limited, reported)
     ("mixed_fp32", 1e-10, 1e-8),
+    ("mixed_bf16", 1e-13, 1e-11),  # BF16-stored inner spinors: same FP64 residual, same gate
 ])
 def test_fermion_force_vs_stored_oracle(c2, precision, tol, gate):
     g, lgt = c2["gold"], c2["lgt"]

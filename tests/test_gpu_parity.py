@@ -180,8 +180,9 @@ def test_cg_solve_heat_bath(lgt):
     assert abs(sf - ee) / ee < 1e-12
 
 
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
 @pytest.mark.parametrize("kappa", [0.10, 0.135])
-def test_mixed_cg_fast_and_slow_convergence(lgt, kappa):
+def test_mixed_cg_fast_and_slow_convergence(lgt, kappa, precision):
     """Mixed solve on smooth 4^4 links: at kappa 0.10 the FP32 recursion
     gains many digits per 16 iterations, so its reliable-update stop has to
     come from the device, not from the host's chunk boundaries."""
@@ -189,15 +190,15 @@ def test_mixed_cg_fast_and_slow_convergence(lgt, kappa):
     u, eta = li.random_links(dims, 0.3, 401), li.gaussian_spinor(dims, 402)
     phi = dirac.dslash_dag(u, eta, kappa)
     lat = lgt.Lattice(dims)
-    X, Y, st = lat.cg_solve(to_dev(u), to_dev(phi), kappa, lgt.Params(precision="mixed_fp32", tol=1e-12))
-    say("mixed cg", kappa, st)
+    X, Y, st = lat.cg_solve(to_dev(u), to_dev(phi), kappa, lgt.Params(precision=precision, tol=1e-12))
+    say("mixed cg", precision, kappa, st)
     assert st["true_rel_residual"] <= 1e-12
     x_ref, _, _, _ = solver.solve_ddag_d(u, phi, kappa, tol=1e-14)
     assert rel_err(to_host(X), x_ref) < 1e-9
     assert rel_err(to_host(Y), eta) < 1e-9
 
 
-@pytest.mark.parametrize("precision,gate", [("fp64", 1e-11), ("mixed_fp32", 1e-9)])
+@pytest.mark.parametrize("precision,gate", [("fp64", 1e-11), ("mixed_fp32", 1e-9), ("mixed_bf16", 1e-9)])
 def test_fermion_force(lgt, precision, gate):
     dims = (4, 4, 4, 4)
     u, eta = li.random_links(dims, 0.5, 101), li.gaussian_spinor(dims, 102)
