@@ -17,7 +17,7 @@ std::string g_create_error;
 
 enum { kPhi = 0, kX = 1, kY = 2, kStageA = 11, kStageB = 12 };
 // packed gauge scratch used here (see smear.hip): thin links, smeared output, gradient
-enum { kThin = 6, kSmeared = 8, kGradIn = 9 };
+enum { kThin = 6, kSmeared = 8, kGradIn = 9, kU0 = 10, kP0 = 11 };
 
 template <typename F>
 lgt_status guarded(lgt_ctx* ctx, F&& f) {
@@ -378,10 +378,13 @@ static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double b
     SolveStats all;
     double sf0 = 0.0, sf1 = 0.0;
 
-    LGT_HIP(launch_kinetic(c->g, c->P64, kPacked, c->red(), 0, c->stream));
-    c->read_results(1);
-    const double k0 = c->host_result[0];
-    const double sg0 = gauge_action(c, beta, thin);
+    // start of the trajectory, kept for the per-site differences of K and S_G
+    double2* u0 = dH ? c->g64(kU0) : nullptr;
+    double2* p0 = dH ? c->g64(kP0) : nullptr;
+    if (dH) {
+      LGT_HIP(launch_copy64(72 * c->vh, thin, u0, c->stream));
+      LGT_HIP(launch_copy64(72 * c->vh, c->P64, p0, c->stream));
+    }
 
     auto kick = [&](double h, bool first, bool last) {
       double* sfp = first ? &sf0 : (last ? &sf1 : nullptr);
@@ -406,11 +409,16 @@ static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double b
       const bool last = k == nsteps - 1;
       kick(last ? 0.5 * dt : dt, false, last);
     }
-    LGT_HIP(launch_kinetic(c->g, c->P64, kPacked, c->red(), 0, c->stream));
-    c->read_results(1);
-    const double k1 = c->host_result[0];
-    const double sg1 = gauge_action(c, beta, thin);
-    if (dH) *dH = (k1 - k0) + (sg1 - sg0) + (sf1 - sf0);
+    if (dH) {
+      // Delta K and Delta S_G as sums of per-link / per-site differences:
+      // their rounding error scales with Delta H, not with K or S_G
+      LGT_HIP(launch_kinetic(c->g, c->P64, kPacked, c->red(), 0, c->stream, p0));
+      LGT_HIP(launch_plaquette(c->g, thin, c->red(), 1, c->stream, u0));
+      c->read_results(2);
+      const double dk = c->host_result[0];
+      const double dsg = -beta / 3.0 * c->host_result[1];
+      *dH = dk + dsg + (sf1 - sf0);
+    }
     LGT_HIP(launch_unpack(c->g, 36, thin, (double2*)U, c->stream));
     LGT_HIP(launch_unpack(c->g, 36, c->P64, (double2*)P, c->stream));
     fill_stats(stats, all, tm.stop());

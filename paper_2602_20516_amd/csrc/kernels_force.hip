@@ -175,75 +175,97 @@ hipError_t launch_gauge_force(const Geom& g, const double2* U, double beta, int 
 }
 
 // sum over sites and mu<nu of Re tr P_mu,nu(x)
-__global__ __launch_bounds__(256) void k_plaquette(Geom g, const double2* __restrict__ U, double* partials) {
+// sum over plaquettes of Re tr P_mu,nu(x) at the site of this thread
+__device__ __forceinline__ double site_plaquettes(const Geom& g, const double2* __restrict__ U, const int c[4]) {
+  double acc = 0.0;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    int xpm[4];
+    shifted(g, c, mu, +1, xpm);
+    const M3<double> a = link_at(U, g, c, mu);
+#pragma unroll
+    for (int nu = mu + 1; nu < 4; ++nu) {
+      int xpn[4];
+      shifted(g, c, nu, +1, xpn);
+      const M3<double> ab = mmul(a, link_at(U, g, xpm, nu));
+      const M3<double> dc = mmul(link_at(U, g, c, nu), link_at(U, g, xpn, mu));
+      // Re tr(A B C^dag D^dag) = Re tr((AB)(DC)^dag)
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) t += ab.m[k].re * dc.m[k].re + ab.m[k].im * dc.m[k].im;
+      acc += t;
+    }
+  }
+  return acc;
+}
+
+// Sum of Re tr P over all plaquettes of U, or (Uold != null) the sum of the
+// per-site differences U minus Uold, which keeps the rounding error of a
+// trajectory's Delta S_G proportional to Delta S_G rather than to S_G.
+__global__ __launch_bounds__(256) void k_plaquette(Geom g, const double2* __restrict__ U,
+                                                   const double2* __restrict__ Uold, double* partials) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int s = lb * 256 + threadIdx.x;
   double acc = 0.0;
   if (s < 2 * g.vh) {
     int c[4];
     lex_coords(g, s, c);
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-      int xpm[4];
-      shifted(g, c, mu, +1, xpm);
-      const M3<double> a = link_at(U, g, c, mu);
-#pragma unroll
-      for (int nu = mu + 1; nu < 4; ++nu) {
-        int xpn[4];
-        shifted(g, c, nu, +1, xpn);
-        const M3<double> ab = mmul(a, link_at(U, g, xpm, nu));
-        const M3<double> dc = mmul(link_at(U, g, c, nu), link_at(U, g, xpn, mu));
-        // Re tr(A B C^dag D^dag) = Re tr((AB)(DC)^dag)
-        double t = 0.0;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) t += ab.m[k].re * dc.m[k].re + ab.m[k].im * dc.m[k].im;
-        acc += t;
-      }
-    }
+    acc = site_plaquettes(g, U, c);
+    if (Uold) acc -= site_plaquettes(g, Uold, c);
   }
   double v[1] = {acc};
   block_partials<256, 1>(v, partials, lb);
 }
 
-hipError_t launch_plaquette(const Geom& g, const double2* U, Reduce red, int slot, hipStream_t s) {
+hipError_t launch_plaquette(const Geom& g, const double2* U, Reduce red, int slot, hipStream_t s,
+                            const double2* Uold) {
   const int nb = (2 * g.vh + 255) / 256;
   if (nb > red.capacity) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_plaquette, dim3(nb), dim3(256), 0, s, g, U, red.partials);
+  hipLaunchKernelGGL(k_plaquette, dim3(nb), dim3(256), 0, s, g, U, Uold, red.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_finalize(kFinResult1, nb, red, nullptr, slot, 0.0, 0, s);
 }
 
-// -sum Re tr(P P) over all links
-__global__ __launch_bounds__(256) void k_kinetic(Geom g, const double2* __restrict__ P, int layout,
-                                                 double* partials) {
+// Re tr(P P) of link t of a gauge-type field in either layout
+__device__ __forceinline__ double link_trsq(const Geom& g, const double2* __restrict__ P, int layout, int t) {
+  M3<double> m;
+  if (layout == kCanonical) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m.m[k] = ld<double>(P + (size_t)t * 9 + k);
+  } else {
+    const int cb = t % g.vh, pm = t / g.vh;  // pm = parity*4 + mu
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m.m[k] = ld<double>(P + ((size_t)pm * 9 + k) * g.vh + cb);
+  }
+  double tr = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) tr += (m.m[3 * i + j] * m.m[3 * j + i]).re;
+  return tr;
+}
+
+// -sum Re tr(P P) over all links, or (Pold != null, same layout) the sum of
+// the per-link differences P minus Pold
+__global__ __launch_bounds__(256) void k_kinetic(Geom g, const double2* __restrict__ P,
+                                                 const double2* __restrict__ Pold, int layout, double* partials) {
   const int nlink = 8 * g.vh;
   double acc = 0.0;
   for (int t = blockIdx.x * 256 + threadIdx.x; t < nlink; t += gridDim.x * 256) {
-    M3<double> m;
-    if (layout == kCanonical) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) m.m[k] = ld<double>(P + (size_t)t * 9 + k);
-    } else {
-      const int cb = t % g.vh, pm = t / g.vh;  // pm = parity*4 + mu
-#pragma unroll
-      for (int k = 0; k < 9; ++k) m.m[k] = ld<double>(P + ((size_t)pm * 9 + k) * g.vh + cb);
-    }
-    double tr = 0.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) tr += (m.m[3 * i + j] * m.m[3 * j + i]).re;
-    acc -= tr;
+    double d = -link_trsq(g, P, layout, t);
+    if (Pold) d += link_trsq(g, Pold, layout, t);
+    acc += d;
   }
   double v[1] = {acc};
   block_partials<256, 1>(v, partials, blockIdx.x);
 }
 
-hipError_t launch_kinetic(const Geom& g, const double2* P, int layout, Reduce red, int slot, hipStream_t s) {
+hipError_t launch_kinetic(const Geom& g, const double2* P, int layout, Reduce red, int slot, hipStream_t s,
+                          const double2* Pold) {
   int nb = (8 * g.vh + 255) / 256;
   if (nb > 1024) nb = 1024;
-  hipLaunchKernelGGL(k_kinetic, dim3(nb), dim3(256), 0, s, g, P, layout, red.partials);
+  hipLaunchKernelGGL(k_kinetic, dim3(nb), dim3(256), 0, s, g, P, Pold, layout, red.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_finalize(kFinResult1, nb, red, nullptr, slot, 0.0, 0, s);

@@ -171,11 +171,14 @@ hipError_t launch_bilinear_force(const Geom& g, const double2* U, const double2*
                                  void* out, int layout, hipStream_t s);
 hipError_t launch_gauge_force(const Geom& g, const double2* U, double beta, int mode, double dt,
                               void* out, int layout, hipStream_t s);
-// result[slot] = sum_x sum_{mu<nu} Re tr P_mu,nu(x)
-hipError_t launch_plaquette(const Geom& g, const double2* U, Reduce red, int slot, hipStream_t s);
-// result[slot] = -sum Re tr P^2 over a gauge-type field of either layout
+// result[slot] = sum_x sum_{mu<nu} Re tr P_mu,nu(x); with Uold, the sum of
+// the per-site differences of that quantity between U and Uold
+hipError_t launch_plaquette(const Geom& g, const double2* U, Reduce red, int slot, hipStream_t s,
+                            const double2* Uold = nullptr);
+// result[slot] = -sum Re tr P^2 over a gauge-type field of either layout;
+// with Pold (same layout), the sum of the per-link differences P minus Pold
 hipError_t launch_kinetic(const Geom& g, const double2* P, int layout, Reduce red, int slot,
-                          hipStream_t s);
+                          hipStream_t s, const double2* Pold = nullptr);
 // U <- reunit(exp(dt P) U), both in `layout`; U32 (packed FP32 copy) refreshed if non-null
 hipError_t launch_link_update(const Geom& g, double2* U, const double2* P, double dt, int layout,
                               float2* U32, hipStream_t s);
