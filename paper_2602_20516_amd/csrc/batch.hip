@@ -33,6 +33,8 @@ struct BatchWork {
   double* hvec = nullptr;   // pinned mirror
   int* dint = nullptr;      // device restart flags
   int* hint = nullptr;
+  int G[2] = {0, 0};        // right-hand sides per hop block, tuned per precision (FP32, FP64) for tuned_nr
+  int tuned_nr = 0;
 };
 
 static void free_batch(BatchWork* w) {
@@ -76,13 +78,60 @@ static BatchWork* batch_work(lgt_ctx* c, int nr) {
   }
   LGT_HIP(hipMalloc(&w->st, sizeof(BatchState)));
   LGT_HIP(hipHostMalloc(&w->hst, sizeof(BatchState), hipHostMallocDefault));
-  w->npart = (size_t)mrhs_hop_blocks(c->g, nr, -1) * kMaxRhs + 1024 * kMaxRhs;
+  w->npart = (size_t)std::max(mrhs_hop_blocks(c->g, -1), 1024) * kMaxRhs;
   LGT_HIP(hipMalloc(&w->partials, w->npart * sizeof(double)));
   LGT_HIP(hipMalloc(&w->dvec, 8 * kMaxRhs * sizeof(double)));
   LGT_HIP(hipHostMalloc(&w->hvec, 8 * kMaxRhs * sizeof(double), hipHostMallocDefault));
   LGT_HIP(hipMalloc(&w->dint, kMaxRhs * sizeof(int)));
   LGT_HIP(hipHostMalloc(&w->hint, kMaxRhs * sizeof(int), hipHostMallocDefault));
   return w;
+}
+
+// Autotuner of the batched hop's group size G (right-hand sides per block):
+// large G loads the links fewer times, small G launches more blocks (more
+// waves to hide latency on small lattices).  Every G that gives a distinct
+// number of groups is timed once per context, right-hand-side count and
+// precision with HIP events on the context stream; the fastest is kept.
+static void tune_group_size(lgt_ctx* c, BatchWork* w, int nr, bool f32) {
+  if (w->tuned_nr != nr) {
+    w->G[0] = w->G[1] = 0;
+    w->tuned_nr = nr;
+  }
+  int& G = w->G[f32 ? 0 : 1];
+  if (G > 0) return;
+  if (f32) c->ensure_u32();
+  const Reduce red{w->partials, c->result, 0, w->npart, nullptr};
+  const double* coef = w->dvec;  // any finite values: only the time is used
+  double best = 1e30;
+  int prev_groups = 0;
+  for (int gsz = nr; gsz >= 1; --gsz) {
+    const int ngroups = (nr + gsz - 1) / gsz;
+    if (ngroups == prev_groups) continue;
+    prev_groups = ngroups;
+    auto once = [&] {
+      if (f32) {
+        HopIn<float> hin{c->U32, w->h[0], w->h[0]};
+        LGT_HIP((launch_mhop_axpy<float, false>(c->g, nr, gsz, 0, hin, w->h[1], w->h[1], nullptr, nullptr, coef,
+                                                 c->stream, nullptr, nullptr, red)));
+      } else {
+        HopIn<double> hin{c->U64, w->f[bW0], w->f[bW0]};
+        LGT_HIP((launch_mhop_axpy<double, false>(c->g, nr, gsz, 0, hin, w->f[bW1], w->f[bW1], nullptr, nullptr,
+                                                  coef, c->stream, nullptr, nullptr, red)));
+      }
+    };
+    once();
+    once();
+    LGT_HIP(hipEventRecord(c->ev0, c->stream));
+    for (int i = 0; i < 8; ++i) once();
+    LGT_HIP(hipEventRecord(c->ev1, c->stream));
+    LGT_HIP(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    LGT_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    if (ms < best) {
+      best = ms;
+      G = gsz;
+    }
+  }
 }
 
 namespace {
@@ -96,6 +145,8 @@ struct BatchSolver {
   std::vector<SolveStats> st;  // per right-hand side
 
   Reduce red() const { return Reduce{w->partials, c->result, 0, w->npart, c->mbox_dev}; }
+  template <typename R>
+  int gsize() const { return w->G[sizeof(R) == 8 ? 1 : 0]; }
   size_t halfn() const { return (size_t)12 * c->vh * nr; }
   double* vec(int slot) const { return w->dvec + slot * kMaxRhs; }
   double2* F(int i) const { return w->f[i]; }
@@ -119,7 +170,7 @@ struct BatchSolver {
   void mhop(int p_out, const R2<R>* gauge, const R2<R>* in, R2<R>* out, const R2<R>* self, const double* coef,
             BatchState* guard = nullptr, const double* pap = nullptr) {
     HopIn<R> hin{gauge, in, in};
-    LGT_HIP((launch_mhop_axpy<R, DAG>(c->g, nr, p_out, hin, out, out, self, self, coef, c->stream, guard, pap,
+    LGT_HIP((launch_mhop_axpy<R, DAG>(c->g, nr, gsize<R>(), p_out, hin, out, out, self, self, coef, c->stream, guard, pap,
                                        red())));
   }
 
@@ -145,11 +196,12 @@ struct BatchSolver {
     const size_t n = halfn();
     mhop<R, DAG>(0, gauge, p, t, nullptr, vec(vOne), w->st);
     HopIn<R> h2{gauge, t, t};
-    LGT_HIP((launch_mhop_schur_norm<R, DAG>(c->g, nr, h2, wv, p, vec(vMK2), w->st, red(), c->stream)));
+    LGT_HIP((launch_mhop_schur_norm<R, DAG>(c->g, nr, gsize<R>(), h2, wv, p, vec(vMK2), w->st, red(), c->stream)));
     mhop<R, !DAG>(0, gauge, wv, t, nullptr, vec(vOne), w->st, w->partials);
     HopIn<R> h4{gauge, t, t};
-    LGT_HIP((launch_mhop_schur_cg<R, !DAG>(c->g, nr, h4, wv, x, r, p, vec(vMK2), w->st, red(), c->stream)));
-    LGT_HIP(launch_mxpay<R>(n, nr, r, p, w->st, c->stream));
+    LGT_HIP((launch_mhop_schur_cg<R, !DAG>(c->g, nr, gsize<R>(), h4, wv, x, r, p, vec(vMK2), w->st, red(),
+                                            c->stream)));
+    LGT_HIP(launch_mxpay<R>(c->vh, nr, r, p, w->st, c->stream));
   }
 
   void cg64(bool dag, double2* z, const double2* rhs, double tol) {
@@ -158,7 +210,7 @@ struct BatchSolver {
     double2* r = F(bW2) + n;
     double2* p = F(bW3) + n;
     double2* wv = F(bW4) + n;
-    LGT_HIP(launch_mcg_init64(n, nr, rhs, r, p, z, w->st, red(), tol, o.max_iter, c->stream));
+    LGT_HIP(launch_mcg_init64(c->vh, nr, rhs, r, p, z, w->st, red(), tol, o.max_iter, c->stream));
     for (int iter0 = 0;;) {
       c->drive(iter0, [&] {
         if (dag) iteration<double, true>(c->U64, t, wv, z, r, p);
@@ -186,7 +238,7 @@ struct BatchSolver {
     double2* r64 = F(bW2) + n;
     LGT_HIP(launch_zero64((int)n, z, c->stream));
     LGT_HIP(launch_zero32((int)n, xs, c->stream));
-    LGT_HIP(launch_mnorm<double>(n, nr, rhs, red(), c->stream));
+    LGT_HIP(launch_mnorm<double>(c->vh, 12, nr, rhs, red(), c->stream));
     read_results(nr);
     std::vector<double> target(nr), sigma(nr);
     std::vector<int> verified(nr, 0), iters(nr, 0);
@@ -213,7 +265,7 @@ struct BatchSolver {
     s.all_done = std::all_of(verified.begin(), verified.end(), [](int v) { return v != 0; });
     upload_vecs();
     LGT_HIP(hipMemcpyAsync(w->dint, w->hint, kMaxRhs * sizeof(int), hipMemcpyHostToDevice, c->stream));
-    LGT_HIP(launch_mrescale(n, nr, rhs, vec(vSigma), rs, ps, w->dint, vec(vPscale), c->stream));
+    LGT_HIP(launch_mrescale(c->vh, nr, rhs, vec(vSigma), rs, ps, w->dint, vec(vPscale), c->stream));
     write_state();
     while (!s.all_done) {
       c->drive(s.iter, [&] {
@@ -233,10 +285,10 @@ struct BatchSolver {
       // reliable update for every right-hand side
       for (int k = 0; k < nr; ++k) w->hvec[vScale * kMaxRhs + k] = 1.0 / sigma[k];
       upload_vecs();
-      LGT_HIP(launch_mmixed_update(n, nr, xs, z, vec(vScale), c->stream));
+      LGT_HIP(launch_mmixed_update(c->vh, nr, xs, z, vec(vScale), c->stream));
       apply_normal64(dag, z, r64);
       LGT_HIP(launch_xmy64((int)n, rhs, r64, c->stream));
-      LGT_HIP(launch_mnorm<double>(n, nr, r64, red(), c->stream));
+      LGT_HIP(launch_mnorm<double>(c->vh, 12, nr, r64, red(), c->stream));
       read_results(nr);
       bool all = true;
       for (int k = 0; k < nr; ++k) {
@@ -274,7 +326,7 @@ struct BatchSolver {
       if (s.all_done) break;
       upload_vecs();
       LGT_HIP(hipMemcpyAsync(w->dint, w->hint, kMaxRhs * sizeof(int), hipMemcpyHostToDevice, c->stream));
-      LGT_HIP(launch_mrescale(n, nr, r64, vec(vSigma), rs, ps, w->dint, vec(vPscale), c->stream));
+      LGT_HIP(launch_mrescale(c->vh, nr, r64, vec(vSigma), rs, ps, w->dint, vec(vPscale), c->stream));
       write_state();
     }
     for (int k = 0; k < nr; ++k) st[k].iters += iters[k];
@@ -307,10 +359,10 @@ struct BatchSolver {
     const size_t h = halfn();
     HopIn<double> hin{c->U64, in, in + h};
     if (dag)
-      LGT_HIP((launch_mhop_axpy<double, true>(c->g, nr, -1, hin, out, out + h, in, in + h, vec(vMKap), c->stream,
+      LGT_HIP((launch_mhop_axpy<double, true>(c->g, nr, gsize<double>(), -1, hin, out, out + h, in, in + h, vec(vMKap), c->stream,
                                                nullptr, nullptr, red())));
     else
-      LGT_HIP((launch_mhop_axpy<double, false>(c->g, nr, -1, hin, out, out + h, in, in + h, vec(vMKap), c->stream,
+      LGT_HIP((launch_mhop_axpy<double, false>(c->g, nr, gsize<double>(), -1, hin, out, out + h, in, in + h, vec(vMKap), c->stream,
                                                 nullptr, nullptr, red())));
   }
 
@@ -325,7 +377,7 @@ struct BatchSolver {
     }
     upload_vecs();
     const double2* phi = F(bPhi);
-    LGT_HIP(launch_mnorm<double>(nfull, nr, phi, red(), c->stream));
+    LGT_HIP(launch_mnorm<double>(c->vh, 24, nr, phi, red(), c->stream));
     read_results(nr);
     std::vector<double> pp(c->host_result, c->host_result + nr);
     for (double v : pp)
@@ -336,7 +388,8 @@ struct BatchSolver {
     for (int pass = 0;; ++pass) {
       dslash_full(F(bX), F(bY), false);
       HopIn<double> hin{c->U64, F(bY), F(bY) + halfn()};
-      LGT_HIP(launch_mhop_residual<true>(c->g, nr, hin, F(bY), phi, F(bRes), vec(vMKap), red(), c->stream));
+      LGT_HIP(launch_mhop_residual<true>(c->g, nr, gsize<double>(), hin, F(bY), phi, F(bRes), vec(vMKap), red(),
+                                         c->stream));
       read_results(nr);
       bool ok = true;
       for (int k = 0; k < nr; ++k) {
@@ -359,6 +412,8 @@ struct BatchSolver {
 std::vector<SolveStats> lgt_ctx::solve_batch(int nr, const double* kappas, const void* const* phis,
                                              void* const* Xs, void* const* Ys, const SolverOpts& o) {
   BatchWork* w = batch_work(this, nr);
+  tune_group_size(this, w, nr, false);
+  if (o.precision != LGT_FP64) tune_group_size(this, w, nr, true);
   BatchSolver b{this, w, nr, o, std::vector<double>(kappas, kappas + nr), std::vector<SolveStats>(nr)};
   for (int k = 0; k < nr; ++k) LGT_HIP(launch_mpack(g, nr, k, (const double2*)phis[k], w->f[bPhi], stream));
   b.run();
@@ -371,6 +426,8 @@ std::vector<SolveStats> lgt_ctx::solve_batch(int nr, const double* kappas, const
 
 double lgt_ctx::bench_mhop(int nr, bool f32, const void* psi, int nrep) {
   BatchWork* w = batch_work(this, nr);
+  tune_group_size(this, w, nr, f32);
+  const int G = w->G[f32 ? 0 : 1];
   for (int k = 0; k < nr; ++k) LGT_HIP(launch_mpack(g, nr, k, (const double2*)psi, w->f[bPhi], stream));
   const size_t h = (size_t)12 * vh * nr;
   for (int k = 0; k < kMaxRhs; ++k) w->hvec[vOne * kMaxRhs + k] = 1.0;
@@ -381,11 +438,11 @@ double lgt_ctx::bench_mhop(int nr, bool f32, const void* psi, int nrep) {
   auto once = [&] {
     if (f32) {
       HopIn<float> hin{U32, w->h[0], w->h[0]};
-      LGT_HIP((launch_mhop_axpy<float, false>(g, nr, 0, hin, w->h[1], w->h[1], nullptr, nullptr, one, stream,
+      LGT_HIP((launch_mhop_axpy<float, false>(g, nr, G, 0, hin, w->h[1], w->h[1], nullptr, nullptr, one, stream,
                                                nullptr, nullptr, red)));
     } else {
       HopIn<double> hin{U64, w->f[bPhi] + h, w->f[bPhi] + h};
-      LGT_HIP((launch_mhop_axpy<double, false>(g, nr, 0, hin, w->f[bX], w->f[bX], nullptr, nullptr, one, stream,
+      LGT_HIP((launch_mhop_axpy<double, false>(g, nr, G, 0, hin, w->f[bX], w->f[bX], nullptr, nullptr, one, stream,
                                                 nullptr, nullptr, red)));
     }
   };

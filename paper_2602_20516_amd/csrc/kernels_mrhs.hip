@@ -1,19 +1,22 @@
-// Multi-right-hand-side kernels: NR spinor fields on one lattice, solved
+// Multi-right-hand-side kernels: nr spinor fields on one lattice, solved
 // together (one pseudofermion per right-hand side, each with its own kappa).
 //
-// Layout of a multi-RHS half field: [12 components][V/2 sites][NR] complex,
-// right-hand side fastest, so the NR threads of one site read one link and
-// NR consecutive spinor values: the link traffic is paid once for all NR
-// solves (the point of batching; the Schur operator is kappa-independent up
-// to the per-RHS factor kappa_n^2 applied in the epilogue).
+// Layout of a multi-RHS half field: [12 components][nr][V/2 sites] complex
+// (site fastest), a full field the even half then the odd half.  Every
+// per-component access of a wave is unit stride, as in the single field.
 //
-// Work decomposition as in the single-field hop: a 256-thread block owns 64
-// consecutive (site, right-hand side) pairs, pair q -> site q / NR, RHS
-// q % NR; wave w (= direction mu) computes both hops along mu for the 64
-// pairs, the partial spinors meet in LDS and wave w then owns spin w of the
-// 64 pairs.  Per-RHS reductions are deterministic: block sums per n in a
-// fixed order, one partial per (block, n), summed by a one-block finalize
-// launch.
+// Hop decomposition: a 256-thread block owns 64 consecutive sites of one
+// parity and a group of G right-hand sides; wave w (= direction mu) loads
+// the two links of its direction once, keeps them in registers (FP32; FP64
+// reloads them per right-hand side to stay clear of spills) and then, for
+// each right-hand side of the group in turn, computes both hops along mu,
+// meets the other waves in LDS and runs the epilogue for spin component w.
+// The link traffic is paid once per group instead of once per field, and
+// the neighbour index arithmetic once per block.  G trades link reuse
+// (large G) against parallelism (small G gives more blocks); the host picks
+// it by timing (see batch.hip).  Per-RHS reductions are deterministic: a
+// fixed-order wave reduction, then the four waves in order, one partial per
+// (site block, right-hand side), summed by a one-block finalize launch.
 #include "lgt_internal.h"
 #include "lgt_hop.h"
 #include "lgt_mrhs.h"
@@ -21,7 +24,7 @@
 namespace lgt {
 
 // ---------------------------------------------------------------------------
-// Epilogues (element (k, cb, n) of the hop result).
+// Epilogues (element (k, n, cb) of the hop result, offset o).
 // ---------------------------------------------------------------------------
 template <typename R>
 struct MEpiAxpy {  // out = self + coef_n * acc
@@ -114,93 +117,141 @@ struct MEpiResidual {  // r = phi - (self + coef_n acc), per-RHS |r|^2 (both par
   __device__ void tail(int) const {}
 };
 
-// Per-RHS block reduction: thread values -> partials[blk * kMaxRhs + n].
-// Thread tid carries pair index q0 + (tid % 64) when pairs_per_wave is 64
-// (hop kernels, 4 waves on the same 64 pairs) or q0 + tid (vector kernels);
-// each n sums its threads in increasing thread order (deterministic).
-__device__ __forceinline__ void block_partials_rhs(double v, int nr, long q0, int lane_mask, double* partials,
-                                                   int blk) {
-  __shared__ double sh[256];
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  if (threadIdx.x < nr) {
-    const int n = threadIdx.x;
-    double s = 0.0;
-    for (int i = 0; i < 256; ++i)
-      if ((int)((q0 + (i & lane_mask)) % nr) == n) s += sh[i];
-    partials[(size_t)blk * kMaxRhs + n] = s;
+
+// Loader of one right-hand side of a multi-RHS field: element (k, n, site)
+// at (k*nr + n)*vh + site; the per-lane offset carries site and n, the
+// component offset is uniform.
+template <typename R>
+struct MrhsIn {
+  BufRsrc rs;
+  unsigned ks;  // component stride in bytes (nr * vh elements)
+  unsigned ns;  // right-hand-side stride in bytes (vh elements)
+  __device__ __forceinline__ unsigned off(int site, int n) const {
+    return (unsigned)site * (unsigned)sizeof(R2<R>) + (unsigned)n * ns;
   }
+  __device__ __forceinline__ C<R> ld(unsigned o, int k) const { return ld_buf<R>(rs, o, k * ks); }
+};
+
+// wave-level sum in a fixed butterfly order (all 64 lanes get the total)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
 template <typename R, bool DAG, typename Epi>
-__global__ __launch_bounds__(256) void k_hop_mrhs(Geom g, int nr, int nbp, int p_fixed, HopIn<R> hin, Epi epi,
-                                                  double* partials) {
+__global__ __launch_bounds__(256) void k_hop_mrhs(Geom g, int nr, int G, int nbp, int ngrp, int p_fixed,
+                                                  HopIn<R> hin, Epi epi, double* partials) {
   if (epi.skip()) return;
   __shared__ R2<R> lds[4][12][64];
+  __shared__ double wred[4][kMaxRhs];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int p = p_fixed >= 0 ? p_fixed : lb / nbp;
-  const int blk = p_fixed >= 0 ? lb : lb % nbp;
+  const int per_par = nbp * ngrp;
+  const int p = p_fixed >= 0 ? p_fixed : lb / per_par;
+  const int rem = p_fixed >= 0 ? lb : lb % per_par;
+  const int blk = rem / ngrp, grp = rem - blk * ngrp;  // neighbouring blocks share a site block
+  const int n0 = grp * G, n1 = min(nr, n0 + G);
   const int lane = threadIdx.x & 63;
   const int mu = threadIdx.x >> 6;
-  const long q0 = (long)blk * 64;
-  const long q = q0 + lane;
-  const int cb = (int)(q / nr), n = (int)(q - (long)cb * nr);
+  const int cb = blk * 64 + lane;
   const bool active = cb < g.vh;
-  C<R> acc[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = czero<R>();
+  constexpr unsigned E = sizeof(R2<R>);
+  const unsigned gs = (unsigned)g.vh * E;
+  const unsigned ns = (unsigned)g.vh * E;
+  const MrhsIn<R> in{make_rsrc(p ? hin.in_even : hin.in_odd, (size_t)12 * nr * ns), (unsigned)nr * ns, ns};
+  int c[4] = {0, 0, 0, 0};
+  int nf = 0, nb = 0;
   if (active) {
-    int c[4];
     cb_coords(g, p, cb, c);
-    const auto in = make_loader<R>(hin, g, p, nr);
-    switch (mu) {
-      case 0: hop_dir<R, 0, DAG>(g, hin.gauge, in, p, cb, c, acc, n); break;
-      case 1: hop_dir<R, 1, DAG>(g, hin.gauge, in, p, cb, c, acc, n); break;
-      case 2: hop_dir<R, 2, DAG>(g, hin.gauge, in, p, cb, c, acc, n); break;
-      default: hop_dir<R, 3, DAG>(g, hin.gauge, in, p, cb, c, acc, n); break;
+    nf = cb_shift(g, c, mu, +1);
+    nb = cb_shift(g, c, mu, -1);
+  }
+  const BufRsrc ruf = make_rsrc(gptr<R>(hin.gauge, g, p, mu), (size_t)9 * gs);
+  const BufRsrc rub = make_rsrc(gptr<R>(hin.gauge, g, 1 - p, mu), (size_t)9 * gs);
+  constexpr bool kKeepLinks = sizeof(R) == 4;
+  M3<R> Uf, Ub;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Uf.m[k] = Ub.m[k] = czero<R>();
+  if (kKeepLinks && active) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      Uf.m[k] = ld_buf<R>(ruf, (unsigned)cb * E, k * gs);
+      Ub.m[k] = ld_buf<R>(rub, (unsigned)nb * E, k * gs);
     }
   }
+  for (int n = n0; n < n1; ++n) {
+    C<R> acc[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    R2<R> v;
-    v.x = acc[k].re;
-    v.y = acc[k].im;
-    lds[mu][k][lane] = v;
+    for (int k = 0; k < 12; ++k) acc[k] = czero<R>();
+    if (active) {
+      if (!kKeepLinks) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          Uf.m[k] = ld_buf<R>(ruf, (unsigned)cb * E, k * gs);
+          Ub.m[k] = ld_buf<R>(rub, (unsigned)nb * E, k * gs);
+        }
+      }
+      const unsigned of = in.off(nf, n), ob = in.off(nb, n);
+      switch (mu) {
+        case 0: hop_dir_u<R, 0, DAG>(g, Uf, Ub, in, of, ob, c, acc); break;
+        case 1: hop_dir_u<R, 1, DAG>(g, Uf, Ub, in, of, ob, c, acc); break;
+        case 2: hop_dir_u<R, 2, DAG>(g, Uf, Ub, in, of, ob, c, acc); break;
+        default: hop_dir_u<R, 3, DAG>(g, Uf, Ub, in, of, ob, c, acc); break;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      R2<R> v;
+      v.x = acc[k].re;
+      v.y = acc[k].im;
+      lds[mu][k][lane] = v;
+    }
+    __syncthreads();
+    double red = 0.0;
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int k = 3 * mu + i;
+        const R2<R> a = lds[0][k][lane], b = lds[1][k][lane], cc = lds[2][k][lane], d = lds[3][k][lane];
+        epi.apply(p, ((size_t)k * nr + n) * g.vh + cb, n,
+                  cmk<R>(((a.x + b.x) + cc.x) + d.x, ((a.y + b.y) + cc.y) + d.y), red);
+      }
+    }
+    if constexpr (Epi::kReduce) {
+      red = wave_sum(red);
+      if (lane == 0) wred[mu][n - n0] = red;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  double red = 0.0;
-  if (active) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int k = 3 * mu + i;
-      const R2<R> a = lds[0][k][lane], b = lds[1][k][lane], cc = lds[2][k][lane], d = lds[3][k][lane];
-      epi.apply(p, ((size_t)k * g.vh + cb) * nr + n, n,
-                cmk<R>(((a.x + b.x) + cc.x) + d.x, ((a.y + b.y) + cc.y) + d.y), red);
+  if constexpr (Epi::kReduce) {
+    const int t = threadIdx.x;
+    if (t < n1 - n0) {
+      const int row = p_fixed >= 0 ? blk : p * nbp + blk;
+      partials[(size_t)row * kMaxRhs + n0 + t] = ((wred[0][t] + wred[1][t]) + wred[2][t]) + wred[3][t];
     }
   }
-  if constexpr (Epi::kReduce) block_partials_rhs(red, nr, q0, 63, partials, lb);
   epi.tail(nr);
 }
 
-static inline int mrhs_blocks_parity(const Geom& g, int nr) { return (int)(((size_t)g.vh * nr + 63) / 64); }
+static inline int mrhs_nbp(const Geom& g) { return (g.vh + 63) / 64; }
 
 template <typename R, bool DAG, typename Epi>
-static hipError_t mlaunch(const Geom& g, int nr, int p_out, const HopIn<R>& hin, const Epi& epi, Reduce red,
+static hipError_t mlaunch(const Geom& g, int nr, int G, int p_out, const HopIn<R>& hin, const Epi& epi, Reduce red,
                           hipStream_t s) {
-  const int nbp = mrhs_blocks_parity(g, nr);
-  const int nb = p_out >= 0 ? nbp : 2 * nbp;
-  if (Epi::kReduce && (size_t)nb * kMaxRhs > red.ndoubles) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_hop_mrhs<R, DAG, Epi>), dim3(nb), dim3(256), 0, s, g, nr, nbp, p_out, hin, epi,
-                     red.partials);
+  if (G < 1 || G > kMaxRhs || nr < 1 || nr > kMaxRhs) return hipErrorInvalidValue;
+  const int nbp = mrhs_nbp(g);
+  const int ngrp = (nr + G - 1) / G;
+  const int rows = p_out >= 0 ? nbp : 2 * nbp;
+  if (Epi::kReduce && (size_t)rows * kMaxRhs > red.ndoubles) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_hop_mrhs<R, DAG, Epi>), dim3(rows * ngrp), dim3(256), 0, s, g, nr, G, nbp, ngrp, p_out, hin,
+                     epi, red.partials);
   return hipGetLastError();
 }
 
-int mrhs_hop_blocks(const Geom& g, int nr, int p_out) {
-  return p_out >= 0 ? mrhs_blocks_parity(g, nr) : 2 * mrhs_blocks_parity(g, nr);
-}
+int mrhs_hop_blocks(const Geom& g, int p_out) { return p_out >= 0 ? mrhs_nbp(g) : 2 * mrhs_nbp(g); }
 
 template <typename R, bool DAG>
-hipError_t launch_mhop_axpy(const Geom& g, int nr, int p_out, HopIn<R> hin, R2<R>* out_e, R2<R>* out_o,
+hipError_t launch_mhop_axpy(const Geom& g, int nr, int G, int p_out, HopIn<R> hin, R2<R>* out_e, R2<R>* out_o,
                             const R2<R>* self_e, const R2<R>* self_o, const double* coef, hipStream_t s,
                             BatchState* guard, const double* pap_partials, Reduce red) {
   MEpiAxpy<R> e;
@@ -211,29 +262,29 @@ hipError_t launch_mhop_axpy(const Geom& g, int nr, int p_out, HopIn<R> hin, R2<R
   e.coef = coef;
   e.guard = guard;
   e.pap_partials = pap_partials;
-  e.pap_nblk = mrhs_blocks_parity(g, nr);
+  e.pap_nblk = mrhs_nbp(g);
   e.state = guard;
-  return mlaunch<R, DAG>(g, nr, p_out, hin, e, red, s);
+  return mlaunch<R, DAG>(g, nr, G, p_out, hin, e, red, s);
 }
 
 template <typename R, bool DAG>
-hipError_t launch_mhop_schur_norm(const Geom& g, int nr, HopIn<R> hin, R2<R>* w, const R2<R>* x,
+hipError_t launch_mhop_schur_norm(const Geom& g, int nr, int G, HopIn<R> hin, R2<R>* w, const R2<R>* x,
                                   const double* coef, BatchState* st, Reduce red, hipStream_t s) {
   MEpiSchurNorm<R> e{w, x, coef, st};
-  return mlaunch<R, DAG>(g, nr, 1, hin, e, red, s);
+  return mlaunch<R, DAG>(g, nr, G, 1, hin, e, red, s);
 }
 
 template <typename R, bool DAG>
-hipError_t launch_mhop_schur_cg(const Geom& g, int nr, HopIn<R> hin, const R2<R>* w, R2<R>* x, R2<R>* r,
+hipError_t launch_mhop_schur_cg(const Geom& g, int nr, int G, HopIn<R> hin, const R2<R>* w, R2<R>* x, R2<R>* r,
                                 const R2<R>* p, const double* coef, BatchState* st, Reduce red, hipStream_t s) {
   MEpiSchurCG<R> e{w, x, r, p, coef, st};
-  hipError_t err = mlaunch<R, DAG>(g, nr, 1, hin, e, red, s);
+  hipError_t err = mlaunch<R, DAG>(g, nr, G, 1, hin, e, red, s);
   if (err != hipSuccess) return err;
-  return launch_mfinalize(kFinCgStep, mrhs_blocks_parity(g, nr), nr, red, st, 0.0, 0, s);
+  return launch_mfinalize(kFinCgStep, mrhs_nbp(g), nr, red, st, 0.0, 0, s);
 }
 
 template <bool DAG>
-hipError_t launch_mhop_residual(const Geom& g, int nr, HopIn<double> hin, const double2* self_full,
+hipError_t launch_mhop_residual(const Geom& g, int nr, int G, HopIn<double> hin, const double2* self_full,
                                 const double2* phi_full, double2* r_full, const double* coef, Reduce red,
                                 hipStream_t s) {
   const size_t half = (size_t)12 * g.vh * nr;
@@ -245,138 +296,143 @@ hipError_t launch_mhop_residual(const Geom& g, int nr, HopIn<double> hin, const 
   e.r[0] = r_full;
   e.r[1] = r_full + half;
   e.coef = coef;
-  hipError_t err = mlaunch<double, DAG>(g, nr, -1, hin, e, red, s);
+  hipError_t err = mlaunch<double, DAG>(g, nr, G, -1, hin, e, red, s);
   if (err != hipSuccess) return err;
-  return launch_mfinalize(kFinResult1, 2 * mrhs_blocks_parity(g, nr), nr, red, nullptr, 0.0, 0, s);
+  return launch_mfinalize(kFinResult1, 2 * mrhs_nbp(g), nr, red, nullptr, 0.0, 0, s);
 }
 
-#define LGT_INST_MHOP(R, DAG)                                                                                  \
-  template hipError_t launch_mhop_axpy<R, DAG>(const Geom&, int, int, HopIn<R>, R2<R>*, R2<R>*, const R2<R>*, \
-                                                const R2<R>*, const double*, hipStream_t, BatchState*,          \
-                                                const double*, Reduce);                                        \
-  template hipError_t launch_mhop_schur_norm<R, DAG>(const Geom&, int, HopIn<R>, R2<R>*, const R2<R>*,         \
-                                                      const double*, BatchState*, Reduce, hipStream_t);       \
-  template hipError_t launch_mhop_schur_cg<R, DAG>(const Geom&, int, HopIn<R>, const R2<R>*, R2<R>*, R2<R>*,   \
-                                                    const R2<R>*, const double*, BatchState*, Reduce,          \
-                                                    hipStream_t);
+#define LGT_INST_MHOP(R, DAG)                                                                                   \
+  template hipError_t launch_mhop_axpy<R, DAG>(const Geom&, int, int, int, HopIn<R>, R2<R>*, R2<R>*,             \
+                                                const R2<R>*, const R2<R>*, const double*, hipStream_t,          \
+                                                BatchState*, const double*, Reduce);                             \
+  template hipError_t launch_mhop_schur_norm<R, DAG>(const Geom&, int, int, HopIn<R>, R2<R>*, const R2<R>*,      \
+                                                      const double*, BatchState*, Reduce, hipStream_t);         \
+  template hipError_t launch_mhop_schur_cg<R, DAG>(const Geom&, int, int, HopIn<R>, const R2<R>*, R2<R>*, R2<R>*, \
+                                                    const R2<R>*, const double*, BatchState*, Reduce, hipStream_t);
 
 LGT_INST_MHOP(double, false)
 LGT_INST_MHOP(double, true)
 LGT_INST_MHOP(float, false)
 LGT_INST_MHOP(float, true)
-template hipError_t launch_mhop_residual<false>(const Geom&, int, HopIn<double>, const double2*, const double2*,
-                                                double2*, const double*, Reduce, hipStream_t);
-template hipError_t launch_mhop_residual<true>(const Geom&, int, HopIn<double>, const double2*, const double2*,
-                                               double2*, const double*, Reduce, hipStream_t);
+template hipError_t launch_mhop_residual<false>(const Geom&, int, int, HopIn<double>, const double2*,
+                                                const double2*, double2*, const double*, Reduce, hipStream_t);
+template hipError_t launch_mhop_residual<true>(const Geom&, int, int, HopIn<double>, const double2*,
+                                               const double2*, double2*, const double*, Reduce, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Vector kernels over multi-RHS fields (n = total complex elements; the
-// right-hand side of element i is i % nr).
+// Vector kernels over multi-RHS fields: grid (site blocks, 12 * nr slabs);
+// slab s of a half field holds component s / nr of right-hand side s % nr.
 // ---------------------------------------------------------------------------
-static inline int mvec_blocks(size_t n) {
-  size_t nb = (n + 255) / 256;
-  return (int)(nb < 1024 ? (nb < 1 ? 1 : nb) : 1024);
-}
+static inline dim3 slab_grid(int vh, int nr) { return dim3((vh + 255) / 256, 12 * nr); }
 
-// per-RHS |a|^2 (and Re <a, b>): partials [blk][kMaxRhs] (norm) and, when b
-// is given, the dot products in a second finalize slot range
+// per-RHS |a|^2 over ncomp components (12: half field, 24: full field):
+// grid (nbx, nr), block (bx, n) sums its sites over all components into
+// partials [bx][kMaxRhs]
 template <typename R>
-__global__ __launch_bounds__(256) void k_mnorm(size_t n, int nr, const R2<R>* __restrict__ a, double* partials) {
-  // grid-stride with a stride that is a multiple of nr keeps every thread on one RHS
-  const size_t stride = (size_t)gridDim.x * 256 / nr * nr;
-  const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_mnorm(int vh, int ncomp, int nr, const R2<R>* __restrict__ a,
+                                               double* partials) {
+  __shared__ double sh[4];
+  const int n = blockIdx.y;
   double acc = 0.0;
-  if (stride > 0 && t < stride) {
-    for (size_t i = t; i < n; i += stride) {
-      const R2<R> v = a[i];
+  for (int s = blockIdx.x * 256 + threadIdx.x; s < vh; s += gridDim.x * 256) {
+    for (int k = 0; k < ncomp; ++k) {
+      const R2<R> v = a[((size_t)k * nr + n) * vh + s];
       acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
     }
   }
-  block_partials_rhs(t < stride ? acc : 0.0, nr, (long)blockIdx.x * 256, 255, partials, blockIdx.x);
+  const double t = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kMaxRhs + n] = t;
+}
+
+static inline int mnorm_blocks(int vh) {
+  const int nb = (vh + 255) / 256;
+  return nb > 1024 ? 1024 : nb;
 }
 
 template <typename R>
-hipError_t launch_mnorm(size_t n, int nr, const R2<R>* a, Reduce red, hipStream_t s) {
-  const int nb = mvec_blocks(n);
-  hipLaunchKernelGGL((k_mnorm<R>), dim3(nb), dim3(256), 0, s, n, nr, a, red.partials);
+hipError_t launch_mnorm(int vh, int ncomp, int nr, const R2<R>* a, Reduce red, hipStream_t s) {
+  const int nb = mnorm_blocks(vh);
+  hipLaunchKernelGGL((k_mnorm<R>), dim3(nb, nr), dim3(256), 0, s, vh, ncomp, nr, a, red.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_mfinalize(kFinResult1, nb, nr, red, nullptr, 0.0, 0, s);
 }
-template hipError_t launch_mnorm<double>(size_t, int, const double2*, Reduce, hipStream_t);
-template hipError_t launch_mnorm<float>(size_t, int, const float2*, Reduce, hipStream_t);
+template hipError_t launch_mnorm<double>(int, int, int, const double2*, Reduce, hipStream_t);
+template hipError_t launch_mnorm<float>(int, int, int, const float2*, Reduce, hipStream_t);
 
 // p = r + beta_n p for right-hand sides still running or stopping for an update
 template <typename R>
-__global__ __launch_bounds__(256) void k_mxpay(size_t n, int nr, const R2<R>* __restrict__ r, R2<R>* __restrict__ p,
+__global__ __launch_bounds__(256) void k_mxpay(int vh, int nr, const R2<R>* __restrict__ r, R2<R>* __restrict__ p,
                                                const BatchState* st) {
-  if (st->all_done && !st->any_update) return;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-    const int k = (int)(i % nr);
-    if (st->done[k] != kDoneRunning && st->done[k] != kDoneUpdate) continue;
-    const R beta = R(st->beta[k]);
-    const R2<R> rv = r[i];
-    R2<R> pv = p[i];
-    pv.x = rv.x + beta * pv.x;
-    pv.y = rv.y + beta * pv.y;
-    p[i] = pv;
-  }
+  const int n = blockIdx.y % nr;
+  const int d = st->done[n];
+  if (d != kDoneRunning && d != kDoneUpdate) return;
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= vh) return;
+  const size_t i = (size_t)blockIdx.y * vh + s;
+  const R beta = R(st->beta[n]);
+  const R2<R> rv = r[i];
+  R2<R> pv = p[i];
+  pv.x = rv.x + beta * pv.x;
+  pv.y = rv.y + beta * pv.y;
+  p[i] = pv;
 }
 template <typename R>
-hipError_t launch_mxpay(size_t n, int nr, const R2<R>* r, R2<R>* p, BatchState* st, hipStream_t s) {
-  hipLaunchKernelGGL((k_mxpay<R>), dim3((n + 255) / 256), dim3(256), 0, s, n, nr, r, p, st);
+hipError_t launch_mxpay(int vh, int nr, const R2<R>* r, R2<R>* p, BatchState* st, hipStream_t s) {
+  hipLaunchKernelGGL((k_mxpay<R>), slab_grid(vh, nr), dim3(256), 0, s, vh, nr, r, p, st);
   return hipGetLastError();
 }
-template hipError_t launch_mxpay<double>(size_t, int, const double2*, double2*, BatchState*, hipStream_t);
-template hipError_t launch_mxpay<float>(size_t, int, const float2*, float2*, BatchState*, hipStream_t);
+template hipError_t launch_mxpay<double>(int, int, const double2*, double2*, BatchState*, hipStream_t);
+template hipError_t launch_mxpay<float>(int, int, const float2*, float2*, BatchState*, hipStream_t);
 
 // x64 += scale_n * xs; xs = 0
-__global__ __launch_bounds__(256) void k_mmixed_update(size_t n, int nr, float2* xs, double2* __restrict__ x,
+__global__ __launch_bounds__(256) void k_mmixed_update(int vh, int nr, float2* xs, double2* __restrict__ x,
                                                        const double* __restrict__ scale) {
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-    const double sc = scale[i % nr];
-    const float2 v = xs[i];
-    double2 xv = x[i];
-    xv.x += sc * (double)v.x;
-    xv.y += sc * (double)v.y;
-    x[i] = xv;
-    xs[i] = make_float2(0.f, 0.f);
-  }
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= vh) return;
+  const size_t i = (size_t)blockIdx.y * vh + s;
+  const double sc = scale[blockIdx.y % nr];
+  const float2 v = xs[i];
+  double2 xv = x[i];
+  xv.x += sc * (double)v.x;
+  xv.y += sc * (double)v.y;
+  x[i] = xv;
+  xs[i] = make_float2(0.f, 0.f);
 }
-hipError_t launch_mmixed_update(size_t n, int nr, float2* xs, double2* x, const double* scale, hipStream_t s) {
-  hipLaunchKernelGGL(k_mmixed_update, dim3((n + 255) / 256), dim3(256), 0, s, n, nr, xs, x, scale);
+hipError_t launch_mmixed_update(int vh, int nr, float2* xs, double2* x, const double* scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_mmixed_update, slab_grid(vh, nr), dim3(256), 0, s, vh, nr, xs, x, scale);
   return hipGetLastError();
 }
 
 // r = sigma_n r64; p = r (restart_n) or p *= pscale_n
-__global__ __launch_bounds__(256) void k_mrescale(size_t n, int nr, const double2* __restrict__ r64,
+__global__ __launch_bounds__(256) void k_mrescale(int vh, int nr, const double2* __restrict__ r64,
                                                   const double* __restrict__ sigma, float2* __restrict__ r,
                                                   float2* __restrict__ p, const int* __restrict__ restart,
                                                   const double* __restrict__ pscale) {
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-    const int k = (int)(i % nr);
-    const double sg = sigma[k];
-    const double2 v = r64[i];
-    const float2 w = make_float2((float)(sg * v.x), (float)(sg * v.y));
-    r[i] = w;
-    if (restart[k]) {
-      p[i] = w;
-    } else {
-      const float2 q = p[i];
-      p[i] = make_float2((float)(pscale[k] * (double)q.x), (float)(pscale[k] * (double)q.y));
-    }
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= vh) return;
+  const int n = blockIdx.y % nr;
+  const size_t i = (size_t)blockIdx.y * vh + s;
+  const double sg = sigma[n];
+  const double2 v = r64[i];
+  const float2 w = make_float2((float)(sg * v.x), (float)(sg * v.y));
+  r[i] = w;
+  if (restart[n]) {
+    p[i] = w;
+  } else {
+    const float2 q = p[i];
+    p[i] = make_float2((float)(pscale[n] * (double)q.x), (float)(pscale[n] * (double)q.y));
   }
 }
-hipError_t launch_mrescale(size_t n, int nr, const double2* r64, const double* sigma, float2* r, float2* p,
+hipError_t launch_mrescale(int vh, int nr, const double2* r64, const double* sigma, float2* r, float2* p,
                            const int* restart, const double* pscale, hipStream_t s) {
-  hipLaunchKernelGGL(k_mrescale, dim3((n + 255) / 256), dim3(256), 0, s, n, nr, r64, sigma, r, p, restart, pscale);
+  hipLaunchKernelGGL(k_mrescale, slab_grid(vh, nr), dim3(256), 0, s, vh, nr, r64, sigma, r, p, restart, pscale);
   return hipGetLastError();
 }
 
 // r = b, p = b, x = 0 (FP64 multi-RHS CG start); per-RHS |b|^2 to state
-__global__ __launch_bounds__(256) void k_mcg_init64(size_t n, int nr, const double2* __restrict__ b,
-                                                    double2* __restrict__ r, double2* __restrict__ p,
-                                                    double2* __restrict__ x) {
+__global__ __launch_bounds__(256) void k_mcg_init64(size_t n, const double2* __restrict__ b, double2* __restrict__ r,
+                                                    double2* __restrict__ p, double2* __restrict__ x) {
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
     const double2 v = b[i];
     r[i] = v;
@@ -384,19 +440,19 @@ __global__ __launch_bounds__(256) void k_mcg_init64(size_t n, int nr, const doub
     x[i] = make_double2(0.0, 0.0);
   }
 }
-hipError_t launch_mcg_init64(size_t n, int nr, const double2* b, double2* r, double2* p, double2* x,
-                             BatchState* st, Reduce red, double tol, int max_iter, hipStream_t s) {
-  hipLaunchKernelGGL(k_mcg_init64, dim3((n + 255) / 256), dim3(256), 0, s, n, nr, b, r, p, x);
+hipError_t launch_mcg_init64(int vh, int nr, const double2* b, double2* r, double2* p, double2* x, BatchState* st,
+                             Reduce red, double tol, int max_iter, hipStream_t s) {
+  const size_t n = (size_t)12 * vh * nr;
+  hipLaunchKernelGGL(k_mcg_init64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, b, r, p, x);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int nb = mvec_blocks(n);
-  hipLaunchKernelGGL((k_mnorm<double>), dim3(nb), dim3(256), 0, s, n, nr, b, red.partials);
+  const int nb = mnorm_blocks(vh);
+  hipLaunchKernelGGL((k_mnorm<double>), dim3(nb, nr), dim3(256), 0, s, vh, 12, nr, b, red.partials);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_mfinalize(kFinCgInit, nb, nr, red, st, tol, max_iter, s);
 }
 
-// One block: per-RHS sums of the partials of the previous launch.
 // The host has to act once every right-hand side is done or, with reliable
 // updates on (delta2 > 0), once half of those not yet verified have stopped
 // (a stopped one idles until the update).
@@ -411,6 +467,7 @@ __device__ __forceinline__ int batch_action(const BatchState* st, int nr) {
   return 2 * stopped >= active;
 }
 
+// One block: per-RHS sums of the partials of the previous launch.
 __global__ __launch_bounds__(256) void k_mfinalize(int mode, int nblk, int nr, const double* __restrict__ partials,
                                                    BatchState* st, double* result, double tol, int max_iter,
                                                    Mailbox* mb) {
@@ -489,8 +546,7 @@ hipError_t launch_mfinalize(int mode, int nblk, int nr, Reduce red, BatchState* 
   return hipGetLastError();
 }
 
-// Multi-RHS pack / unpack of one right-hand side n: canonical [V][12]
-// complex128 <-> packed [2][12][vh][nr] (element stride nr).
+// canonical spinor [V][4][3] of right-hand side n <-> full multi-RHS field
 __global__ __launch_bounds__(256) void k_mpack(Geom g, int nr, int n, const double2* __restrict__ canon,
                                                double2* __restrict__ packed) {
   const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -498,7 +554,7 @@ __global__ __launch_bounds__(256) void k_mpack(Geom g, int nr, int n, const doub
   const int s = (int)(t / 12), k = (int)(t % 12);
   int c[4];
   lex_coords(g, s, c);
-  packed[(((size_t)parity_of(c) * 12 + k) * g.vh + (s >> 1)) * nr + n] = canon[t];
+  packed[(((size_t)parity_of(c) * 12 + k) * nr + n) * g.vh + (s >> 1)] = canon[t];
 }
 __global__ __launch_bounds__(256) void k_munpack(Geom g, int nr, int n, const double2* __restrict__ packed,
                                                  double2* __restrict__ canon) {
@@ -507,7 +563,7 @@ __global__ __launch_bounds__(256) void k_munpack(Geom g, int nr, int n, const do
   const int s = (int)(t / 12), k = (int)(t % 12);
   int c[4];
   lex_coords(g, s, c);
-  canon[t] = packed[(((size_t)parity_of(c) * 12 + k) * g.vh + (s >> 1)) * nr + n];
+  canon[t] = packed[(((size_t)parity_of(c) * 12 + k) * nr + n) * g.vh + (s >> 1)];
 }
 hipError_t launch_mpack(const Geom& g, int nr, int n, const double2* canon, double2* packed, hipStream_t s) {
   const size_t tot = 2 * (size_t)g.vh * 12;

@@ -82,6 +82,40 @@ __device__ __forceinline__ SpinorIn<R, T> make_loader(const HopIn<R, T>& h, cons
   return SpinorIn<R, T>{make_rsrc(p ? h.in_even : h.in_odd, (size_t)12 * ks), ks, (unsigned)nr};
 }
 
+// w = U h (forward hop) and w = U^dag h (backward hop) for the two colour
+// vectors of a projected half spinor
+template <typename R>
+__device__ __forceinline__ void umul(const M3<R>& U, const C<R>* h, C<R>* w) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      C<R> s = U.m[3 * i] * h[3 * a];
+      s += U.m[3 * i + 1] * h[3 * a + 1];
+      s += U.m[3 * i + 2] * h[3 * a + 2];
+      w[3 * a + i] = s;
+    }
+}
+template <typename R>
+__device__ __forceinline__ void umul_dag(const M3<R>& U, const C<R>* h, C<R>* w) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      C<R> s = cjmul(U.m[i], h[3 * a]);
+      s += cjmul(U.m[3 + i], h[3 * a + 1]);
+      s += cjmul(U.m[6 + i], h[3 * a + 2]);
+      w[3 * a + i] = s;
+    }
+}
+// fermion boundary sign on the temporal links crossing t = Lt-1 -> 0
+template <typename R>
+__device__ __forceinline__ void apply_bc(const Geom& g, C<R>* w) {
+  const R b = R(g.bc);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) w[k] = b * w[k];
+}
+
 // Both hops along MU for output site (p, cb) with coordinates c, right-hand
 // side n of the loader's field.
 template <typename R, int MU, bool DAG, typename L>
@@ -101,20 +135,8 @@ __device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__
     M3<R> U;
 #pragma unroll
     for (int k = 0; k < 9; ++k) U.m[k] = ld_buf<R>(ru, (unsigned)cb * E, k * gs);
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        C<R> s = U.m[3 * i] * h[3 * a];
-        s += U.m[3 * i + 1] * h[3 * a + 1];
-        s += U.m[3 * i + 2] * h[3 * a + 2];
-        w[3 * a + i] = s;
-      }
-    if (MU == 3 && c[3] == g.L[3] - 1) {
-      const R b = R(g.bc);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) w[k] = b * w[k];
-    }
+    umul(U, h, w);
+    if (MU == 3 && c[3] == g.L[3] - 1) apply_bc(g, w);
     reconstruct<R, MU, SF>(w, acc);
   }
   {  // backward: (1 + SB gamma) U_mu(x - mu)^dag psi(x - mu)
@@ -127,22 +149,33 @@ __device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__
     M3<R> U;
 #pragma unroll
     for (int k = 0; k < 9; ++k) U.m[k] = ld_buf<R>(ru, (unsigned)nb * E, k * gs);
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        C<R> s = cjmul(U.m[i], h[3 * a]);
-        s += cjmul(U.m[3 + i], h[3 * a + 1]);
-        s += cjmul(U.m[6 + i], h[3 * a + 2]);
-        w[3 * a + i] = s;
-      }
-    if (MU == 3 && c[3] == 0) {
-      const R b = R(g.bc);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) w[k] = b * w[k];
-    }
+    umul_dag(U, h, w);
+    if (MU == 3 && c[3] == 0) apply_bc(g, w);
     reconstruct<R, MU, SB>(w, acc);
   }
+}
+
+// The same with the two links already loaded (Uf = U_mu(x), Ub = U_mu(x-mu))
+// and the loader offsets of the two neighbours given: the form the batched
+// hop uses to apply one pair of links to several right-hand sides.
+template <typename R, int MU, bool DAG, typename L>
+__device__ __forceinline__ void hop_dir_u(const Geom& g, const M3<R>& Uf, const M3<R>& Ub, const L& in,
+                                          unsigned of, unsigned ob, const int c[4], C<R>* acc) {
+  constexpr int SF = DAG ? +1 : -1;
+  constexpr int SB = -SF;
+  C<R> psi[12], h[6], w[6];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) psi[k] = in.ld(of, k);
+  project<R, MU, SF>(psi, h);
+  umul(Uf, h, w);
+  if (MU == 3 && c[3] == g.L[3] - 1) apply_bc(g, w);
+  reconstruct<R, MU, SF>(w, acc);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) psi[k] = in.ld(ob, k);
+  project<R, MU, SB>(psi, h);
+  umul_dag(Ub, h, w);
+  if (MU == 3 && c[3] == 0) apply_bc(g, w);
+  reconstruct<R, MU, SB>(w, acc);
 }
 
 }  // namespace lgt
