@@ -121,9 +121,9 @@ typedef struct lgt_solver_params {
   double tol;            /* stop when ||phi - D^dag D X|| / ||phi|| <= tol (FP64, recomputed) */
   int32_t max_iter;      /* cap on inner CG iterations per solve (<= 0: 20000) */
   double reliable_delta; /* mixed precision: FP64 residual update when the inner
-                            residual norm drops by this factor; the FP32
-                            recursion stays accurate over a drop of 1e-2
-                            (outside (0, 1): 0.01) */
+                            residual norm drops by this factor (outside (0, 1):
+                            0.001 for LGT_MIXED_FP32, 0.01 for LGT_MIXED_BF16,
+                            whose recursion drifts faster) */
 } lgt_solver_params;
 
 typedef struct lgt_solver_stats {

@@ -43,7 +43,7 @@ class Params:
     precision: str = "fp64"
     tol: float = 1e-10
     max_iter: int = 20000
-    reliable_delta: float = 0.01
+    reliable_delta: float = 0.0  # 0: the library's default for the precision
     even_odd: int = 1
 
     def to_c(self) -> SolverParams:

@@ -54,7 +54,10 @@ SolverOpts parse(const lgt_solver_params* p) {
   o.precision = p->precision;
   o.tol = p->tol;
   o.max_iter = p->max_iter > 0 ? p->max_iter : 20000;
-  o.delta = p->reliable_delta > 0.0 && p->reliable_delta < 1.0 ? p->reliable_delta : 0.01;
+  // default: the FP32 recursion stays accurate over a residual drop of 1e-3,
+  // the BF16-stored one (rounding ~2^-9 per iteration) over about 1e-2
+  const double dflt = p->precision == LGT_MIXED_BF16 ? 0.01 : 0.001;
+  o.delta = p->reliable_delta > 0.0 && p->reliable_delta < 1.0 ? p->reliable_delta : dflt;
   return o;
 }
 

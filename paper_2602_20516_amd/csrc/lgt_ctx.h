@@ -39,7 +39,7 @@ struct SolverOpts {
   int precision = LGT_FP64;
   double tol = 1e-10;
   int max_iter = 20000;
-  double delta = 0.1;
+  double delta = 0.001;
 };
 
 }  // namespace lgt

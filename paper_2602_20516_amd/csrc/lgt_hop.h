@@ -116,43 +116,57 @@ __device__ __forceinline__ void apply_bc(const Geom& g, C<R>* w) {
   for (int k = 0; k < 6; ++k) w[k] = b * w[k];
 }
 
-// Both hops along MU for output site (p, cb) with coordinates c, right-hand
-// side n of the loader's field.
+// The hop from x + mu (forward) or x - mu (backward) along MU for output
+// site (p, cb) with coordinates c, right-hand side n of the loader's field,
+// added to acc.
 template <typename R, int MU, bool DAG, typename L>
-__device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__ gauge, const L& in, int p, int cb,
+__device__ __forceinline__ void hop_fwd(const Geom& g, const R2<R>* __restrict__ gauge, const L& in, int p, int cb,
                                         const int c[4], C<R>* acc, int n) {
   constexpr int SF = DAG ? +1 : -1;  // forward projector 1 + SF gamma
-  constexpr int SB = -SF;
   constexpr unsigned E = sizeof(R2<R>);
   const unsigned gs = (unsigned)g.vh * E;  // link element stride in bytes (uniform)
   C<R> psi[12], h[6], w[6];
-  {  // forward: (1 + SF gamma) U_mu(x) psi(x + mu)
-    const unsigned of = in.off(cb_shift(g, c, MU, +1), n);
+  // (1 + SF gamma) U_mu(x) psi(x + mu)
+  const unsigned of = in.off(cb_shift(g, c, MU, +1), n);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k] = in.ld(of, k);
-    project<R, MU, SF>(psi, h);
-    const BufRsrc ru = make_rsrc(gptr<R>(gauge, g, p, MU), (size_t)9 * gs);
-    M3<R> U;
+  for (int k = 0; k < 12; ++k) psi[k] = in.ld(of, k);
+  project<R, MU, SF>(psi, h);
+  const BufRsrc ru = make_rsrc(gptr<R>(gauge, g, p, MU), (size_t)9 * gs);
+  M3<R> U;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) U.m[k] = ld_buf<R>(ru, (unsigned)cb * E, k * gs);
-    umul(U, h, w);
-    if (MU == 3 && c[3] == g.L[3] - 1) apply_bc(g, w);
-    reconstruct<R, MU, SF>(w, acc);
-  }
-  {  // backward: (1 + SB gamma) U_mu(x - mu)^dag psi(x - mu)
-    const int nb = cb_shift(g, c, MU, -1);
-    const unsigned ob = in.off(nb, n);
+  for (int k = 0; k < 9; ++k) U.m[k] = ld_buf<R>(ru, (unsigned)cb * E, k * gs);
+  umul(U, h, w);
+  if (MU == 3 && c[3] == g.L[3] - 1) apply_bc(g, w);
+  reconstruct<R, MU, SF>(w, acc);
+}
+template <typename R, int MU, bool DAG, typename L>
+__device__ __forceinline__ void hop_bwd(const Geom& g, const R2<R>* __restrict__ gauge, const L& in, int p,
+                                        const int c[4], C<R>* acc, int n) {
+  constexpr int SB = DAG ? -1 : +1;  // backward projector 1 + SB gamma
+  constexpr unsigned E = sizeof(R2<R>);
+  const unsigned gs = (unsigned)g.vh * E;
+  C<R> psi[12], h[6], w[6];
+  // (1 + SB gamma) U_mu(x - mu)^dag psi(x - mu)
+  const int nb = cb_shift(g, c, MU, -1);
+  const unsigned ob = in.off(nb, n);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k] = in.ld(ob, k);
-    project<R, MU, SB>(psi, h);
-    const BufRsrc ru = make_rsrc(gptr<R>(gauge, g, 1 - p, MU), (size_t)9 * gs);
-    M3<R> U;
+  for (int k = 0; k < 12; ++k) psi[k] = in.ld(ob, k);
+  project<R, MU, SB>(psi, h);
+  const BufRsrc ru = make_rsrc(gptr<R>(gauge, g, 1 - p, MU), (size_t)9 * gs);
+  M3<R> U;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) U.m[k] = ld_buf<R>(ru, (unsigned)nb * E, k * gs);
-    umul_dag(U, h, w);
-    if (MU == 3 && c[3] == 0) apply_bc(g, w);
-    reconstruct<R, MU, SB>(w, acc);
-  }
+  for (int k = 0; k < 9; ++k) U.m[k] = ld_buf<R>(ru, (unsigned)nb * E, k * gs);
+  umul_dag(U, h, w);
+  if (MU == 3 && c[3] == 0) apply_bc(g, w);
+  reconstruct<R, MU, SB>(w, acc);
+}
+
+// Both hops along MU (forward first), right-hand side n.
+template <typename R, int MU, bool DAG, typename L>
+__device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__ gauge, const L& in, int p, int cb,
+                                        const int c[4], C<R>* acc, int n) {
+  hop_fwd<R, MU, DAG>(g, gauge, in, p, cb, c, acc, n);
+  hop_bwd<R, MU, DAG>(g, gauge, in, p, c, acc, n);
 }
 
 // The same with the two links already loaded (Uf = U_mu(x), Ub = U_mu(x-mu))
