@@ -105,7 +105,7 @@ struct lgt_ctx {
   // (the surplus ones see the stopped state and return at once).  iter0 is
   // the device's iteration count before the first step; no unfinished CG
   // step may be on the stream.  Returns after synchronising the stream.
-  static constexpr int kQueueAhead = 3;
+  static constexpr int kQueueAhead = 2;
   template <typename Step>
   void drive(int iter0, Step&& step) {
     unsigned long long* w = &mbox_host->word;
