@@ -151,3 +151,59 @@ def test_pure_gauge_delta_h_scaling():
     dh = [md.trajectory_dh(u, p, None, 5.7, 0.0, 0.2 / n, n, with_fermion=False)[2]
           for n in (20, 40)]
     assert 3.8 < dh[0] / dh[1] < 4.2
+
+
+# ---- Sexton-Weingarten multiple time-scale integrator -----------------------
+
+def test_sw_with_one_inner_step_is_the_leapfrog(f):
+    """With n_inner = 1 every kick acts at the same links as the leapfrog's,
+    and kicks at equal links commute, so the two integrators coincide."""
+    u, _, phi, k = f
+    p = li.random_momenta(DIMS, 3)
+    a = md.leapfrog(u, p, phi, 5.7, k, 0.05, 3, tol=1e-14)
+    b = md.sexton_weingarten(u, p, phi, 5.7, k, 0.05, 3, 1, tol=1e-14)
+    assert np.abs(a[0] - b[0]).max() < 1e-12
+    assert np.abs(a[1] - b[1]).max() < 1e-11
+
+
+def test_sw_without_fermions_is_a_fine_leapfrog(f):
+    """kappa = 0: the outer kicks vanish and SW(dt, n, m) is the plain
+    leapfrog with step dt/m and n*m steps, exactly."""
+    u, _, phi, _ = f
+    p = li.random_momenta(DIMS, 3)
+    a = md.sexton_weingarten(u, p, phi, 5.7, 0.0, 0.1, 2, 4, tol=1e-14)
+    b = md.leapfrog(u, p, phi, 5.7, 0.0, 0.025, 8, tol=1e-14, with_fermion=False)
+    assert np.abs(a[0] - b[0]).max() < 1e-12
+    assert np.abs(a[1] - b[1]).max() < 1e-11
+
+
+def test_sw_reversibility(f):
+    u, _, phi, k = f
+    p = li.random_momenta(DIMS, 3)
+    u1, p1 = md.sexton_weingarten(u, p, phi, 5.7, k, 0.1, 2, 5, tol=1e-14)
+    u2, p2 = md.sexton_weingarten(u1, -p1, phi, 5.7, k, 0.1, 2, 5, tol=1e-14)
+    assert np.abs(u2 - u).max() < 1e-11
+    assert np.abs(-p2 - p).max() < 1e-10
+
+
+def test_sw_delta_h_scales_as_dt_squared(f):
+    u, _, phi, k = f
+    p = li.random_momenta(DIMS, 3)
+    dh = [md.sw_trajectory_dh(u, p, phi, 5.7, k, 0.5 / n, n, 10, tol=1e-13)[2] for n in (8, 16)]
+    assert 3.5 < dh[0] / dh[1] < 4.5
+
+
+def test_sw_smeared_reduces_to_leapfrog_of_smeared_action(f):
+    """n_inner = 1 with one stout level: the same kicks as a leapfrog of the
+    total smeared force (stout.total_force), applied by hand here."""
+    from oracle import stout
+    u, _, phi, k = f
+    p = li.random_momenta(DIMS, 3)
+    dt, n, rho = 0.05, 2, 0.3
+    a = md.sexton_weingarten(u, p, phi, 5.7, k, dt, n, 1, tol=1e-14, rho=rho, nlevels=1)
+    ub, pb = u, p - 0.5 * dt * stout.total_force(u, phi, 5.7, k, rho, 1, tol=1e-14)
+    for j in range(n):
+        ub = md.link_update(ub, pb, dt)
+        pb = pb - (dt if j < n - 1 else 0.5 * dt) * stout.total_force(ub, phi, 5.7, k, rho, 1, tol=1e-14)
+    assert np.abs(a[0] - ub).max() < 1e-12
+    assert np.abs(a[1] - pb).max() < 1e-10
