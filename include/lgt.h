@@ -259,6 +259,18 @@ LGT_API lgt_status lgt_md_step_smeared(lgt_ctx* ctx, void* U, void* P, const voi
                                        const lgt_solver_params* params, double* dH_or_null,
                                        lgt_solver_stats* stats);
 
+/* Sexton-Weingarten multiple time-scale trajectory (the integrator Sec. III B
+ * pairs with stout smearing, there with 10 inner steps): nsteps outer steps
+ * of size dt, each Pi -= dt/2 F_f; n_inner leapfrog steps of size
+ * dt/n_inner on the gauge force alone; Pi -= dt/2 F_f, adjacent outer
+ * half-kicks merged.  F_f is the pseudofermion force of the plain action
+ * (nlevels = 0) or of the smeared one (nlevels > 0, rho as lgt_stout_smear).
+ * n_inner = 1 is the leapfrog of lgt_md_step / lgt_md_step_smeared.  U, P,
+ * phi, params, dH_or_null and stats as lgt_md_step. */
+LGT_API lgt_status lgt_md_step_sw(lgt_ctx* ctx, void* U, void* P, const void* phi, double beta, double kappa,
+                                  double rho, int32_t nlevels, double dt, int32_t nsteps, int32_t n_inner,
+                                  const lgt_solver_params* params, double* dH_or_null, lgt_solver_stats* stats);
+
 /* One right-hand side of a batched solve. */
 typedef struct lgt_batch_item {
   const void* phi; /* spinor (input) */

@@ -87,6 +87,8 @@ PROTOTYPES = {
                                 ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
     "lgt_md_step_smeared": (_st, [_vp, _vp, _vp, _vp, _d, _d, _d, _i, _d, _i, ctypes.POINTER(SolverParams),
                                   ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
+    "lgt_md_step_sw": (_st, [_vp, _vp, _vp, _vp, _d, _d, _d, _i, _d, _i, _i, ctypes.POINTER(SolverParams),
+                             ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
 }
 
 _LIB = None

@@ -298,6 +298,22 @@ class Lattice:
         _check(self.lib, self.ctx, st, stats)
         return dh.value, stats.as_dict()
 
+    def md_step_sw(self, U, P, phi, beta: float, kappa: float, dt: float, nsteps: int, n_inner: int,
+                   params: Optional[Params] = None, rho: float = 0.0, nlevels: int = 0):
+        """lgt_md_step_sw: Sexton-Weingarten trajectory (gauge force on n_inner
+        sub-steps), plain (nlevels = 0) or smeared action; returns (dH, stats)."""
+        params = params or Params()
+        dh = ctypes.c_double()
+        stats = SolverStats()
+        cp = params.to_c()
+        self._bind_stream()
+        st = self.lib.lgt_md_step_sw(self.ctx, self._field(U, "gauge", "U"), self._field(P, "gauge", "P"),
+                                     self._field(phi, "spinor", "phi") if phi is not None else None,
+                                     float(beta), float(kappa), float(rho), int(nlevels), float(dt), int(nsteps),
+                                     int(n_inner), ctypes.byref(cp), ctypes.byref(dh), ctypes.byref(stats))
+        _check(self.lib, self.ctx, st, stats)
+        return dh.value, stats.as_dict()
+
     def hop_benchmark(self, U, psi, precision: str = "fp64", nrep: int = 50) -> float:
         """lgt_hop_benchmark: mean duration (ms) of one even/odd hop launch."""
         ms = ctypes.c_double()
@@ -386,3 +402,7 @@ def lgt_smeared_force(lat: Lattice, U, phi, beta, kappa, rho, nlevels, params=No
 
 def lgt_md_step_smeared(lat: Lattice, U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, params=None):
     return lat.md_step_smeared(U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, params)
+
+
+def lgt_md_step_sw(lat: Lattice, U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, n_inner, params=None):
+    return lat.md_step_sw(U, P, phi, beta, kappa, dt, nsteps, n_inner, params, rho, nlevels)

@@ -352,16 +352,19 @@ lgt_status lgt_kinetic(lgt_ctx* c, const void* P, double* K) {
 }
 
 // Leapfrog with merged half-kicks (Sec. III B), nlevels = 0: plain action,
-// nlevels > 0: stout-smeared fermion action.
+// nlevels > 0: stout-smeared fermion action.  n_inner > 1: Sexton-Weingarten
+// multiple time-scale integrator (Sec. III B): the fermion force on the outer
+// scale dt, the gauge force on n_inner leapfrog sub-steps of dt / n_inner.
 static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double beta, double kappa, double rho,
-                         int32_t nlevels, double dt, int32_t nsteps, const lgt_solver_params* params, double* dH,
-                         lgt_solver_stats* stats) {
+                         int32_t nlevels, double dt, int32_t nsteps, int32_t n_inner,
+                         const lgt_solver_params* params, double* dH, lgt_solver_stats* stats) {
   if (!c) return LGT_ERR_INVALID_ARGUMENT;
   bool nc = false;
   lgt_status s = guarded(c, [&] {
     require(U && P, "null field pointer");
     require(nsteps >= 1, "nsteps must be >= 1");
     require(nlevels >= 0, "nlevels must be >= 0");
+    require(n_inner >= 1, "n_inner must be >= 1");
     require(std::isfinite(dt) && std::isfinite(rho), "dt and rho must be finite");
     const SolverOpts o = parse(params);
     const bool ferm = phi != nullptr && kappa != 0.0;
@@ -405,12 +408,41 @@ static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double b
       LGT_HIP(launch_bilinear_force(c->g, thin, c->f64(kY), c->f64(kX), kappa, -2.0, LGT_OUT_MOMENTUM, h,
                                     c->P64, kPacked, c->stream));
     };
-    kick(0.5 * dt, true, nsteps == 0);
-    for (int k = 0; k < nsteps; ++k) {
-      LGT_HIP(launch_link_update(c->g, thin, c->P64, dt, kPacked, (mixed && !smeared) ? c->U32 : nullptr,
-                                 c->stream));
-      const bool last = k == nsteps - 1;
-      kick(last ? 0.5 * dt : dt, false, last);
+    float2* u32 = (mixed && !smeared) ? c->U32 : nullptr;  // the FP32 copy the inner solver reads
+    if (n_inner == 1) {
+      kick(0.5 * dt, true, nsteps == 0);
+      for (int k = 0; k < nsteps; ++k) {
+        LGT_HIP(launch_link_update(c->g, thin, c->P64, dt, kPacked, u32, c->stream));
+        const bool last = k == nsteps - 1;
+        kick(last ? 0.5 * dt : dt, false, last);
+      }
+    } else {
+      // fermion part alone (beta = 0 removes the gauge term of the smeared force)
+      auto kick_fermion = [&](double h, double* sfp) {
+        if (!ferm) return;
+        if (smeared) {
+          merge(all, c->smeared_force(thin, c->f64(kPhi), 0.0, rho, nlevels, o, LGT_OUT_MOMENTUM, h, c->P64,
+                                      kPacked, sfp));
+          return;
+        }
+        merge(all, c->solve_ddagd(c->f64(kPhi), c->f64(kX), c->f64(kY), o));
+        if (sfp) *sfp = c->action_fermion(c->f64(kPhi), c->f64(kX), c->f64(kY));
+        LGT_HIP(launch_bilinear_force(c->g, thin, c->f64(kY), c->f64(kX), kappa, -2.0, LGT_OUT_MOMENTUM, h,
+                                      c->P64, kPacked, c->stream));
+      };
+      auto kick_gauge = [&](double h) {
+        LGT_HIP(launch_gauge_force(c->g, thin, beta, LGT_OUT_MOMENTUM, h, c->P64, kPacked, c->stream));
+      };
+      const double hi = dt / n_inner;
+      for (int k = 0; k < nsteps; ++k) {
+        kick_fermion(k == 0 ? 0.5 * dt : dt, k == 0 ? &sf0 : nullptr);  // adjacent outer half-kicks merged
+        kick_gauge(0.5 * hi);
+        for (int j = 0; j < n_inner; ++j) {
+          LGT_HIP(launch_link_update(c->g, thin, c->P64, hi, kPacked, u32, c->stream));
+          kick_gauge(j < n_inner - 1 ? hi : 0.5 * hi);
+        }
+      }
+      kick_fermion(0.5 * dt, &sf1);
     }
     if (dH) {
       // Delta K and Delta S_G as sums of per-link / per-site differences:
@@ -436,13 +468,19 @@ static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double b
 
 lgt_status lgt_md_step(lgt_ctx* c, void* U, void* P, const void* phi, double beta, double kappa, double dt,
                        int32_t nsteps, const lgt_solver_params* params, double* dH, lgt_solver_stats* stats) {
-  return md_run(c, U, P, phi, beta, kappa, 0.0, 0, dt, nsteps, params, dH, stats);
+  return md_run(c, U, P, phi, beta, kappa, 0.0, 0, dt, nsteps, 1, params, dH, stats);
 }
 
 lgt_status lgt_md_step_smeared(lgt_ctx* c, void* U, void* P, const void* phi, double beta, double kappa,
                                double rho, int32_t nlevels, double dt, int32_t nsteps,
                                const lgt_solver_params* params, double* dH, lgt_solver_stats* stats) {
-  return md_run(c, U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, params, dH, stats);
+  return md_run(c, U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, 1, params, dH, stats);
+}
+
+lgt_status lgt_md_step_sw(lgt_ctx* c, void* U, void* P, const void* phi, double beta, double kappa, double rho,
+                          int32_t nlevels, double dt, int32_t nsteps, int32_t n_inner, const lgt_solver_params* params,
+                          double* dH, lgt_solver_stats* stats) {
+  return md_run(c, U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, n_inner, params, dH, stats);
 }
 
 lgt_status lgt_stout_smear(lgt_ctx* c, const void* U_in, void* U_out, double rho, int32_t nlevels) {

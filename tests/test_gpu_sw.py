@@ -1,0 +1,101 @@
+"""GPU parity of the Sexton-Weingarten multiple time-scale trajectory
+(lgt_md_step_sw) against the oracle's integrator, plain and stout-smeared."""
+import sys
+
+import numpy as np
+import pytest
+
+import lgt_inputs as li
+from oracle import dirac, md, stout
+
+from gpu_common import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lgt():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2602_20516_amd as m
+    return m
+
+
+def inputs(dims, seed=101, eps=0.5):
+    return (li.random_links(dims, eps, seed), li.gaussian_spinor(dims, seed + 1), li.random_momenta(dims, seed + 2))
+
+
+@pytest.mark.parametrize("n_inner", [1, 5])
+def test_sw_plain_vs_oracle(lgt, n_inner):
+    dims = (4, 4, 4, 4)
+    u, eta, p = inputs(dims)
+    beta, k, dt, n = 5.7, 0.12, 0.1, 2
+    phi = dirac.dslash_dag(u, eta, k)
+    u1, p1, dh_ref = md.sw_trajectory_dh(u, p, phi, beta, k, dt, n, n_inner, tol=1e-14)
+    lat = lgt.Lattice(dims)
+    U, P = to_dev(u), to_dev(p)
+    dh, st = lat.md_step_sw(U, P, to_dev(phi), beta, k, dt, n, n_inner, lgt.Params(tol=1e-13))
+    say("sw plain", n_inner, dh, dh_ref, st)
+    assert rel_err(to_host(U), u1) < 1e-13
+    assert rel_err(to_host(P), p1) < 1e-11
+    assert abs(dh - dh_ref) < 1e-9 * max(1.0, abs(dh_ref))
+
+
+def test_sw_one_inner_step_is_the_leapfrog(lgt):
+    dims = (4, 4, 4, 4)
+    u, eta, p = inputs(dims, 201)
+    beta, k, dt, n = 5.7, 0.12, 0.05, 3
+    phi = to_dev(dirac.dslash_dag(u, eta, k))
+    lat = lgt.Lattice(dims)
+    prm = lgt.Params(tol=1e-13)
+    Ua, Pa = to_dev(u), to_dev(p)
+    dha, _ = lat.md_step(Ua, Pa, phi, beta, k, dt, n, prm)
+    Ub, Pb = to_dev(u), to_dev(p)
+    dhb, _ = lat.md_step_sw(Ub, Pb, phi, beta, k, dt, n, 1, prm)
+    assert rel_err(to_host(Ub), to_host(Ua)) < 1e-14
+    assert rel_err(to_host(Pb), to_host(Pa)) < 1e-12
+    assert abs(dha - dhb) < 1e-10
+
+
+def test_sw_smeared_vs_oracle(lgt):
+    """The paper's setting in small: stout rho = 0.3, one level, 10 inner steps."""
+    dims = (4, 4, 4, 4)
+    u, eta, p = inputs(dims, 301, 0.4)
+    beta, k, dt, n, n_inner, rho = 5.7, 0.12, 0.1, 2, 10, 0.3
+    phi = dirac.dslash_dag(stout.stout(u, rho, 1), eta, k)
+    u1, p1, dh_ref = md.sw_trajectory_dh(u, p, phi, beta, k, dt, n, n_inner, tol=1e-14, rho=rho, nlevels=1)
+    lat = lgt.Lattice(dims)
+    U, P = to_dev(u), to_dev(p)
+    dh, st = lat.md_step_sw(U, P, to_dev(phi), beta, k, dt, n, n_inner, lgt.Params(tol=1e-13), rho, 1)
+    say("sw smeared", dh, dh_ref, st)
+    assert rel_err(to_host(U), u1) < 1e-12
+    assert rel_err(to_host(P), p1) < 1e-10
+    assert abs(dh - dh_ref) < 1e-8 * max(1.0, abs(dh_ref))
+
+
+def test_sw_mixed_reversibility_and_dt_squared(lgt):
+    """8^4, stout rho 0.3, 10 inner steps, mixed-precision solves."""
+    dims = (8, 8, 8, 8)
+    u, eta, p = inputs(dims, 401, 0.3)
+    beta, k, rho = 5.7, 0.12, 0.3
+    lat = lgt.Lattice(dims)
+    U0 = to_dev(u)
+    phi = lat.dslash(lat.stout_smear(U0, rho, 1), to_dev(eta), k, dagger=True)
+    prm = lgt.Params(precision="mixed_fp32", tol=1e-12)
+    dhs = []
+    for n in (4, 8):
+        U, P = U0.clone(), to_dev(p)
+        dh, _ = lat.md_step_sw(U, P, phi, beta, k, 0.4 / n, n, 10, prm, rho, 1)
+        dhs.append(dh)
+    say("sw dH", dhs)
+    assert 3.0 < dhs[0] / dhs[1] < 5.0
+    U, P = U0.clone(), to_dev(p)
+    lat.md_step_sw(U, P, phi, beta, k, 0.1, 4, 10, prm, rho, 1)
+    P.neg_()
+    lat.md_step_sw(U, P, phi, beta, k, 0.1, 4, 10, prm, rho, 1)
+    assert rel_err(to_host(U), u) < 1e-10
+    assert rel_err(-to_host(P), p) < 1e-9
