@@ -21,7 +21,13 @@ Other workloads (each prints its own JSON line; none is the headline):
   --config 5  32^3x64, kappa 0.135, 2 stout levels rho 0.1: one leapfrog
               trajectory (10 steps, tau 1), dH, reversibility
 
+Study (not a timing): --study dh-vs-dt runs HMC chains (Metropolis) for the
+paper's step-size test, 8^4 leapfrog and 6^4 stout (rho 0.3) with the
+Sexton-Weingarten integrator (10 inner steps), and reports <Delta H>,
+rms Delta H, <exp(-Delta H)> and acceptance against dt.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--config 2|3|4|5]
+                       [--study dh-vs-dt]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -105,11 +111,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4, 5))
+    ap.add_argument("--study", default=None, choices=("dh-vs-dt",))
+    ap.add_argument("--therm", type=int, default=100, help="thermalisation trajectories of the study")
+    ap.add_argument("--meas", type=int, default=40, help="measured trajectories per step size in the study")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path here is single-GPU (no collectives); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.study == "dh-vs-dt":
+        print(json.dumps(study_dh_vs_dt(args)), flush=True)
+        return
     if args.config != 2:
         rec = {3: bench_c3, 4: bench_c4, 5: bench_c5}[args.config](args)
         print(json.dumps(rec), flush=True)
@@ -420,6 +432,68 @@ def bench_c5(args):
         "dH": dh, "dH_reversed": dh_back, "reversibility_rel_U": rev_u, "reversibility_rel_P": rev_p,
         "iters": st["iters"], "reliable_updates": st["reliable_updates"],
         "max_true_rel_residual": st["true_rel_residual"], "V": int(np.prod(dims)),
+    }
+
+
+def study_dh_vs_dt(args):
+    """HMC step-size study (Sec. III B): Delta H against dt at tau = 1."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import lgt_inputs as li
+    import paper_2602_20516_amd as lgt
+    from paper_2602_20516_amd.hmc import HMC, HMCRecord
+
+    settings = [
+        dict(name="8^4 Wilson fermions, leapfrog", dims=(8, 8, 8, 8), beta=5.7, kappa=0.12, n_inner=1, rho=0.0,
+             nlevels=0, seed=701, therm_steps=40, steps=(20, 40, 80)),
+        dict(name="6^4 Wilson fermions, stout rho 0.3 (1 level), Sexton-Weingarten 10 inner steps",
+             dims=(6, 6, 6, 6), beta=5.7, kappa=0.12, n_inner=10, rho=0.3, nlevels=1, seed=702, therm_steps=10,
+             steps=(5, 10, 20)),
+    ]
+    prm = lgt.Params(precision="mixed_fp32", tol=1e-10)
+    out = []
+    t_all = time.perf_counter()
+    for st in settings:
+        lat = lgt.Lattice(st["dims"])
+        U = torch.from_numpy(li.random_links(st["dims"], 0.5, st["seed"])).to("cuda")
+
+        def chain(nsteps, n, rec, seed):
+            nonlocal U
+            h = HMC(lat, st["beta"], st["kappa"], 1.0 / nsteps, nsteps, st["n_inner"], st["rho"], st["nlevels"], prm,
+                    seed)
+            for i in range(n):
+                U = h.update(U, rec)
+                if (i + 1) % 20 == 0:
+                    log(f"study {st['dims']}: nsteps {nsteps}: {i + 1}/{n} trajectories")
+
+        chain(st["therm_steps"], args.therm, None, st["seed"] * 10)
+        rows = []
+        for j, nsteps in enumerate(st["steps"]):
+            rec = HMCRecord()
+            chain(nsteps, args.meas, rec, st["seed"] * 10 + j + 1)
+            r = rec.summary()
+            r["dt"] = 1.0 / nsteps
+            r["nsteps"] = nsteps
+            rows.append(r)
+            log(f"study {st['dims']}: dt {1.0 / nsteps:.3f}: {r}")
+        dts = np.log([r["dt"] for r in rows])
+        slope_rms = float(np.polyfit(dts, np.log([r["rms_dH"] for r in rows]), 1)[0])
+        pos = [r for r in rows if r["mean_dH"] > 0]
+        slope_mean = (float(np.polyfit(np.log([r["dt"] for r in pos]), np.log([r["mean_dH"] for r in pos]), 1)[0])
+                      if len(pos) >= 2 else None)
+        out.append({"setting": st["name"], "dims": list(st["dims"]), "beta": st["beta"], "kappa": st["kappa"],
+                    "n_inner": st["n_inner"], "rho": st["rho"], "stout_levels": st["nlevels"],
+                    "thermalisation_trajectories": args.therm, "measured_per_dt": args.meas, "rows": rows,
+                    "slope_log_rms_dH_vs_log_dt": slope_rms, "slope_log_mean_dH_vs_log_dt": slope_mean})
+    return {
+        "study": "HMC Delta H vs dt (tau = 1), mixed-precision solves to FP64 true residual 1e-10",
+        "expected": "rms Delta H ~ dt^2 (second-order integrator); <Delta H> ~ dt^4 and <exp(-Delta H)> = 1 "
+                    "in equilibrium",
+        "beta_kappa_note": "the paper does not state beta and kappa; beta 5.7, kappa 0.12 are this study's choice",
+        "results": out, "seconds": round(time.perf_counter() - t_all, 1),
     }
 
 

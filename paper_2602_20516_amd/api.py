@@ -183,6 +183,11 @@ class Lattice:
         _check(self.lib, self.ctx, st, stats)
         return (sg.value if gauge else None), (sf.value if fermion else None), stats.as_dict()
 
+    def mean_plaquette(self, U) -> float:
+        """<(1/3) Re tr P_mu,nu(x)> over the 6V plaquettes, from lgt_action's S_G at beta = 1."""
+        sg, _, _ = self.action(U, None, 1.0, 0.0, gauge=True, fermion=False)
+        return 1.0 - sg / (6.0 * self.volume)
+
     def fermion_force(self, U, phi, kappa: float, params: Optional[Params] = None, mode: str = "force",
                       dt: float = 0.0, out=None):
         """lgt_fermion_force: returns (out, stats)."""
