@@ -1,0 +1,103 @@
+"""Pins of the oracle's even/odd-preconditioned pseudofermion action (CPU)."""
+import numpy as np
+import pytest
+
+import lgt_inputs as li
+from oracle import dirac, eo, force
+
+DIMS = (2, 2, 2, 4)
+
+
+@pytest.fixture(scope="module")
+def f():
+    u = li.random_links(DIMS, 0.5, 11)
+    eta = li.gaussian_spinor(DIMS, 12)
+    odd = eo.parity_mask(DIMS, 1)
+    return u, odd * eta, odd
+
+
+def _odd_indices():
+    lx, ly, lz, lt = DIMS
+    idx = []
+    for t in range(lt):
+        for z in range(lz):
+            for y in range(ly):
+                for x in range(lx):
+                    if (x + y + z + t) % 2 == 1:
+                        s = dirac.site_index(DIMS, x, y, z, t)
+                        idx.extend(range(12 * s, 12 * s + 12))
+    return np.array(idx)
+
+
+def _schur_matrix(u, kappa):
+    """Columns: Dhat applied to the odd-site unit vectors, in dense index order."""
+    odd = _odd_indices()
+    lx, ly, lz, lt = DIMS
+    cols = []
+    for j in odd:
+        e = np.zeros(12 * lx * ly * lz * lt, dtype=np.complex128)
+        e[j] = 1.0
+        v = eo.schur(u, e.reshape((lt, lz, ly, lx, 4, 3)), kappa).ravel()
+        cols.append(v[odd])
+    return np.array(cols).T
+
+
+def test_schur_is_the_schur_complement_of_the_dense_operator(f):
+    """Dhat = D_oo - D_oe D_ee^-1 D_eo with D from the loop-built dense matrix."""
+    u, _, _ = f
+    k = 0.13
+    d = dirac.dense_dirac(u, k)
+    odd = _odd_indices()
+    even = np.setdiff1d(np.arange(d.shape[0]), odd)
+    ref = d[np.ix_(odd, odd)] - d[np.ix_(odd, even)] @ np.linalg.solve(d[np.ix_(even, even)], d[np.ix_(even, odd)])
+    assert np.abs(_schur_matrix(u, k) - ref).max() < 1e-13
+
+
+def test_same_determinant_as_the_unpreconditioned_operator(f):
+    u, _, _ = f
+    k = 0.13
+    s_full, l_full = np.linalg.slogdet(dirac.dense_dirac(u, k))
+    s_eo, l_eo = np.linalg.slogdet(_schur_matrix(u, k))
+    assert abs(l_full - l_eo) < 1e-11
+    assert abs(s_full - s_eo) < 1e-11
+
+
+def test_schur_dagger_is_the_adjoint(f):
+    u, eta_o, odd = f
+    k = 0.12
+    b = odd * li.gaussian_spinor(DIMS, 13)
+    lhs = np.vdot(b.ravel(), eo.schur(u, eta_o, k).ravel())
+    rhs = np.vdot(eo.schur_dag(u, b, k).ravel(), eta_o.ravel())
+    assert abs(lhs - rhs) < 1e-13
+
+
+def test_heat_bath_action_equals_eta_norm(f):
+    u, eta_o, _ = f
+    k = 0.12
+    phi_o = eo.schur_dag(u, eta_o, k)
+    s = eo.eo_action(u, phi_o, k)
+    ee = float(np.vdot(eta_o.ravel(), eta_o.ravel()).real)
+    assert abs(s - ee) / ee < 1e-12
+
+
+def test_gradient_against_component_differences(f):
+    u, _, odd = f
+    k = 0.12
+    phi_o = odd * li.gaussian_spinor(DIMS, 14)  # any odd-site field
+    g = eo.eo_grad(u, phi_o, k)
+    act = lambda v: eo.eo_action(v, phi_o, k)  # noqa: E731
+    for site, mu, i, j in [((0, 0, 0, 0), 0, 0, 1), ((1, 1, 0, 1), 3, 2, 0), ((3, 0, 1, 0), 2, 1, 1)]:
+        re = force.component_fd(act, u, site, mu, i, j, False)
+        im = force.component_fd(act, u, site, mu, i, j, True)
+        assert abs(g[site + (mu, i, j)] - (re + 1j * im)) < 1e-6 * max(1.0, abs(g[site + (mu, i, j)]))
+
+
+def test_force_against_lie_differences(f):
+    u, eta_o, _ = f
+    k = 0.12
+    phi_o = eo.schur_dag(u, eta_o, k)
+    fo = eo.eo_force(u, phi_o, k)
+    d = force.lie_derivatives(fo)
+    act = lambda v: eo.eo_action(v, phi_o, k)  # noqa: E731
+    for site, mu, a in [((0, 1, 0, 1), 1, 0), ((2, 0, 1, 1), 3, 5), ((1, 1, 1, 0), 0, 7)]:
+        assert abs(d[site + (mu, a)] - force.lie_fd(act, u, site, mu, a)) < 1e-6
