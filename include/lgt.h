@@ -271,6 +271,35 @@ LGT_API lgt_status lgt_md_step_sw(lgt_ctx* ctx, void* U, void* P, const void* ph
                                   double rho, int32_t nlevels, double dt, int32_t nsteps, int32_t n_inner,
                                   const lgt_solver_params* params, double* dH_or_null, lgt_solver_stats* stats);
 
+/* ---- Even/odd-preconditioned pseudofermion action -------------------------
+ * With Mhat = 1 - kappa^2 H_oe H_eo on the odd sites (H_eo: odd -> even
+ * hops of D = 1 - kappa H), det D = det Mhat, so
+ *   S_eo = phi_o^dag (Mhat^dag Mhat)^-1 phi_o
+ * carries the determinant weight of the action of eq. S3.1 with one Schur
+ * solve per evaluation; its heat bath is phi_o = Mhat^dag eta_o.  Spinors are
+ * full canonical fields of which only the odd sites ((x+y+z+t) odd) count. */
+
+/* out = Mhat in (dagger = 0) or Mhat^dag in, on the odd sites; the even
+ * sites of out are set to zero and those of in are ignored.  FP64. */
+LGT_API lgt_status lgt_schur_dslash(lgt_ctx* ctx, const void* U, const void* in, void* out, double kappa,
+                                    int32_t dagger);
+
+/* Force of S_eo (derivative through the Schur solve, projected as in
+ * lgt_fermion_force): with X_o = (Mhat^dag Mhat)^-1 phi_o to the FP64 true
+ * residual params->tol and Y_o = Mhat X_o, dS_eo = -2 Re[Y_o^dag dMhat X_o],
+ * evaluated as the bilinear of the full operator with a = (H_oe^dag Y_o, Y_o),
+ * b = (H_eo X_o, X_o) and coefficient -2 kappa.  mode/dt/out as
+ * lgt_fermion_force; S_F_or_null receives S_eo. */
+LGT_API lgt_status lgt_fermion_force_eo(lgt_ctx* ctx, const void* U, const void* phi, double kappa,
+                                        const lgt_solver_params* params, int32_t mode, double dt, void* out,
+                                        double* S_F_or_null, lgt_solver_stats* stats);
+
+/* Trajectory (leapfrog for n_inner = 1, Sexton-Weingarten otherwise, as
+ * lgt_md_step_sw) for H = K + S_G(U) + S_eo(U; phi_o); thin links. */
+LGT_API lgt_status lgt_md_step_eo(lgt_ctx* ctx, void* U, void* P, const void* phi, double beta, double kappa,
+                                  double dt, int32_t nsteps, int32_t n_inner, const lgt_solver_params* params,
+                                  double* dH_or_null, lgt_solver_stats* stats);
+
 /* One right-hand side of a batched solve. */
 typedef struct lgt_batch_item {
   const void* phi; /* spinor (input) */

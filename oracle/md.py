@@ -74,8 +74,12 @@ def trajectory_dh(u, p, phi, beta, kappa, dt, nsteps, bc=-1, tol=1e-12, with_fer
     return u1, p1, h1 - h0
 
 
-def fermion_force_only(u, phi, kappa, bc=-1, tol=1e-12, rho=0.0, nlevels=0):
-    """F_f at U: of S_f(U), or of S_f(stout^n(U)) when nlevels > 0."""
+def fermion_force_only(u, phi, kappa, bc=-1, tol=1e-12, rho=0.0, nlevels=0, eo=False):
+    """F_f at U: of S_f(U), or of S_f(stout^n(U)) when nlevels > 0, or of the
+    even/odd-preconditioned action S_eo(U; phi_o) when eo (eo.py)."""
+    if eo:
+        from .eo import eo_force
+        return eo_force(u, phi, kappa, bc, tol)
     if nlevels > 0:
         from .stout import smeared_fermion_grad
         return force_from_grad(u, smeared_fermion_grad(u, phi, kappa, rho, nlevels, bc, tol))
@@ -83,30 +87,34 @@ def fermion_force_only(u, phi, kappa, bc=-1, tol=1e-12, rho=0.0, nlevels=0):
     return fermion_force_from_solution(u, chi, eta, kappa, bc)
 
 
-def sexton_weingarten(u, p, phi, beta, kappa, dt, nsteps, n_inner, bc=-1, tol=1e-12, rho=0.0, nlevels=0):
+def sexton_weingarten(u, p, phi, beta, kappa, dt, nsteps, n_inner, bc=-1, tol=1e-12, rho=0.0, nlevels=0,
+                      eo=False):
     """Returns (U, Pi) after nsteps outer steps of size dt, each with n_inner
     gauge-force leapfrog steps of size dt / n_inner (module docstring)."""
     h = dt / n_inner
     for _ in range(nsteps):
-        p = p - 0.5 * dt * fermion_force_only(u, phi, kappa, bc, tol, rho, nlevels)
+        p = p - 0.5 * dt * fermion_force_only(u, phi, kappa, bc, tol, rho, nlevels, eo)
         for _ in range(n_inner):
             p = p - 0.5 * h * gauge_force(u, beta)
             u = link_update(u, p, h)
             p = p - 0.5 * h * gauge_force(u, beta)
-        p = p - 0.5 * dt * fermion_force_only(u, phi, kappa, bc, tol, rho, nlevels)
+        p = p - 0.5 * dt * fermion_force_only(u, phi, kappa, bc, tol, rho, nlevels, eo)
     return u, p
 
 
-def hamiltonian_smeared(u, p, phi, beta, kappa, bc=-1, tol=1e-12, rho=0.0, nlevels=0):
+def hamiltonian_smeared(u, p, phi, beta, kappa, bc=-1, tol=1e-12, rho=0.0, nlevels=0, eo=False):
+    if eo:
+        from .eo import eo_action
+        return kinetic(p) + gauge_action(u, beta) + eo_action(u, phi, kappa, bc, tol)
     if nlevels > 0:
         from .stout import total_action
         return kinetic(p) + total_action(u, phi, beta, kappa, rho, nlevels, bc, tol)
     return hamiltonian(u, p, phi, beta, kappa, bc, tol)
 
 
-def sw_trajectory_dh(u, p, phi, beta, kappa, dt, nsteps, n_inner, bc=-1, tol=1e-12, rho=0.0, nlevels=0):
-    """(U', Pi', Delta H) for one Sexton-Weingarten trajectory."""
-    h0 = hamiltonian_smeared(u, p, phi, beta, kappa, bc, tol, rho, nlevels)
-    u1, p1 = sexton_weingarten(u, p, phi, beta, kappa, dt, nsteps, n_inner, bc, tol, rho, nlevels)
-    h1 = hamiltonian_smeared(u1, p1, phi, beta, kappa, bc, tol, rho, nlevels)
+def sw_trajectory_dh(u, p, phi, beta, kappa, dt, nsteps, n_inner, bc=-1, tol=1e-12, rho=0.0, nlevels=0, eo=False):
+    """(U', Pi', Delta H) for one Sexton-Weingarten trajectory (n_inner = 1: leapfrog)."""
+    h0 = hamiltonian_smeared(u, p, phi, beta, kappa, bc, tol, rho, nlevels, eo)
+    u1, p1 = sexton_weingarten(u, p, phi, beta, kappa, dt, nsteps, n_inner, bc, tol, rho, nlevels, eo)
+    h1 = hamiltonian_smeared(u1, p1, phi, beta, kappa, bc, tol, rho, nlevels, eo)
     return u1, p1, h1 - h0

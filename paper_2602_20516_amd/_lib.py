@@ -89,6 +89,11 @@ PROTOTYPES = {
                                   ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
     "lgt_md_step_sw": (_st, [_vp, _vp, _vp, _vp, _d, _d, _d, _i, _d, _i, _i, ctypes.POINTER(SolverParams),
                              ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
+    "lgt_schur_dslash": (_st, [_vp, _vp, _vp, _vp, _d, _i]),
+    "lgt_fermion_force_eo": (_st, [_vp, _vp, _vp, _d, ctypes.POINTER(SolverParams), _i, _d, _vp,
+                                   ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
+    "lgt_md_step_eo": (_st, [_vp, _vp, _vp, _vp, _d, _d, _d, _i, _i, ctypes.POINTER(SolverParams),
+                             ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
 }
 
 _LIB = None

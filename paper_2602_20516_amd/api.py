@@ -319,6 +319,45 @@ class Lattice:
         _check(self.lib, self.ctx, st, stats)
         return dh.value, stats.as_dict()
 
+    def schur_dslash(self, U, psi, kappa: float, dagger: bool = False, out=None):
+        """lgt_schur_dslash: Mhat psi (or Mhat^dag psi) on the odd sites, even sites zero."""
+        out = self.empty_spinor() if out is None else out
+        self._bind_stream()
+        st = self.lib.lgt_schur_dslash(self.ctx, self._field(U, "gauge", "U"), self._field(psi, "spinor", "psi"),
+                                       self._field(out, "spinor", "out"), float(kappa), int(bool(dagger)))
+        _check(self.lib, self.ctx, st)
+        return out
+
+    def fermion_force_eo(self, U, phi, kappa: float, params: Optional[Params] = None, mode: str = "force",
+                         dt: float = 0.0, out=None):
+        """lgt_fermion_force_eo: returns (out, S_eo, stats)."""
+        params = params or Params()
+        out = self.empty_gauge() if out is None else out
+        sf = ctypes.c_double()
+        stats = SolverStats()
+        cp = params.to_c()
+        self._bind_stream()
+        st = self.lib.lgt_fermion_force_eo(self.ctx, self._field(U, "gauge", "U"), self._field(phi, "spinor", "phi"),
+                                           float(kappa), ctypes.byref(cp), _MODES[mode], float(dt),
+                                           self._field(out, "gauge", "out"), ctypes.byref(sf), ctypes.byref(stats))
+        _check(self.lib, self.ctx, st, stats)
+        return out, sf.value, stats.as_dict()
+
+    def md_step_eo(self, U, P, phi, beta: float, kappa: float, dt: float, nsteps: int, n_inner: int = 1,
+                   params: Optional[Params] = None):
+        """lgt_md_step_eo: trajectory with the even/odd-preconditioned action; returns (dH, stats)."""
+        params = params or Params()
+        dh = ctypes.c_double()
+        stats = SolverStats()
+        cp = params.to_c()
+        self._bind_stream()
+        st = self.lib.lgt_md_step_eo(self.ctx, self._field(U, "gauge", "U"), self._field(P, "gauge", "P"),
+                                     self._field(phi, "spinor", "phi") if phi is not None else None,
+                                     float(beta), float(kappa), float(dt), int(nsteps), int(n_inner),
+                                     ctypes.byref(cp), ctypes.byref(dh), ctypes.byref(stats))
+        _check(self.lib, self.ctx, st, stats)
+        return dh.value, stats.as_dict()
+
     def hop_benchmark(self, U, psi, precision: str = "fp64", nrep: int = 50) -> float:
         """lgt_hop_benchmark: mean duration (ms) of one even/odd hop launch."""
         ms = ctypes.c_double()
@@ -407,6 +446,18 @@ def lgt_smeared_force(lat: Lattice, U, phi, beta, kappa, rho, nlevels, params=No
 
 def lgt_md_step_smeared(lat: Lattice, U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, params=None):
     return lat.md_step_smeared(U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, params)
+
+
+def lgt_schur_dslash(lat: Lattice, U, psi, kappa, dagger=False, out=None):
+    return lat.schur_dslash(U, psi, kappa, dagger, out)
+
+
+def lgt_fermion_force_eo(lat: Lattice, U, phi, kappa, params=None, mode="force", dt=0.0, out=None):
+    return lat.fermion_force_eo(U, phi, kappa, params, mode, dt, out)
+
+
+def lgt_md_step_eo(lat: Lattice, U, P, phi, beta, kappa, dt, nsteps, n_inner=1, params=None):
+    return lat.md_step_eo(U, P, phi, beta, kappa, dt, nsteps, n_inner, params)
 
 
 def lgt_md_step_sw(lat: Lattice, U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, n_inner, params=None):

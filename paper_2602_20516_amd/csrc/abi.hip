@@ -357,7 +357,7 @@ lgt_status lgt_kinetic(lgt_ctx* c, const void* P, double* K) {
 // scale dt, the gauge force on n_inner leapfrog sub-steps of dt / n_inner.
 static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double beta, double kappa, double rho,
                          int32_t nlevels, double dt, int32_t nsteps, int32_t n_inner,
-                         const lgt_solver_params* params, double* dH, lgt_solver_stats* stats) {
+                         const lgt_solver_params* params, double* dH, lgt_solver_stats* stats, bool eo = false) {
   if (!c) return LGT_ERR_INVALID_ARGUMENT;
   bool nc = false;
   lgt_status s = guarded(c, [&] {
@@ -370,6 +370,7 @@ static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double b
     const bool ferm = phi != nullptr && kappa != 0.0;
     const bool mixed = ferm && o.precision != LGT_FP64;
     const bool smeared = ferm && nlevels > 0;
+    require(!(eo && nlevels > 0), "the even/odd-preconditioned action is implemented for thin links only");
     Timer tm(c);
     c->ensure_p64();
     // thin links: U64 for the plain action; a separate field when smearing
@@ -392,6 +393,20 @@ static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double b
       LGT_HIP(launch_copy64(72 * c->vh, c->P64, p0, c->stream));
     }
 
+    // plain (or even/odd-preconditioned) pseudofermion force kick at the thin links
+    auto fermion_kick = [&](double h, double* sfp) {
+      if (eo) {
+        merge(all, c->solve_eo(c->f64(kPhi), c->f64(kX), c->f64(kY), o));
+        if (sfp) *sfp = c->action_eo(c->f64(kPhi), c->f64(kX), c->f64(kY));
+        LGT_HIP(launch_bilinear_force(c->g, thin, c->f64(kY), c->f64(kX), kappa, -2.0 * kappa, LGT_OUT_MOMENTUM, h,
+                                      c->P64, kPacked, c->stream));
+        return;
+      }
+      merge(all, c->solve_ddagd(c->f64(kPhi), c->f64(kX), c->f64(kY), o));
+      if (sfp) *sfp = c->action_fermion(c->f64(kPhi), c->f64(kX), c->f64(kY));
+      LGT_HIP(launch_bilinear_force(c->g, thin, c->f64(kY), c->f64(kX), kappa, -2.0, LGT_OUT_MOMENTUM, h, c->P64,
+                                    kPacked, c->stream));
+    };
     auto kick = [&](double h, bool first, bool last) {
       double* sfp = first ? &sf0 : (last ? &sf1 : nullptr);
       if (smeared) {
@@ -402,11 +417,7 @@ static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double b
       }
       LGT_HIP(launch_gauge_force(c->g, thin, beta, LGT_OUT_MOMENTUM, h, c->P64, kPacked, c->stream));
       if (!ferm) return;
-      SolveStats st = c->solve_ddagd(c->f64(kPhi), c->f64(kX), c->f64(kY), o);
-      merge(all, st);
-      if (sfp) *sfp = c->action_fermion(c->f64(kPhi), c->f64(kX), c->f64(kY));
-      LGT_HIP(launch_bilinear_force(c->g, thin, c->f64(kY), c->f64(kX), kappa, -2.0, LGT_OUT_MOMENTUM, h,
-                                    c->P64, kPacked, c->stream));
+      fermion_kick(h, sfp);
     };
     float2* u32 = (mixed && !smeared) ? c->U32 : nullptr;  // the FP32 copy the inner solver reads
     if (n_inner == 1) {
@@ -425,10 +436,7 @@ static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double b
                                       kPacked, sfp));
           return;
         }
-        merge(all, c->solve_ddagd(c->f64(kPhi), c->f64(kX), c->f64(kY), o));
-        if (sfp) *sfp = c->action_fermion(c->f64(kPhi), c->f64(kX), c->f64(kY));
-        LGT_HIP(launch_bilinear_force(c->g, thin, c->f64(kY), c->f64(kX), kappa, -2.0, LGT_OUT_MOMENTUM, h,
-                                      c->P64, kPacked, c->stream));
+        fermion_kick(h, sfp);
       };
       auto kick_gauge = [&](double h) {
         LGT_HIP(launch_gauge_force(c->g, thin, beta, LGT_OUT_MOMENTUM, h, c->P64, kPacked, c->stream));
@@ -475,6 +483,65 @@ lgt_status lgt_md_step_smeared(lgt_ctx* c, void* U, void* P, const void* phi, do
                                double rho, int32_t nlevels, double dt, int32_t nsteps,
                                const lgt_solver_params* params, double* dH, lgt_solver_stats* stats) {
   return md_run(c, U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, 1, params, dH, stats);
+}
+
+lgt_status lgt_md_step_eo(lgt_ctx* c, void* U, void* P, const void* phi, double beta, double kappa, double dt,
+                          int32_t nsteps, int32_t n_inner, const lgt_solver_params* params, double* dH,
+                          lgt_solver_stats* stats) {
+  return md_run(c, U, P, phi, beta, kappa, 0.0, 0, dt, nsteps, n_inner, params, dH, stats, true);
+}
+
+lgt_status lgt_schur_dslash(lgt_ctx* c, const void* U, const void* in, void* out, double kappa, int32_t dagger) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(U && in && out, "null field pointer");
+    require(std::isfinite(kappa), "kappa must be finite");
+    pack_links(c, U, false);
+    double2* a = c->f64(kStageA);
+    double2* b = c->f64(kStageB);
+    pack_spinor(c, in, a);
+    const size_t h = c->half_elems();
+    const HopIn<double> ha{c->U64, a, a + h};
+    const HopIn<double> hb{c->U64, b, b + h};
+    // Mhat: H_eo then H_oe;  Mhat^dag: (H^dag)_eo then (H^dag)_oe
+    if (dagger) {
+      LGT_HIP((launch_hop_axpy<double, true>(c->g, 0, ha, b, b, nullptr, nullptr, 1.0, c->stream)));
+      LGT_HIP((launch_hop_axpy<double, true>(c->g, 1, hb, b, b + h, nullptr, a + h, -kappa * kappa, c->stream)));
+    } else {
+      LGT_HIP((launch_hop_axpy<double, false>(c->g, 0, ha, b, b, nullptr, nullptr, 1.0, c->stream)));
+      LGT_HIP((launch_hop_axpy<double, false>(c->g, 1, hb, b, b + h, nullptr, a + h, -kappa * kappa, c->stream)));
+    }
+    LGT_HIP(launch_zero64((int)h, b, c->stream));
+    LGT_HIP(launch_unpack(c->g, 12, b, (double2*)out, c->stream));
+  });
+}
+
+lgt_status lgt_fermion_force_eo(lgt_ctx* c, const void* U, const void* phi, double kappa,
+                                const lgt_solver_params* params, int32_t mode, double dt, void* out,
+                                double* S_F_or_null, lgt_solver_stats* stats) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  bool nc = false;
+  lgt_status s = guarded(c, [&] {
+    require(U && phi && out, "null field pointer");
+    require(mode >= LGT_OUT_FORCE && mode <= LGT_OUT_MOMENTUM, "unknown output mode");
+    const SolverOpts o = parse(params);
+    Timer tm(c);
+    pack_links(c, U, o.precision != LGT_FP64);
+    pack_spinor(c, phi, c->f64(kPhi));
+    check_nonfinite(c, "U or phi");
+    c->kappa = kappa;
+    SolveStats st = c->solve_eo(c->f64(kPhi), c->f64(kX), c->f64(kY), o);
+    if (S_F_or_null) *S_F_or_null = c->action_eo(c->f64(kPhi), c->f64(kX), c->f64(kY));
+    LGT_HIP(launch_bilinear_force(c->g, c->U64, c->f64(kY), c->f64(kX), kappa, -2.0 * kappa, mode, dt, out,
+                                  kCanonical, c->stream));
+    fill_stats(stats, st, tm.stop());
+    nc = !st.converged;
+  });
+  if (s == LGT_OK && nc) {
+    c->err = "solver did not reach the tolerance";
+    return LGT_ERR_NOT_CONVERGED;
+  }
+  return s;
 }
 
 lgt_status lgt_md_step_sw(lgt_ctx* c, void* U, void* P, const void* phi, double beta, double kappa, double rho,

@@ -96,6 +96,9 @@ struct lgt_ctx {
   lgt::SolveStats solve_ddagd(const double2* phi, double2* X, double2* Y, const lgt::SolverOpts& o);
   void dslash_full(const double2* in, double2* out, double kappa, bool dag);
   double action_fermion(const double2* phi, const double2* X, const double2* Y);
+  // even/odd-preconditioned action (odd half of phi) and its force fields
+  lgt::SolveStats solve_eo(const double2* phi, double2* X, double2* A, const lgt::SolverOpts& o);
+  double action_eo(const double2* phi, const double2* X, const double2* A);
   void sync();
   void read_results(int n);
 

@@ -101,3 +101,16 @@ def test_force_against_lie_differences(f):
     act = lambda v: eo.eo_action(v, phi_o, k)  # noqa: E731
     for site, mu, a in [((0, 1, 0, 1), 1, 0), ((2, 0, 1, 1), 3, 5), ((1, 1, 1, 0), 0, 7)]:
         assert abs(d[site + (mu, a)] - force.lie_fd(act, u, site, mu, a)) < 1e-6
+
+
+def test_eo_trajectory_reversible_and_second_order(f):
+    from oracle import md
+    u, eta_o, _ = f
+    k = 0.12
+    phi_o = eo.schur_dag(u, eta_o, k)
+    p = li.random_momenta(DIMS, 15)
+    u1, p1 = md.sexton_weingarten(u, p, phi_o, 5.7, k, 0.1, 3, 2, tol=1e-14, eo=True)
+    u2, p2 = md.sexton_weingarten(u1, -p1, phi_o, 5.7, k, 0.1, 3, 2, tol=1e-14, eo=True)
+    assert np.abs(u2 - u).max() < 1e-11 and np.abs(p2 + p).max() < 1e-10
+    dh = [md.sw_trajectory_dh(u, p, phi_o, 5.7, k, 0.5 / n, n, 1, tol=1e-14, eo=True)[2] for n in (8, 16)]
+    assert 3.5 < dh[0] / dh[1] < 4.5
