@@ -47,8 +47,9 @@ def schur_dag(u, psi_o, kappa, bc=-1):
     return psi_o - kappa * kappa * hop_to(u, hop_to(u, psi_o, 0, bc, True), 1, bc, True)
 
 
-def solve_normal(u, phi_o, kappa, bc=-1, tol=1e-14, max_iter=20000):
-    """X_o = (Dhat^dag Dhat)^-1 phi_o by textbook CG on the odd sites."""
+def solve_normal(u, phi_o, kappa, bc=-1, tol=1e-14, max_iter=20000, shift=0.0):
+    """X_o = (Dhat^dag Dhat + shift)^-1 phi_o by textbook CG on the odd sites
+    (one system; the multi-shift solver's result for each shift, by definition)."""
     x = np.zeros_like(phi_o)
     r = phi_o.copy()
     p = r.copy()
@@ -57,7 +58,7 @@ def solve_normal(u, phi_o, kappa, bc=-1, tol=1e-14, max_iter=20000):
     for _ in range(max_iter):
         if rr <= tol * tol * bb:
             break
-        q = schur_dag(u, schur(u, p, kappa, bc), kappa, bc)
+        q = schur_dag(u, schur(u, p, kappa, bc), kappa, bc) + shift * p
         alpha = rr / float(np.vdot(p.ravel(), q.ravel()).real)
         x = x + alpha * p
         r = r - alpha * q

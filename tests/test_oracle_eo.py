@@ -114,3 +114,17 @@ def test_eo_trajectory_reversible_and_second_order(f):
     assert np.abs(u2 - u).max() < 1e-11 and np.abs(p2 + p).max() < 1e-10
     dh = [md.sw_trajectory_dh(u, p, phi_o, 5.7, k, 0.5 / n, n, 1, tol=1e-14, eo=True)[2] for n in (8, 16)]
     assert 3.5 < dh[0] / dh[1] < 4.5
+
+
+@pytest.mark.parametrize("shift", [0.0, 0.05, 0.7])
+def test_shifted_solve_against_dense(f, shift):
+    """(Dhat^dag Dhat + shift) x = phi_o against numpy.linalg.solve of the dense Schur matrix."""
+    u, eta_o, _ = f
+    k = 0.13
+    m = _schur_matrix(u, k)
+    odd = _odd_indices()
+    b = eta_o.ravel()[odd]
+    ref = np.linalg.solve(m.conj().T @ m + shift * np.eye(m.shape[0]), b)
+    x = eo.solve_normal(u, eta_o, k, shift=shift, tol=1e-14)
+    assert np.abs(x.ravel()[odd] - ref).max() < 1e-11 * np.abs(ref).max()
+    assert np.abs(np.delete(x.ravel(), odd)).max() == 0.0  # stays on the odd sites
