@@ -319,6 +319,28 @@ typedef struct lgt_batch_item {
 LGT_API lgt_status lgt_cg_solve_batch(lgt_ctx* ctx, const void* U, int32_t n, const lgt_batch_item* items,
                                       const lgt_solver_params* params, lgt_solver_stats* stats_per_item);
 
+/* Multi-shift solve, the building block of a rational (RHMC) pseudofermion
+ * action (RHMC is one of the method's target algorithms, Sec. I): for each
+ * of nshift (1..32) shifts sigma_i >= 0,
+ *   X_i = (Mhat^dag Mhat + sigma_i)^-1 phi_o,
+ * Mhat = 1 - kappa^2 H_oe H_eo the even/odd Schur operator of
+ * lgt_schur_dslash (only the odd sites of phi are read).  All shifts come
+ * from one Krylov space: one CG on Mhat^dag Mhat, with each shifted solution
+ * formed by scalar recurrences (shifted CG), so the cost is that of one
+ * solve plus one vector update per shift and iteration.  X (device, nshift
+ * canonical spinor pointers, caller-owned) receive X_i on the odd sites and
+ * zero on the even ones.  Each shift stops once its recursive residual is
+ * below tol / 2 relative to ||phi_o||; stats->true_rel_residual is the
+ * largest FP64 true residual ||phi_o - (Mhat^dag Mhat + sigma_i) X_i|| /
+ * ||phi_o|| over the shifts, NOT_CONVERGED if it exceeds tol (or max_iter
+ * was reached).  FP64 only: other precisions return UNSUPPORTED.
+ * INVALID_ARGUMENT for a null pointer, a negative or non-finite shift, or
+ * nshift outside 1..32.  Holds 2 * nshift FP64 half spinors of workspace
+ * on the context, kept until it is destroyed or a larger nshift is asked. */
+LGT_API lgt_status lgt_cg_solve_multishift(lgt_ctx* ctx, const void* U, const void* phi, double kappa,
+                                           int32_t nshift, const double* shifts, void* const* X,
+                                           const lgt_solver_params* params, lgt_solver_stats* stats);
+
 /* Measurement entry point: times nrep back-to-back launches of the
  * even/odd hop kernel H_eo (the dominant kernel of the CG; FP64 for
  * precision = LGT_FP64, FP32 otherwise) on links U and input spinor psi,

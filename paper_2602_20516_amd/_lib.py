@@ -94,6 +94,8 @@ PROTOTYPES = {
                                    ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
     "lgt_md_step_eo": (_st, [_vp, _vp, _vp, _vp, _d, _d, _d, _i, _i, ctypes.POINTER(SolverParams),
                              ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
+    "lgt_cg_solve_multishift": (_st, [_vp, _vp, _vp, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_vp),
+                                      ctypes.POINTER(SolverParams), ctypes.POINTER(SolverStats)]),
 }
 
 _LIB = None

@@ -358,6 +358,24 @@ class Lattice:
         _check(self.lib, self.ctx, st, stats)
         return dh.value, stats.as_dict()
 
+    def cg_solve_multishift(self, U, phi, kappa: float, shifts, params: Optional[Params] = None):
+        """lgt_cg_solve_multishift: X_i = (Mhat^dag Mhat + shifts[i])^-1 phi_o for every shift.
+
+        Returns (Xs, stats): one spinor per shift (zero on even sites)."""
+        params = params or Params()
+        n = len(shifts)
+        Xs = [self.empty_spinor() for _ in range(n)]
+        sh = (ctypes.c_double * max(n, 1))(*[float(v) for v in shifts])
+        ptrs = (ctypes.c_void_p * max(n, 1))(*[self._field(x, "spinor", f"X[{i}]") for i, x in enumerate(Xs)])
+        stats = SolverStats()
+        cp = params.to_c()
+        self._bind_stream()
+        st = self.lib.lgt_cg_solve_multishift(self.ctx, self._field(U, "gauge", "U"),
+                                              self._field(phi, "spinor", "phi"), float(kappa), n, sh, ptrs,
+                                              ctypes.byref(cp), ctypes.byref(stats))
+        _check(self.lib, self.ctx, st, stats)
+        return Xs, stats.as_dict()
+
     def hop_benchmark(self, U, psi, precision: str = "fp64", nrep: int = 50) -> float:
         """lgt_hop_benchmark: mean duration (ms) of one even/odd hop launch."""
         ms = ctypes.c_double()

@@ -15,7 +15,6 @@ namespace {
 
 std::string g_create_error;
 
-enum { kPhi = 0, kX = 1, kY = 2, kStageA = 11, kStageB = 12 };
 // packed gauge scratch used here (see smear.hip): thin links, smeared output, gradient
 enum { kThin = 6, kSmeared = 8, kGradIn = 9, kU0 = 10, kP0 = 11 };
 
@@ -184,6 +183,7 @@ lgt_status lgt_destroy(lgt_ctx* c) {
   if (!c) return LGT_OK;
   if (c->stream || c->U64) (void)hipStreamSynchronize(c->stream);
   lgt_ctx_free_batch(c);
+  lgt_ctx_free_multishift(c);
   for (auto* p : c->full64) (void)hipFree(p);
   for (auto* p : c->half32) (void)hipFree(p);
   (void)hipFree(c->U64);
@@ -640,6 +640,37 @@ lgt_status lgt_cg_solve_batch(lgt_ctx* c, const void* U, int32_t n, const lgt_ba
   });
   if (s == LGT_OK && nc) {
     c->err = "solver did not reach the tolerance for every right-hand side";
+    return LGT_ERR_NOT_CONVERGED;
+  }
+  return s;
+}
+
+lgt_status lgt_cg_solve_multishift(lgt_ctx* c, const void* U, const void* phi, double kappa, int32_t nshift,
+                                   const double* shifts, void* const* X, const lgt_solver_params* params,
+                                   lgt_solver_stats* stats) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  bool nc = false;
+  lgt_status s = guarded(c, [&] {
+    require(U && phi && shifts && X, "null pointer");
+    require(nshift >= 1 && nshift <= lgt_ctx_max_shifts(), "nshift out of range (1 to 32)");
+    require(std::isfinite(kappa), "kappa must be finite");
+    for (int i = 0; i < nshift; ++i) {
+      require(std::isfinite(shifts[i]) && shifts[i] >= 0.0, "shifts must be finite and non-negative");
+      require(X[i] != nullptr, "null output field");
+    }
+    const SolverOpts o = parse(params);
+    if (o.precision != LGT_FP64) throw Error(LGT_ERR_UNSUPPORTED, "the multi-shift solve runs in FP64 only");
+    Timer tm(c);
+    pack_links(c, U, false);
+    pack_spinor(c, phi, c->f64(kPhi));
+    check_nonfinite(c, "U or phi");
+    c->kappa = kappa;
+    const SolveStats st = c->solve_multishift(c->f64(kPhi), nshift, shifts, X, o);
+    fill_stats(stats, st, tm.stop());
+    nc = !st.converged;
+  });
+  if (s == LGT_OK && nc) {
+    c->err = "solver did not reach the tolerance for every shift";
     return LGT_ERR_NOT_CONVERGED;
   }
   return s;

@@ -90,7 +90,7 @@ struct EpiSchurNorm {  // w = x + coef * acc (odd sites), block partials of |w|^
 };
 
 template <typename R, typename T>
-struct EpiSchurCG {  // q = w + coef * acc; x += alpha p; r -= alpha q; block partials of |r|^2
+struct EpiSchurCG {  // q = w + coef * acc; x += alpha p (if x); r -= alpha q; block partials of |r|^2
   static constexpr bool kReduce = true;
   const T* w;
   R2<R>* x;
@@ -106,10 +106,8 @@ struct EpiSchurCG {  // q = w + coef * acc; x += alpha p; r -= alpha q; block pa
     for (int i = 0; i < 3; ++i) {
       const size_t o = (size_t)(3 * spin + i) * vh + cb;
       const C<R> q = Store<R, T>::ld(w + o) + coef * acc[i];
-      const C<R> pv = Store<R, T>::ld(p + o);
-      C<R> xv = ld<R>(x + o) + alpha * pv;
+      if (x) st<R>(x + o, ld<R>(x + o) + alpha * Store<R, T>::ld(p + o));
       C<R> rv = ld<R>(r + o) - alpha * q;
-      st<R>(x + o, xv);
       st<R>(r + o, rv);
       red += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
     }
@@ -235,10 +233,10 @@ hipError_t launch_hop_schur_norm(const Geom& g, HopIn<R, T> hin, T* w, const T* 
 
 template <typename R, typename T, bool DAG>
 hipError_t launch_hop_schur_cg(const Geom& g, HopIn<R, T> hin, const T* w, R2<R>* x, R2<R>* r, const T* p,
-                               double coef, SolverState* st, Reduce red, hipStream_t s) {
+                               double coef, SolverState* st, Reduce red, hipStream_t s, bool with_finalize) {
   EpiSchurCG<R, T> e{w, x, r, p, R(coef), g.vh, st};
   hipError_t err = launch<R, DAG>(g, 1, hin, e, red.partials, s, red.capacity);
-  if (err != hipSuccess) return err;
+  if (err != hipSuccess || !with_finalize) return err;
   return launch_finalize(kFinCgStep, nblk_parity(g), red, st, 0, 0.0, 0, s);
 }
 
@@ -268,7 +266,7 @@ hipError_t launch_hop_residual(const Geom& g, HopIn<double> hin, const double2* 
   template hipError_t launch_hop_schur_norm<R, T, DAG>(const Geom&, HopIn<R, T>, T*, const T*, double,       \
                                                         SolverState*, Reduce, hipStream_t);                 \
   template hipError_t launch_hop_schur_cg<R, T, DAG>(const Geom&, HopIn<R, T>, const T*, R2<R>*, R2<R>*,     \
-                                                      const T*, double, SolverState*, Reduce, hipStream_t);
+                                                      const T*, double, SolverState*, Reduce, hipStream_t, bool);
 
 LGT_INST_AXPY(double, false, double2)
 LGT_INST_AXPY(double, true, double2)

@@ -35,6 +35,13 @@ struct SolveStats {
   bool converged = true;
 };
 
+// slots of the context's full FP64 scratch fields (lgt_ctx::f64)
+enum ScratchSlot {
+  kPhi = 0, kX = 1, kY = 2, kRes = 3, kE = 4, kYtmp = 5,
+  kW0 = 6, kW1 = 7, kW2 = 8, kW3 = 9, kW4 = 10,
+  kStageA = 11, kStageB = 12
+};
+
 struct SolverOpts {
   int precision = LGT_FP64;
   double tol = 1e-10;
@@ -44,9 +51,12 @@ struct SolverOpts {
 
 }  // namespace lgt
 
-struct BatchWork;  // batched-solver workspace (batch.hip)
+struct BatchWork;       // batched-solver workspace (batch.hip)
+struct MultiShiftWork;  // multi-shift solver workspace (multishift.hip)
 struct lgt_ctx;
 void lgt_ctx_free_batch(lgt_ctx* c);
+void lgt_ctx_free_multishift(lgt_ctx* c);
+int lgt_ctx_max_shifts();
 
 struct lgt_ctx {
   lgt::Geom g{};
@@ -148,6 +158,11 @@ struct lgt_ctx {
   double bench_mhop(int nr, bool f32, const void* psi, int nrep);  // ms per multi-RHS hop launch
   std::vector<lgt::SolveStats> solve_batch(int nr, const double* kappas, const void* const* phis, void* const* Xs,
                                            void* const* Ys, const lgt::SolverOpts& o);
+
+  // multi-shift CG (multishift.hip): X_i = (Mhat^dag Mhat + shifts[i])^-1 phi_o
+  MultiShiftWork* mshift = nullptr;
+  lgt::SolveStats solve_multishift(const double2* phi, int ns, const double* shifts, void* const* Xout,
+                                   const lgt::SolverOpts& o);
 
   double kappa = 0.0;  // hopping parameter of the current solve
  private:

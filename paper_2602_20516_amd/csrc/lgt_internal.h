@@ -125,9 +125,11 @@ hipError_t launch_hop_axpy(const Geom& g, int p_out, HopIn<R, T> hin, T* out_eve
 template <typename R, typename T, bool DAG>
 hipError_t launch_hop_schur_norm(const Geom& g, HopIn<R, T> hin, T* w, const T* x, double coef, SolverState* st,
                                  Reduce red, hipStream_t s);
+// (x may be null: the multi-shift solver tracks no base solution; without
+// with_finalize the caller launches its own finalize)
 template <typename R, typename T, bool DAG>
 hipError_t launch_hop_schur_cg(const Geom& g, HopIn<R, T> hin, const T* w, R2<R>* x, R2<R>* r, const T* p,
-                               double coef, SolverState* st, Reduce red, hipStream_t s);
+                               double coef, SolverState* st, Reduce red, hipStream_t s, bool with_finalize = true);
 // Residual of the full operator: r = phi - (self + coef * H in) over both parities,
 // result[slot] = |r|^2
 template <bool DAG>

@@ -14,7 +14,6 @@ namespace {
 // 4 gradient ping-pong, 5 fermion gradient, 6 thin links (ABI), 7 recomputed
 // level, 8 smeared output (ABI)
 enum { kPing = 0, kPong = 1, kLam = 2, kGpart = 3, kGtmp = 4, kGf = 5, kRecomp = 7 };
-enum { kPhi = 0, kX = 1, kY = 2 };
 }  // namespace
 
 double2* lgt_ctx::g64(int i) {

@@ -61,12 +61,6 @@ void lgt_ctx::read_results(int n) {
   sync();
 }
 
-// scratch full fields
-enum {
-  kPhi = 0, kX = 1, kY = 2, kRes = 3, kE = 4, kYtmp = 5,
-  kW0 = 6, kW1 = 7, kW2 = 8, kW3 = 9, kW4 = 10,
-  kStageA = 11, kStageB = 12
-};
 
 void lgt_ctx::dslash_full(const double2* in, double2* out, double k, bool dag) {
   const size_t h = half_elems();
