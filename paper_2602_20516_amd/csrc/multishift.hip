@@ -25,7 +25,7 @@ using namespace lgt;
 
 namespace {
 
-constexpr int kMaxShift = 32;
+constexpr int kMaxShift = 32;  // two result slots per shift fill the context's 64
 
 struct ShiftState {
   int ns, pad;
@@ -35,37 +35,43 @@ struct ShiftState {
   int done[kMaxShift], upd[kMaxShift];
 };
 
-// rr = sum of the |r|^2 partials of the last hop; beta; shift recurrences; stop test
+// rr = sum of the |r|^2 partials of the last hop; beta; the shift
+// recurrences (thread i: shift i) and the stop test.
 __global__ __launch_bounds__(256) void k_msfinalize(int nblk, const double* __restrict__ partials, SolverState* st,
                                                     ShiftState* ss, Mailbox* mb) {
+  const int i = threadIdx.x;
+  const int ns = ss->ns;
   if (st->done != kDoneRunning) {  // the iteration was skipped
-    if (threadIdx.x == 0) {
-      for (int i = 0; i < ss->ns; ++i) ss->upd[i] = 0;
-      post_progress(mb, st->iter, 1);
-    }
+    if (i < ns) ss->upd[i] = 0;
+    if (i == 0) post_progress(mb, st->iter, 1);
     return;
   }
+  __shared__ double s_rr;
   double tot[1];
   sum_partials<256, 1>(partials, nblk, tot);
-  if (threadIdx.x != 0) return;
-  const double rr = tot[0];
+  if (i == 0) s_rr = tot[0];
+  __syncthreads();
+  const double rr = s_rr;
   const double a = st->alpha;  // alpha of this iteration (formed by the third hop)
   const double b = rr / st->rr;
-  int all = 1;
-  for (int i = 0; i < ss->ns; ++i) {
+  int open = 0;
+  if (i < ns) {
     ss->upd[i] = 0;
-    if (ss->done[i]) continue;
-    const double z = ss->zeta[i], zp = ss->zeta_prev[i];
-    const double zn = z * zp * ss->alpha_prev /
-                      (a * ss->beta_prev * (zp - z) + zp * ss->alpha_prev * (1.0 + ss->sigma[i] * a));
-    ss->alpha_s[i] = a * zn / z;
-    ss->beta_s[i] = b * (zn / z) * (zn / z);
-    ss->zeta_prev[i] = z;
-    ss->zeta[i] = zn;
-    ss->upd[i] = 1;
-    if (zn * zn * rr <= ss->rr_stop) ss->done[i] = 1;
-    else all = 0;
+    if (!ss->done[i]) {
+      const double z = ss->zeta[i], zp = ss->zeta_prev[i];
+      const double zn = z * zp * ss->alpha_prev /
+                        (a * ss->beta_prev * (zp - z) + zp * ss->alpha_prev * (1.0 + ss->sigma[i] * a));
+      ss->alpha_s[i] = a * zn / z;
+      ss->beta_s[i] = b * (zn / z) * (zn / z);
+      ss->zeta_prev[i] = z;
+      ss->zeta[i] = zn;
+      ss->upd[i] = 1;
+      if (zn * zn * rr <= ss->rr_stop) ss->done[i] = 1;
+      else open = 1;
+    }
   }
+  const int all = __syncthreads_and(!open);
+  if (i != 0) return;
   ss->alpha_prev = a;
   ss->beta_prev = b;
   st->beta = b;
@@ -253,19 +259,22 @@ SolveStats lgt_ctx::solve_multishift(const double2* phi, int ns, const double* s
   st.iters = b0.iter;
   if (b0.done == kDoneBreakdown) throw Error(LGT_ERR_NONFINITE, "multi-shift CG breakdown");
   if (b0.done == kDoneMaxIter) st.converged = false;
+  // true residuals, all norms read back at once (two result slots per shift)
   double2* q = w->q;
-  double worst = 0.0;
   for (int i = 0; i < ns; ++i) {
     double2* xi = w->X + (size_t)i * h;
     apply_mhat_dag_mhat64(false, xi, q);
     LGT_HIP(launch_axpy64(n, shifts[i], xi, q, stream));
     LGT_HIP(launch_xmy64(n, phio, q, stream));  // q = phi_o - (A + sigma_i) X_i
-    LGT_HIP(launch_norm_dot(n, q, nullptr, red(), 0, stream));
-    read_results(1);
-    const double tr = std::sqrt(host_result[0] / bb);
+    LGT_HIP(launch_norm_dot(n, q, nullptr, red(), 2 * i, stream));
+    emit(i, xi);
+  }
+  read_results(2 * ns);
+  double worst = 0.0;
+  for (int i = 0; i < ns; ++i) {
+    const double tr = std::sqrt(host_result[2 * i] / bb);
     if (!std::isfinite(tr)) throw Error(LGT_ERR_NONFINITE, "non-finite residual");
     worst = std::max(worst, tr);
-    emit(i, xi);
   }
   st.true_res = worst;
   if (worst > o.tol) st.converged = false;

@@ -128,3 +128,15 @@ def test_shifted_solve_against_dense(f, shift):
     x = eo.solve_normal(u, eta_o, k, shift=shift, tol=1e-14)
     assert np.abs(x.ravel()[odd] - ref).max() < 1e-11 * np.abs(ref).max()
     assert np.abs(np.delete(x.ravel(), odd)).max() == 0.0  # stays on the odd sites
+
+
+def test_shifted_solve_large_shift_limit(f):
+    """(A + s)^-1 phi = phi/s - A phi/s^2 + O(s^-3): at s = 1e6 the first two
+    terms of the Neumann series fix x to ~1e-12 relative."""
+    u, eta_o, _ = f
+    k = 0.13
+    s = 1e6
+    x = eo.solve_normal(u, eta_o, k, shift=s, tol=1e-15)
+    a_eta = eo.schur_dag(u, eo.schur(u, eta_o, k), k)
+    approx = eta_o / s - a_eta / s**2
+    assert np.abs(x - approx).max() < 1e-11 * np.abs(eta_o / s).max()
