@@ -20,6 +20,10 @@ Other workloads (each prints its own JSON line; none is the headline):
               sequential solves, batched-hop roofline
   --config 5  32^3x64, kappa 0.135, 2 stout levels rho 0.1: one leapfrog
               trajectory (10 steps, tau 1), dH, reversibility
+  --stout-depth N  32^3x64 (the config-5 lattice) with N stout levels (default
+              8, rho 0.1): the reverse pass through the chain under several
+              checkpoint schedules (none kept ... every level kept), and the
+              whole smeared force with none and with every level kept
   --multishift  16^4 (headline links and kappa): one multi-shift CG with 12
               shifts 1e-4..10 on the even/odd normal operator (the solve
               of a rational pseudofermion action), FP64, against 12
@@ -31,7 +35,7 @@ Sexton-Weingarten integrator (10 inner steps), and reports <Delta H>,
 rms Delta H, <exp(-Delta H)> and acceptance against dt.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--config 2|3|4|5]
-                       [--multishift] [--study dh-vs-dt]
+                       [--multishift] [--stout-depth N] [--study dh-vs-dt]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -116,6 +120,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4, 5))
     ap.add_argument("--multishift", action="store_true")
+    ap.add_argument("--stout-depth", type=int, default=0, help="stout levels of the checkpointing benchmark")
     ap.add_argument("--study", default=None, choices=("dh-vs-dt",))
     ap.add_argument("--therm", type=int, default=100, help="thermalisation trajectories of the study")
     ap.add_argument("--meas", type=int, default=40, help="measured trajectories per step size in the study")
@@ -129,6 +134,9 @@ def main():
         return
     if args.multishift:
         print(json.dumps(bench_multishift(args)), flush=True)
+        return
+    if args.stout_depth:
+        print(json.dumps(bench_stout_depth(args)), flush=True)
         return
     if args.config != 2:
         rec = {3: bench_c3, 4: bench_c4, 5: bench_c5}[args.config](args)
@@ -465,6 +473,70 @@ def bench_multishift(args):
         "speedup_vs_single_shift_solves": round(ts / tm, 3),
         "note": "the shifted updates (x_i, p_i for every unconverged shift) move 4 x 12 V/2 x 16 B per shift "
                 "and iteration; kernel durations in the committed rocprofv3 summary",
+    }
+
+
+def bench_stout_depth(args):
+    """Checkpoint schedules of a deep stout chain at 32^3x64: reverse pass and smeared force."""
+    import numpy as np
+    import torch
+
+    import lgt_inputs as li
+    import paper_2602_20516_amd as lgt
+
+    c = li.config(5)
+    dims, rho, n = c["dims"], c["rho"], args.stout_depth
+    V = int(np.prod(dims))
+    log("bench stout-depth: generating inputs")
+    U = torch.from_numpy(li.random_links(dims, c["eps"], c["seeds"]["links"])).to("cuda")
+    E = torch.from_numpy(li.gaussian_spinor(dims, c["seeds"]["eta"])).to("cuda")
+    GT = torch.from_numpy(li.random_links(dims, 1.0, 7)).to("cuda")
+    lat = lgt.Lattice(dims)
+    slot_gb = 72 * 16 * (V // 2) / 1e9
+    reps = max(1, min(args.steps, 5))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    caps = sorted({0, 1, 2, int(round(n ** 0.5)), n - 1})
+    backprop = []
+    out = lat.empty_gauge()
+    for cap in caps:
+        lat.set_stout_checkpoints(cap)
+        t = timed(lambda: lat.stout_backprop(U, GT, rho, n, out=out))
+        sch = lat.stout_last_schedule()
+        backprop.append({"stored_levels": sch["stored_levels"], "recompute_passes": sch["recompute_passes"],
+                         "extra_GB": round(sch["stored_levels"] * slot_gb, 2), "ms": round(t * 1e3, 2)})
+        log(f"bench stout-depth: backprop {backprop[-1]}")
+    # one level forward alone, for the per-pass cost
+    t_fwd = timed(lambda: lat.stout_smear(U, rho, 1, out=out))
+    phi = lat.dslash(lat.stout_smear(U, rho, n), E, c["kappa"], dagger=True)
+    prm = lgt.Params(precision=c["precision"], tol=c["tol"])
+    force = {}
+    for name, cap in (("none_kept", 0), ("all_kept", -1)):
+        lat.set_stout_checkpoints(cap)
+        t = timed(lambda: lat.smeared_force(U, phi, c["beta"], c["kappa"], rho, n, prm, "force", out=out))
+        st = lat.smeared_force(U, phi, c["beta"], c["kappa"], rho, n, prm, "force", out=out)[2]
+        force[name] = {"ms": round(t * 1e3, 2), "iters": st["iters"],
+                       "stored_levels": lat.stout_last_schedule()["stored_levels"]}
+        log(f"bench stout-depth: force {name} {force[name]}")
+    best, worst = backprop[-1]["ms"], backprop[0]["ms"]
+    return {
+        "metric": f"reverse pass through {n} stout levels at 32^3x64, ms, by checkpoint schedule",
+        "value": best, "unit": "ms", "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": best,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded SU(3) links eps=0.2, Gaussian eta, random cotangent)",
+        "config": {"workload": f"32^3x64 stout chain, rho {rho}, {n} levels: lgt_stout_backprop under checkpoint "
+                               f"caps {caps}; smeared force (FP32 inner CG to FP64 true residual {c['tol']}, kappa "
+                               f"{c['kappa']}) with no level and every level kept", "dims": list(dims), "nlevels": n},
+        "stout_forward_level_ms": round(t_fwd * 1e3, 3), "level_field_GB": round(slot_gb, 3),
+        "backprop": backprop, "speedup_all_kept_vs_none": round(worst / best, 3), "smeared_force": force,
     }
 
 

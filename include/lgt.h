@@ -232,15 +232,45 @@ LGT_API lgt_status lgt_md_step(lgt_ctx* ctx, void* U, void* P, const void* phi, 
  *                                   + U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu)],
  *   U' = exp(P_su3[C U^dag]) U,
  * all directions from the previous level, no reunitarization.  FP64;
- * nlevels >= 0; U_in and U_out may not overlap. */
+ * nlevels 0..256; U_in and U_out may not overlap. */
 LGT_API lgt_status lgt_stout_smear(lgt_ctx* ctx, const void* U_in, void* U_out, double rho, int32_t nlevels);
 
 /* Reverse mode through the smearing (the adjoint update of eq. 3, written
  * by hand): G_out = gradient at U_in of Re tr(G_top^dag stout^n(U_in)), in the
- * G convention.  Intermediate levels are recomputed from U_in, not stored.
- * FP64.  G_top is a gauge-type buffer at the smeared links. */
+ * G convention.  The intermediate levels each level's adjoint needs follow
+ * the context's checkpoint schedule (lgt_set_stout_checkpoints): the sweep
+ * U_in -> the last forward checkpoint runs first, the rest are recomputed as
+ * the schedule says.  The result does not depend on the schedule (same bits).
+ * FP64.  G_top is a gauge-type buffer at the smeared links.  nlevels 0..256. */
 LGT_API lgt_status lgt_stout_backprop(lgt_ctx* ctx, const void* U_in, const void* G_top, double rho,
                                       int32_t nlevels, void* G_out);
+
+/* Checkpointing of deep smearing chains (memory reduction by checkpointing
+ * is the first extension the paper's outlook names, Sec. IV).  The reverse
+ * pass through n levels needs U_{n-1}, ..., U_0 in that order.  The forward
+ * sweep that builds U_n for the solver keeps up to max_stored_levels of them
+ * (one gauge field of 72 * V complex doubles each, held by the context);
+ * every other level is recomputed from the nearest kept one, along the
+ * schedule with the fewest recomputed smearing passes for that many slots
+ * (dynamic programming over segment splits, lgt_stout_schedule).  With
+ * n - 1 slots nothing is recomputed; with 0 every level is recomputed from
+ * the thin links (n(n-1)/2 passes).  max_stored_levels = -1 (the default):
+ * as many as the device's free memory holds beyond a reserve of 1/8 of its
+ * total.  Applies to lgt_smeared_force, lgt_stout_backprop and the smeared
+ * trajectories.  INVALID_ARGUMENT for values below -1. */
+LGT_API lgt_status lgt_set_stout_checkpoints(lgt_ctx* ctx, int32_t max_stored_levels);
+
+/* What the last reverse pass through the smearing did: levels kept in
+ * checkpoint slots and smearing passes recomputed beyond the forward sweep. */
+LGT_API lgt_status lgt_stout_last_schedule(const lgt_ctx* ctx, int32_t* stored_levels, int64_t* recompute_passes);
+
+/* The schedule alone (host computation, no context, no device): the
+ * recomputed passes of an nlevels-level reverse pass with stored_levels
+ * slots, and the levels the forward sweep keeps (checkpoints_or_null: room
+ * for stored_levels entries, increasing; n_checkpoints_or_null: their
+ * count).  INVALID_ARGUMENT for nlevels outside 0..256 or stored_levels < 0. */
+LGT_API lgt_status lgt_stout_schedule(int32_t nlevels, int32_t stored_levels, int64_t* recompute_passes,
+                                      int32_t* checkpoints_or_null, int32_t* n_checkpoints_or_null);
 
 /* Force of the smeared action S = S_G(U) + phi^dag (D^dag D)^-1 phi with D
  * built on stout^n(U) (links enter D only): the pseudofermion force on the

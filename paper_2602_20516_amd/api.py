@@ -376,6 +376,16 @@ class Lattice:
         _check(self.lib, self.ctx, st, stats)
         return Xs, stats.as_dict()
 
+    def set_stout_checkpoints(self, max_stored_levels: int = -1):
+        """lgt_set_stout_checkpoints: cap on the smearing levels kept for the reverse pass (-1: automatic)."""
+        _check(self.lib, self.ctx, self.lib.lgt_set_stout_checkpoints(self.ctx, int(max_stored_levels)))
+
+    def stout_last_schedule(self) -> dict:
+        """lgt_stout_last_schedule: levels kept and passes recomputed by the last reverse pass."""
+        s, p = ctypes.c_int32(), ctypes.c_int64()
+        _check(self.lib, self.ctx, self.lib.lgt_stout_last_schedule(self.ctx, ctypes.byref(s), ctypes.byref(p)))
+        return {"stored_levels": s.value, "recompute_passes": p.value}
+
     def hop_benchmark(self, U, psi, precision: str = "fp64", nrep: int = 50) -> float:
         """lgt_hop_benchmark: mean duration (ms) of one even/odd hop launch."""
         ms = ctypes.c_double()
@@ -397,6 +407,19 @@ class Lattice:
 
 
 # Module-level functions with the ABI's names.
+def stout_schedule(nlevels: int, stored_levels: int) -> dict:
+    """lgt_stout_schedule (host only): recomputed passes and forward checkpoints of the
+    reverse pass through nlevels stout levels with stored_levels slots."""
+    lib = _lib.load()
+    passes = ctypes.c_int64()
+    cp = (ctypes.c_int32 * max(1, int(stored_levels)))()
+    ncp = ctypes.c_int32()
+    st = lib.lgt_stout_schedule(int(nlevels), int(stored_levels), ctypes.byref(passes), cp, ctypes.byref(ncp))
+    if st != _lib.LGT_OK:
+        raise LGTError(st, "invalid schedule arguments")
+    return {"recompute_passes": passes.value, "checkpoints": [cp[i] for i in range(ncp.value)]}
+
+
 def lgt_create(dims, fermion_bc: int = -1) -> Lattice:
     return Lattice(dims, fermion_bc)
 
@@ -480,3 +503,7 @@ def lgt_md_step_eo(lat: Lattice, U, P, phi, beta, kappa, dt, nsteps, n_inner=1, 
 
 def lgt_md_step_sw(lat: Lattice, U, P, phi, beta, kappa, rho, nlevels, dt, nsteps, n_inner, params=None):
     return lat.md_step_sw(U, P, phi, beta, kappa, dt, nsteps, n_inner, params, rho, nlevels)
+
+
+def lgt_cg_solve_multishift(lat: Lattice, U, phi, kappa, shifts, params=None):
+    return lat.cg_solve_multishift(U, phi, kappa, shifts, params)

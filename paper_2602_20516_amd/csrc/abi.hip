@@ -363,7 +363,7 @@ static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double b
   lgt_status s = guarded(c, [&] {
     require(U && P, "null field pointer");
     require(nsteps >= 1, "nsteps must be >= 1");
-    require(nlevels >= 0, "nlevels must be >= 0");
+    require(nlevels >= 0 && nlevels <= kMaxStoutLevels, "nlevels must be in 0..256");
     require(n_inner >= 1, "n_inner must be >= 1");
     require(std::isfinite(dt) && std::isfinite(rho), "dt and rho must be finite");
     const SolverOpts o = parse(params);
@@ -554,7 +554,7 @@ lgt_status lgt_stout_smear(lgt_ctx* c, const void* U_in, void* U_out, double rho
   if (!c) return LGT_ERR_INVALID_ARGUMENT;
   return guarded(c, [&] {
     require(U_in && U_out, "null field pointer");
-    require(nlevels >= 0 && std::isfinite(rho), "invalid smearing parameters");
+    require(nlevels >= 0 && nlevels <= kMaxStoutLevels && std::isfinite(rho), "invalid smearing parameters");
     double2* thin = c->g64(kThin);
     double2* out = c->g64(kSmeared);
     LGT_HIP(launch_pack(c->g, 36, (const double2*)U_in, thin, nullptr, c->flags, c->stream));
@@ -568,12 +568,12 @@ lgt_status lgt_stout_backprop(lgt_ctx* c, const void* U_in, const void* G_top, d
   if (!c) return LGT_ERR_INVALID_ARGUMENT;
   return guarded(c, [&] {
     require(U_in && G_top && G_out, "null field pointer");
-    require(nlevels >= 0 && std::isfinite(rho), "invalid smearing parameters");
+    require(nlevels >= 0 && nlevels <= kMaxStoutLevels && std::isfinite(rho), "invalid smearing parameters");
     double2* thin = c->g64(kThin);
     double2* G = c->g64(kGradIn);
     LGT_HIP(launch_pack(c->g, 36, (const double2*)U_in, thin, nullptr, c->flags, c->stream));
     LGT_HIP(launch_pack(c->g, 36, (const double2*)G_top, G, nullptr, c->flags, c->stream));
-    c->stout_backprop(thin, nlevels, rho, G);
+    c->stout_backprop(thin, nlevels, rho, G, c->stout_plan(nlevels), false);
     LGT_HIP(launch_unpack(c->g, 36, G, (double2*)G_out, c->stream));
   });
 }
@@ -586,7 +586,7 @@ lgt_status lgt_smeared_force(lgt_ctx* c, const void* U, const void* phi, double 
   lgt_status s = guarded(c, [&] {
     require(U && phi && out, "null field pointer");
     require(mode >= LGT_OUT_FORCE && mode <= LGT_OUT_MOMENTUM, "unknown output mode");
-    require(nlevels >= 0 && std::isfinite(rho), "invalid smearing parameters");
+    require(nlevels >= 0 && nlevels <= kMaxStoutLevels && std::isfinite(rho), "invalid smearing parameters");
     const SolverOpts o = parse(params);
     Timer tm(c);
     double2* thin = c->g64(kThin);
@@ -603,6 +603,38 @@ lgt_status lgt_smeared_force(lgt_ctx* c, const void* U, const void* phi, double 
     return LGT_ERR_NOT_CONVERGED;
   }
   return s;
+}
+
+lgt_status lgt_set_stout_checkpoints(lgt_ctx* c, int32_t max_stored_levels) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(max_stored_levels >= -1, "max_stored_levels must be -1 (automatic) or >= 0");
+    c->stout_slot_cap = max_stored_levels;
+  });
+}
+
+lgt_status lgt_stout_last_schedule(const lgt_ctx* c, int32_t* stored_levels, int64_t* recompute_passes) {
+  if (!c || !stored_levels || !recompute_passes) return LGT_ERR_INVALID_ARGUMENT;
+  *stored_levels = c->last_stout_slots;
+  *recompute_passes = c->last_stout_passes;
+  return LGT_OK;
+}
+
+lgt_status lgt_stout_schedule(int32_t nlevels, int32_t stored_levels, int64_t* recompute_passes,
+                              int32_t* checkpoints_or_null, int32_t* n_checkpoints_or_null) {
+  if (!recompute_passes || nlevels < 0 || nlevels > kMaxStoutLevels || stored_levels < 0)
+    return LGT_ERR_INVALID_ARGUMENT;
+  try {
+    const StoutSchedule plan(nlevels, stored_levels);
+    *recompute_passes = plan.cost();
+    const std::vector<int> cp = plan.forward_checkpoints();
+    if (checkpoints_or_null)
+      for (size_t i = 0; i < cp.size(); ++i) checkpoints_or_null[i] = cp[i];
+    if (n_checkpoints_or_null) *n_checkpoints_or_null = (int32_t)cp.size();
+  } catch (...) {
+    return LGT_ERR_OUT_OF_MEMORY;
+  }
+  return LGT_OK;
 }
 
 lgt_status lgt_cg_solve_batch(lgt_ctx* c, const void* U, int32_t n, const lgt_batch_item* items,

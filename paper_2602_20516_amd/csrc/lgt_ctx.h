@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <memory>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -11,6 +12,7 @@
 
 #include "../../include/lgt.h"
 #include "lgt_internal.h"
+#include "stout_schedule.h"
 
 namespace lgt {
 
@@ -148,7 +150,18 @@ struct lgt_ctx {
 
   // stout smearing (smear.hip): U0, G packed FP64
   void smear(const double2* U0, int nlevels, double rho, double2* dst);
-  void stout_backprop(const double2* U0, int nlevels, double rho, double2* G);
+  // checkpointed reverse pass (stout_schedule.h): slot cap (-1: as many
+  // levels as device memory holds), the schedule for n levels, the forward
+  // sweep that keeps its checkpoints, and the reverse pass over it
+  int stout_slot_cap = -1;
+  int last_stout_slots = 0;
+  int64_t last_stout_passes = 0;
+  std::unique_ptr<lgt::StoutSchedule> sched;
+  int stout_slots(int nlevels);
+  const lgt::StoutSchedule& stout_plan(int nlevels);
+  void smear_checkpointed(const double2* U0, int nlevels, double rho, double2* dst, const lgt::StoutSchedule& plan);
+  void stout_backprop(const double2* U0, int nlevels, double rho, double2* G, const lgt::StoutSchedule& plan,
+                      bool forward_done);
   lgt::SolveStats smeared_force(const double2* U0, const double2* phi, double beta, double rho, int nlevels,
                                 const lgt::SolverOpts& o, int mode, double dt, void* out, int layout,
                                 double* S_F);
