@@ -113,6 +113,11 @@ def load() -> ctypes.CDLL:
         raise ImportError(
             f"{LIB_PATH} is missing: build the gfx950 library first "
             "(python paper_2602_20516_amd/build.py)")
+    # PyTorch ships its own ROCm runtime libraries.  Loaded first, they also
+    # satisfy this library's HIP dependency, so the process holds one HIP
+    # runtime; loaded after this library, they bring a second runtime, and
+    # whichever of the two initialises later finds no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in PROTOTYPES.items():
         fn = getattr(lib, name)

@@ -8,6 +8,8 @@
 // Vector kernels work on flat arrays of n complex numbers (grid-stride,
 // unit-stride).  Reductions write block partials; the one-block finalize
 // kernel sums them in a fixed order (deterministic, see block_partials).
+#include <algorithm>
+
 #include "lgt_internal.h"
 
 namespace lgt {
@@ -146,13 +148,6 @@ template <int NV>
 __global__ __launch_bounds__(256) void k_finalize(int mode, int nblk, const double* __restrict__ partials,
                                                   SolverState* st, double* result, double tol, int max_iter,
                                                   Mailbox* mb) {
-  if (mode == kFinCgStep && st->done != kDoneRunning) {  // the iteration was skipped
-    if (threadIdx.x == 0) {
-      if (st->done == kDoneUpdate) st->done = kDoneUpdateHeld;
-      post_progress(mb, st->iter, 1);
-    }
-    return;
-  }
   double tot[NV];
   sum_partials<256, NV>(partials, nblk, tot);
   if (threadIdx.x != 0) return;
@@ -172,17 +167,6 @@ __global__ __launch_bounds__(256) void k_finalize(int mode, int nblk, const doub
     st->pap = 0.0;
     st->delta2 = 0.0;
     st->done = !isfinite(rr) ? kDoneBreakdown : (rr == 0.0 ? kDoneConverged : kDoneRunning);
-  } else {  // kFinCgStep
-    const double rr = tot[0];
-    st->beta = rr / st->rr;
-    st->rr = rr;
-    st->iter += 1;
-    if (rr > st->rr_max) st->rr_max = rr;
-    if (!isfinite(rr)) st->done = kDoneBreakdown;
-    else if (rr <= st->rr_stop) st->done = st->delta2 > 0.0 ? kDoneUpdate : kDoneConverged;
-    else if (rr <= st->delta2 * st->rr_max) st->done = kDoneUpdate;
-    else if (st->iter >= st->max_iter) st->done = kDoneMaxIter;
-    post_progress(mb, st->iter, st->done != kDoneRunning);
   }
 }
 
@@ -199,26 +183,67 @@ hipError_t launch_finalize(int mode, int nblk, Reduce red, SolverState* st, int 
 }
 
 template <typename R, typename T>
-__global__ __launch_bounds__(256) void k_cg_xpay(int n, const R2<R>* __restrict__ r, T* __restrict__ p,
-                                                 const SolverState* st) {
-  if (st->done != kDoneRunning) return;
-  const R beta = R(st->beta);
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const C<R> rv = ld<R>(r + i);
-    const C<R> pv = Store<R, T>::ld(p + i);
-    Store<R, T>::st(p + i, C<R>{rv.re + beta * pv.re, rv.im + beta * pv.im});
+__global__ __launch_bounds__(256) void k_cg_step(int n, int nblk, const double* __restrict__ partials,
+                                                 const R2<R>* __restrict__ r, T* __restrict__ p, SolverState* st,
+                                                 Mailbox* mb) {
+  const int done0 = st->done;
+  if (done0 != kDoneRunning) {  // the iteration was skipped (or block 0 below already stopped it)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (done0 == kDoneUpdate) st->done = kDoneUpdateHeld;
+      post_progress(mb, st->iter, 1);
+    }
+    return;
+  }
+  // every block forms the same rr (same partials, same order) and so takes
+  // the same decision; the inputs are the copies the third hop made, which
+  // block 0's writes below do not touch
+  __shared__ double s_rr;
+  double tot[1];
+  sum_partials<256, 1>(partials, nblk, tot);
+  if (threadIdx.x == 0) s_rr = tot[0];
+  __syncthreads();
+  const double rr = s_rr;
+  const double beta = rr / st->rr_prev;
+  const int iter = st->iter_prev + 1;
+  const double rr_max = fmax(st->rr_max, rr);  // block 0 may have stored this same value already
+  int code = kDoneRunning;
+  if (!isfinite(rr)) code = kDoneBreakdown;
+  else if (rr <= st->rr_stop) code = st->delta2 > 0.0 ? kDoneUpdate : kDoneConverged;
+  else if (rr <= st->delta2 * rr_max) code = kDoneUpdate;
+  else if (iter >= st->max_iter) code = kDoneMaxIter;
+  if (code == kDoneRunning) {
+    const R b = R(beta);
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+      const C<R> rv = ld<R>(r + i);
+      const C<R> pv = Store<R, T>::ld(p + i);
+      Store<R, T>::st(p + i, C<R>{rv.re + b * pv.re, rv.im + b * pv.im});
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->beta = beta;
+    st->rr = rr;
+    st->iter = iter;
+    st->rr_max = rr_max;
+    if (code != kDoneRunning) st->done = code;
+    post_progress(mb, iter, code != kDoneRunning);
   }
 }
 
 template <typename R, typename T>
-hipError_t launch_cg_xpay(int n, const R2<R>* r, T* p, SolverState* st, hipStream_t s) {
-  const int nb = (n + 255) / 256;
-  hipLaunchKernelGGL((k_cg_xpay<R, T>), dim3(nb), dim3(256), 0, s, n, r, p, st);
+hipError_t launch_cg_step(int n, const R2<R>* r, T* p, SolverState* st, Reduce red, int nblk, hipStream_t s) {
+  if (nblk > red.capacity) return hipErrorInvalidValue;
+  // each block also sums the nblk partials: cap the grid so that this stays
+  // small next to the vector work
+  const int nb = std::min((n + 255) / 256, 2048);
+  hipLaunchKernelGGL((k_cg_step<R, T>), dim3(nb), dim3(256), 0, s, n, nblk, red.partials, r, p, st, red.mbox);
   return hipGetLastError();
 }
-template hipError_t launch_cg_xpay<double, double2>(int, const double2*, double2*, SolverState*, hipStream_t);
-template hipError_t launch_cg_xpay<float, float2>(int, const float2*, float2*, SolverState*, hipStream_t);
-template hipError_t launch_cg_xpay<float, Bf16c>(int, const float2*, Bf16c*, SolverState*, hipStream_t);
+template hipError_t launch_cg_step<double, double2>(int, const double2*, double2*, SolverState*, Reduce, int,
+                                                    hipStream_t);
+template hipError_t launch_cg_step<float, float2>(int, const float2*, float2*, SolverState*, Reduce, int,
+                                                  hipStream_t);
+template hipError_t launch_cg_step<float, Bf16c>(int, const float2*, Bf16c*, SolverState*, Reduce, int,
+                                                 hipStream_t);
 
 __global__ __launch_bounds__(256) void k_norm_dot(int n, const double2* __restrict__ a,
                                                   const double2* __restrict__ b, double* partials) {

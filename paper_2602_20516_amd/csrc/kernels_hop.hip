@@ -57,6 +57,8 @@ struct EpiAxpy {  // out = self + coef * acc
     if (threadIdx.x == 0) {
       const double pap = tot[0];
       guard->pap = pap;
+      guard->rr_prev = guard->rr;
+      guard->iter_prev = guard->iter;
       if (!(pap > 0.0) || !isfinite(pap)) {
         guard->alpha = 0.0;
         guard->done = kDoneBreakdown;
@@ -233,11 +235,9 @@ hipError_t launch_hop_schur_norm(const Geom& g, HopIn<R, T> hin, T* w, const T* 
 
 template <typename R, typename T, bool DAG>
 hipError_t launch_hop_schur_cg(const Geom& g, HopIn<R, T> hin, const T* w, R2<R>* x, R2<R>* r, const T* p,
-                               double coef, SolverState* st, Reduce red, hipStream_t s, bool with_finalize) {
+                               double coef, SolverState* st, Reduce red, hipStream_t s) {
   EpiSchurCG<R, T> e{w, x, r, p, R(coef), g.vh, st};
-  hipError_t err = launch<R, DAG>(g, 1, hin, e, red.partials, s, red.capacity);
-  if (err != hipSuccess || !with_finalize) return err;
-  return launch_finalize(kFinCgStep, nblk_parity(g), red, st, 0, 0.0, 0, s);
+  return launch<R, DAG>(g, 1, hin, e, red.partials, s, red.capacity);
 }
 
 template <bool DAG>
@@ -266,7 +266,7 @@ hipError_t launch_hop_residual(const Geom& g, HopIn<double> hin, const double2* 
   template hipError_t launch_hop_schur_norm<R, T, DAG>(const Geom&, HopIn<R, T>, T*, const T*, double,       \
                                                         SolverState*, Reduce, hipStream_t);                 \
   template hipError_t launch_hop_schur_cg<R, T, DAG>(const Geom&, HopIn<R, T>, const T*, R2<R>*, R2<R>*,     \
-                                                      const T*, double, SolverState*, Reduce, hipStream_t, bool);
+                                                      const T*, double, SolverState*, Reduce, hipStream_t);
 
 LGT_INST_AXPY(double, false, double2)
 LGT_INST_AXPY(double, true, double2)

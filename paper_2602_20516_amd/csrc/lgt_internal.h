@@ -23,16 +23,17 @@ struct SolverState {
   double rr0;       // |b|^2
   double rr_max;    // mixed precision: largest |r|^2 since the last FP64 update
   double delta2;    // mixed precision: stop for an FP64 update once rr <= delta2 * rr_max (0: never)
-  int iter;
+  double rr_prev;   // rr and iter as the third hop of the running iteration found them (the
+  int iter;         // step kernel's blocks read these copies while its block 0 rewrites rr, iter)
   int max_iter;
   int done;         // a kDone* code
-  int pad1;
+  int iter_prev;
 };
 
 // kDoneUpdate: the recursion stopped for an FP64 (reliable) update in this
-// iteration, whose final direction update p = r + beta p still runs, so the
-// search direction stays consistent with the residual; the next finalize
-// turns it into kDoneUpdateHeld, which no kernel touches.
+// iteration; its direction update is skipped (the reliable update forms the
+// next direction from the true residual).  The next step kernel turns it
+// into kDoneUpdateHeld, which no kernel touches.
 enum { kDoneRunning = 0, kDoneConverged = 1, kDoneMaxIter = 2, kDoneBreakdown = 3, kDoneUpdate = 4,
        kDoneUpdateHeld = 5 };
 
@@ -113,23 +114,25 @@ hipError_t launch_hop_axpy(const Geom& g, int p_out, HopIn<R, T> hin, T* out_eve
                            double coef, hipStream_t s, SolverState* guard = nullptr,
                            const double* pap_partials = nullptr);
 // One CG iteration on Mhat^dag Mhat (Mhat = 1 - kappa^2 H_oe H_eo, odd sites)
-// is four hop launches, the finalize and the direction update:
+// is four hop launches and the step kernel:
 //  (1) t = H p                                      launch_hop_axpy (guard)
 //  (2) w = p + coef H t, |w|^2 partials             launch_hop_schur_norm
 //  (3) t = H^dag w; block 0: alpha = rr / |w|^2    launch_hop_axpy with pap_partials
-//  (4) q = w + coef H^dag t; x += alpha p; r -= alpha q; |r|^2; finalize (rr,
-//      beta, stop)                                  launch_hop_schur_cg
-//  (5) p = r + beta p                               launch_cg_xpay
+//  (4) q = w + coef H^dag t; x += alpha p; r -= alpha q; |r|^2 partials
+//                                                   launch_hop_schur_cg
+//  (5) rr, beta and the stop decision (every block sums the partials),
+//      p = r + beta p unless stopping, block 0 records the state and posts
+//                                                   launch_cg_step
 // (for the dagger operator the roles of H and H^dag swap).  t, w, p are
 // stored as T; x and r as R2<R>.
 template <typename R, typename T, bool DAG>
 hipError_t launch_hop_schur_norm(const Geom& g, HopIn<R, T> hin, T* w, const T* x, double coef, SolverState* st,
                                  Reduce red, hipStream_t s);
-// (x may be null: the multi-shift solver tracks no base solution; without
-// with_finalize the caller launches its own finalize)
+// (x may be null: the multi-shift solver tracks no base solution).  The
+// |r|^2 partials are left for the caller's step or finalize kernel.
 template <typename R, typename T, bool DAG>
 hipError_t launch_hop_schur_cg(const Geom& g, HopIn<R, T> hin, const T* w, R2<R>* x, R2<R>* r, const T* p,
-                               double coef, SolverState* st, Reduce red, hipStream_t s, bool with_finalize = true);
+                               double coef, SolverState* st, Reduce red, hipStream_t s);
 // Residual of the full operator: r = phi - (self + coef * H in) over both parities,
 // result[slot] = |r|^2
 template <bool DAG>
@@ -138,11 +141,14 @@ hipError_t launch_hop_residual(const Geom& g, HopIn<double> hin, const double2* 
                                int slot, hipStream_t s);
 
 // Vector kernels (kernels_field.hip).  n = number of complex elements.
-// p = r + beta p (p stored as T) while the solve runs; the iteration whose
-// finalize stopped the recursion leaves p alone (the reliable update forms
-// the next direction, see launch_rescale_residual)
+// End of a CG iteration: rr = sum of the nblk |r|^2 partials of (4), beta =
+// rr / rr_prev, the stop test (target, reliable-update threshold, iteration
+// cap, non-finite), p = r + beta p (p stored as T) unless the recursion
+// stops here (the reliable update then forms the next direction, see
+// launch_rescale_residual); the new state and the mailbox post come from
+// block 0.  A skipped iteration only posts (and holds an update).
 template <typename R, typename T>
-hipError_t launch_cg_xpay(int n, const R2<R>* r, T* p, SolverState* st, hipStream_t s);
+hipError_t launch_cg_step(int n, const R2<R>* r, T* p, SolverState* st, Reduce red, int nblk, hipStream_t s);
 template <typename R>
 hipError_t launch_cg_init(int n, const R2<R>* b, R2<R>* r, R2<R>* p, R2<R>* x, SolverState* st,
                           Reduce red, double tol, int max_iter, hipStream_t s);

@@ -242,7 +242,7 @@ SolveStats lgt_ctx::solve_multishift(const double2* phi, int ns, const double* s
                                             state, rd.partials)));
     // r -= alpha A p, |r|^2 partials; the base solution is not formed
     LGT_HIP((launch_hop_schur_cg<double, double2, true>(g, HopIn<double>{U64, t, t}, wv, nullptr, r, p, k2, state, rd,
-                                                         stream, false)));
+                                                         stream)));
     hipLaunchKernelGGL(k_msfinalize, dim3(1), dim3(256), 0, stream, hop_blocks(g, 1), rd.partials, state, w->ss,
                        rd.mbox);
     LGT_HIP(hipGetLastError());

@@ -96,8 +96,8 @@ void lgt_ctx::apply_mhat_dag_mhat64(bool dag, const double2* x, double2* out) {
   }
 }
 
-// One CG iteration on Mhat^dag Mhat: four hop launches, the finalize and
-// the direction update.  t, w, p stored as T; x, r as R2<R>.
+// One CG iteration on Mhat^dag Mhat: four hop launches and the step kernel
+// (scalars, stop test, direction update).  t, w, p stored as T; x, r as R2<R>.
 template <typename R, typename T, bool DAG>
 static void cg_iteration(const Geom& g, const R2<R>* gauge, double kappa, T* t, T* w, R2<R>* x, R2<R>* r, T* p,
                          SolverState* st, Reduce red, hipStream_t s, int n) {
@@ -108,7 +108,7 @@ static void cg_iteration(const Geom& g, const R2<R>* gauge, double kappa, T* t, 
   LGT_HIP((launch_hop_axpy<R, !DAG, T>(g, 0, HopIn<R, T>{gauge, w, w}, t, t, nullptr, nullptr, 1.0, s, st,
                                          red.partials)));
   LGT_HIP((launch_hop_schur_cg<R, T, !DAG>(g, HopIn<R, T>{gauge, t, t}, w, x, r, p, k2, st, red, s)));
-  LGT_HIP((launch_cg_xpay<R, T>(n, r, p, st, s)));
+  LGT_HIP((launch_cg_step<R, T>(n, r, p, st, red, hop_blocks(g, 1), s)));
 }
 
 // CG on Mhat^dag Mhat z = rhs (odd half fields), FP64.  Returns the state's done code.
