@@ -63,13 +63,21 @@ struct LinkIdx {
   int c[4];
 };
 
+// Thread -> link: a block owns 64 consecutive sites of one parity, wave w
+// the links of direction w there (the four links of a site share most of
+// their staple links), and blocks are numbered XCD-contiguously, so that
+// neighbouring site blocks -- whose staples read each other's links -- run
+// under the same L2.  (Against one direction per launch segment and
+// round-robin XCDs, this raised the L2 hit rate of the forward kernel from
+// 11 % to 46 % and cut its time 1.6x at 24^3x48; walking each XCD's slab
+// with t fastest gained nothing more.)
 __device__ __forceinline__ bool link_of_thread(const Geom& g, LinkIdx& li) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= 8 * g.vh) return false;
-  const int pm = t / g.vh;
-  li.cb = t - pm * g.vh;
-  li.p = pm >> 2;
-  li.mu = pm & 3;
+  const int nbp = (g.vh + 63) / 64;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  li.p = lb / nbp;
+  li.cb = (lb - li.p * nbp) * 64 + (threadIdx.x & 63);
+  li.mu = threadIdx.x >> 6;
+  if (li.p > 1 || li.cb >= g.vh) return false;
   cb_coords(g, li.p, li.cb, li.c);
   return true;
 }
@@ -179,7 +187,7 @@ __global__ __launch_bounds__(256) void k_grad_to_force(Geom g, const double2* __
   }
 }
 
-static inline int nb_links(const Geom& g) { return (8 * g.vh + 255) / 256; }
+static inline int nb_links(const Geom& g) { return 2 * ((g.vh + 63) / 64); }
 
 hipError_t launch_stout_fwd(const Geom& g, const double2* U, double2* Uo, double rho, hipStream_t s) {
   hipLaunchKernelGGL(k_stout_fwd, dim3(nb_links(g)), dim3(256), 0, s, g, U, Uo, rho);

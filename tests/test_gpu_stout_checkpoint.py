@@ -51,6 +51,19 @@ def test_backprop_every_schedule_same_bits(lgt, dims, nlev):
     assert rel_err(outs[-1], ref) < 1e-12
 
 
+def test_stout_at_full_block_size(lgt):
+    """8^4: 32 full 64-site blocks per parity (the small lattices fill one
+    block partially); forward and reverse against the oracle."""
+    dims = (8, 8, 8, 8)
+    u = li.random_links(dims, 0.5, 71)
+    gt = li.random_links(dims, 1.0, 72)
+    lat = lgt.Lattice(dims)
+    U = to_dev(u)
+    assert rel_err(to_host(lat.stout_smear(U, RHO, 2)), stout.stout(u, RHO, 2)) < 1e-13
+    got = to_host(lat.stout_backprop(U, to_dev(gt), RHO, 2))
+    assert rel_err(got, stout.stout_vjp(u, gt, RHO, 2)) < 1e-12
+
+
 def test_deep_smeared_force_vs_oracle(lgt):
     dims = (4, 4, 4, 4)
     nlev = 6
