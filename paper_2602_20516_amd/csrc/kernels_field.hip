@@ -190,7 +190,8 @@ __global__ __launch_bounds__(256) void k_cg_step(int n, int nblk, const double* 
   if (done0 != kDoneRunning) {  // the iteration was skipped (or block 0 below already stopped it)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       if (done0 == kDoneUpdate) st->done = kDoneUpdateHeld;
-      post_progress(mb, st->iter, 1);
+      // the same action as the stop itself, in case the host has not seen it
+      post_progress(mb, st->iter, action_word(st->epoch, done0 == kDoneUpdateHeld ? kDoneUpdate : done0));
     }
     return;
   }
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(256) void k_cg_step(int n, int nblk, const double* 
     st->iter = iter;
     st->rr_max = rr_max;
     if (code != kDoneRunning) st->done = code;
-    post_progress(mb, iter, code != kDoneRunning);
+    post_progress(mb, iter, code != kDoneRunning ? action_word(st->epoch, code) : 0u);
   }
 }
 
@@ -333,7 +334,9 @@ hipError_t launch_convert_64_32(int n, const double2* x, float2* y, hipStream_t 
 }
 
 // x (FP64) += scale * xs (FP32); xs = 0
-__global__ __launch_bounds__(256) void k_mixed_update(int n, float2* xs, double2* __restrict__ x, double scale) {
+__global__ __launch_bounds__(256) void k_mixed_fold(int n, float2* xs, double2* __restrict__ x,
+                                                    const SolverState* st) {
+  const double scale = 1.0 / st->sigma;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const float2 v = xs[i];
     double2 xv = x[i];
@@ -343,8 +346,45 @@ __global__ __launch_bounds__(256) void k_mixed_update(int n, float2* xs, double2
     xs[i] = make_float2(0.f, 0.f);
   }
 }
-hipError_t launch_mixed_update(int n, float2* xs, double2* x, double scale, hipStream_t s) {
-  hipLaunchKernelGGL(k_mixed_update, dim3((n + 255) / 256), dim3(256), 0, s, n, xs, x, scale);
+hipError_t launch_mixed_fold(int n, float2* xs, double2* x, const SolverState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_mixed_fold, dim3((n + 255) / 256), dim3(256), 0, s, n, xs, x, st);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_reliable_decide(int nblk, const double* __restrict__ partials,
+                                                         SolverState* st, Mailbox* mb) {
+  double tot[2];
+  sum_partials<256, 2>(partials, nblk, tot);
+  if (threadIdx.x != 0) return;
+  const double rr64 = tot[0];
+  const int entry = st->done;
+  st->nupd += 1;
+  st->epoch += 1;
+  int code = kDoneRunning;
+  if (!isfinite(rr64)) {
+    code = kDoneFailed;
+  } else if (rr64 <= st->rr_target) {
+    code = kDoneConverged;
+  } else {
+    const double sn = 1.0 / sqrt(rr64);
+    st->restart = entry == kDoneBreakdown;
+    st->bscale = st->beta * sn / st->sigma;
+    st->sigma = sn;
+    st->rr = 1.0;
+    st->rr0 = 1.0;
+    st->rr_max = 1.0;
+    st->rr_stop = st->rr_target * sn * sn;
+  }
+  st->done = code;
+  post_progress(mb, st->iter, code != kDoneRunning ? action_word(st->epoch, code) : 0u);
+}
+hipError_t launch_reliable_decide(int n, const double2* r64, Reduce red, SolverState* st, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  if (nb > red.capacity) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_norm_dot, dim3(nb), dim3(256), 0, s, n, r64, (const double2*)nullptr, red.partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reliable_decide, dim3(1), dim3(256), 0, s, nb, red.partials, st, red.mbox);
   return hipGetLastError();
 }
 
@@ -374,6 +414,36 @@ hipError_t launch_rescale_residual(int n, const double2* r64, double sigma, floa
                      bscale);
   return hipGetLastError();
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_rescale_residual_dev(int n, const double2* __restrict__ r64,
+                                                              float2* __restrict__ r, T* __restrict__ p,
+                                                              const SolverState* state) {
+  if (state->done != kDoneRunning) return;
+  const double sigma = state->sigma, bscale = state->bscale;
+  const int restart = state->restart;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const double2 v = r64[i];
+    const double rx = sigma * v.x, ry = sigma * v.y;
+    st<float>(r + i, C<float>{(float)rx, (float)ry});
+    if (restart) {
+      Store<float, T>::st(p + i, C<float>{(float)rx, (float)ry});
+    } else {
+      const C<float> q = Store<float, T>::ld(p + i);
+      Store<float, T>::st(p + i, C<float>{(float)(rx + bscale * (double)q.re), (float)(ry + bscale * (double)q.im)});
+    }
+  }
+}
+template <typename T>
+hipError_t launch_rescale_residual_dev(int n, const double2* r64, float2* r, T* p, const SolverState* st,
+                                       hipStream_t s) {
+  hipLaunchKernelGGL((k_rescale_residual_dev<T>), dim3((n + 255) / 256), dim3(256), 0, s, n, r64, r, p, st);
+  return hipGetLastError();
+}
+template hipError_t launch_rescale_residual_dev<float2>(int, const double2*, float2*, float2*, const SolverState*,
+                                                        hipStream_t);
+template hipError_t launch_rescale_residual_dev<Bf16c>(int, const double2*, float2*, Bf16c*, const SolverState*,
+                                                       hipStream_t);
+
 template hipError_t launch_rescale_residual<float2>(int, const double2*, double, float2*, float2*, int, double,
                                                     hipStream_t);
 template hipError_t launch_rescale_residual<Bf16c>(int, const double2*, double, float2*, Bf16c*, int, double,

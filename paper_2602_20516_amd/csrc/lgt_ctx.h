@@ -114,22 +114,29 @@ struct lgt_ctx {
   void sync();
   void read_results(int n);
 
-  // Enqueues step() -- one CG iteration, ending in a finalize that posts to
+  // Enqueues step() -- one CG iteration, ending in a kernel that posts to
   // the mailbox -- until the device posts that the host has to act, keeping
   // kQueueAhead iterations queued beyond the last one the device finished
   // (the surplus ones see the stopped state and return at once).  iter0 is
   // the device's iteration count before the first step; no unfinished CG
-  // step may be on the stream.  Returns after synchronising the stream.
+  // step may be on the stream.  Actions whose epoch (the high bits of the
+  // action, see action_word) is below min_epoch are stale -- posted by
+  // iterations queued behind a stop the caller has already acted on -- and
+  // ignored.  Returns the mailbox word (action in the high 32 bits; none if
+  // nothing was posted for 30 s), after synchronising the stream unless
+  // sync_end is false.
   static constexpr int kQueueAhead = 2;
   template <typename Step>
-  void drive(int iter0, Step&& step) {
+  unsigned long long drive(int iter0, Step&& step, unsigned min_epoch = 0, bool sync_end = true) {
     unsigned long long* w = &mbox_host->word;
     __atomic_store_n(w, (unsigned long long)(unsigned)iter0, __ATOMIC_RELEASE);
     int queued = iter0, seen_prev = iter0;
+    unsigned long long v = 0;
     auto t_prev = std::chrono::steady_clock::now();
     for (;;) {
-      const unsigned long long v = __atomic_load_n(w, __ATOMIC_ACQUIRE);
-      if (v >> 32) break;
+      v = __atomic_load_n(w, __ATOMIC_ACQUIRE);
+      const unsigned act = (unsigned)(v >> 32);
+      if (act && (act >> 8) >= min_epoch) break;
       const int seen = (int)(unsigned)v;
       if (queued - seen < kQueueAhead) {
         step();
@@ -141,11 +148,13 @@ struct lgt_ctx {
         seen_prev = seen;
         t_prev = now;
       } else if (now - t_prev > std::chrono::seconds(30)) {
-        break;  // nothing posted for long: let the caller read the state after the sync
+        v = (unsigned long long)(unsigned)seen;  // nothing posted for long: the caller reads the state
+        break;
       }
       __builtin_ia32_pause();
     }
-    sync();
+    if (sync_end) sync();
+    return v;
   }
 
   // stout smearing (smear.hip): U0, G packed FP64

@@ -24,10 +24,18 @@ struct SolverState {
   double rr_max;    // mixed precision: largest |r|^2 since the last FP64 update
   double delta2;    // mixed precision: stop for an FP64 update once rr <= delta2 * rr_max (0: never)
   double rr_prev;   // rr and iter as the third hop of the running iteration found them (the
-  int iter;         // step kernel's blocks read these copies while its block 0 rewrites rr, iter)
+                    // step kernel's blocks read these copies while its block 0 rewrites rr, iter)
+  double sigma;     // mixed precision: units of the FP32 recursion (1 / |FP64 residual| at the last update)
+  double rr_target; // mixed precision: FP64 |r|^2 at which the solve has converged
+  double bscale;    // mixed precision: factor of the old direction in the first new one
+  int iter;
   int max_iter;
   int done;         // a kDone* code
   int iter_prev;
+  int epoch;        // reliable updates done; tags the mailbox actions (see post_action)
+  int restart;      // mixed precision: the next direction restarts from the residual
+  int nupd;         // FP64 residual recomputations
+  int pad;
 };
 
 // kDoneUpdate: the recursion stopped for an FP64 (reliable) update in this
@@ -35,7 +43,8 @@ struct SolverState {
 // next direction from the true residual).  The next step kernel turns it
 // into kDoneUpdateHeld, which no kernel touches.
 enum { kDoneRunning = 0, kDoneConverged = 1, kDoneMaxIter = 2, kDoneBreakdown = 3, kDoneUpdate = 4,
-       kDoneUpdateHeld = 5 };
+       kDoneUpdateHeld = 5, kDoneFailed = 6 };
+// kDoneFailed: the FP64 residual of a reliable update is not finite.
 
 // Output layout of the gauge-type kernels (forces, link update).
 enum Layout { kCanonical = 0, kPacked = 1 };
@@ -64,6 +73,13 @@ __device__ __forceinline__ void post_progress(Mailbox* mb, int iter, int action)
   if (!mb) return;
   const unsigned long long v = ((unsigned long long)(unsigned)action << 32) | (unsigned)iter;
   __hip_atomic_store(&mb->word, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Action word of a CG stop: the stop code and the state's epoch, so that the
+// host can tell a stop it has already acted on (posted again by iterations
+// that were queued behind it) from a new one.
+__host__ __device__ inline unsigned action_word(int epoch, int code) {
+  return ((unsigned)epoch << 8) | (unsigned)code;
 }
 
 // Workspace scalars used by reductions.
@@ -162,7 +178,21 @@ hipError_t launch_zero64(int n, double2* y, hipStream_t s);
 hipError_t launch_zero32(int n, float2* y, hipStream_t s);
 hipError_t launch_convert_64_32(int n, const double2* x, float2* y, hipStream_t s);
 // mixed precision helpers
-hipError_t launch_mixed_update(int n, float2* xs, double2* x, double scale, hipStream_t s);  // x += scale xs; xs = 0
+// Device-side reliable update, enqueued without a host round trip:
+//   launch_mixed_fold:       x += xs / st->sigma; xs = 0
+//   launch_reliable_decide:  |r64|^2 (deterministic two-launch reduction),
+//     then: not finite -> kDoneFailed; <= rr_target -> kDoneConverged; else
+//     new units sigma = 1 / |r64|, restart flag (the recursion broke down),
+//     bscale = beta sigma_new / sigma_old, the recursion's state reset
+//     (rr = rr_max = 1, rr_stop = rr_target sigma^2), kDoneRunning; epoch
+//     and nupd counted; a stop is posted to the mailbox
+//   launch_rescale_residual_dev: as launch_rescale_residual with sigma,
+//     restart and bscale from the state, and only if it is running
+hipError_t launch_mixed_fold(int n, float2* xs, double2* x, const SolverState* st, hipStream_t s);
+hipError_t launch_reliable_decide(int n, const double2* r64, Reduce red, SolverState* st, hipStream_t s);
+template <typename T>
+hipError_t launch_rescale_residual_dev(int n, const double2* r64, float2* r, T* p, const SolverState* st,
+                                       hipStream_t s);
 // reliable update of the FP32 recursion: r = (float)(sigma r64); then the
 // next search direction p = r (restart) or p = r + bscale p (bscale = beta
 // of the stopping iteration times the change of units), p stored as T

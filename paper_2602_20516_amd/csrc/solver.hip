@@ -178,53 +178,61 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
   LGT_HIP(launch_zero32(n, xs, stream));
   LGT_HIP(launch_rescale_residual(n, rhs, sigma, rs, ps, 1, 0.0, stream));
   SolverState s{};
-  auto write_state = [&](int iter) {
-    s = SolverState{};
-    s.rr = 1.0;
-    s.rr0 = 1.0;
-    s.rr_max = 1.0;
-    s.rr_stop = rr_target * sigma * sigma;
-    s.delta2 = delta * delta;
-    s.iter = iter;
-    s.max_iter = max_iter;
-    s.done = kDoneRunning;
-    *host_state = s;
-    LGT_HIP(hipMemcpyAsync(state, host_state, sizeof(SolverState), hipMemcpyHostToDevice, stream));
-  };
-  write_state(0);
+  s.rr = 1.0;
+  s.rr0 = 1.0;
+  s.rr_max = 1.0;
+  s.rr_stop = rr_target * sigma * sigma;
+  s.delta2 = delta * delta;
+  s.sigma = sigma;
+  s.rr_target = rr_target;
+  s.max_iter = max_iter;
+  s.done = kDoneRunning;
+  *host_state = s;
+  LGT_HIP(hipMemcpyAsync(state, host_state, sizeof(SolverState), hipMemcpyHostToDevice, stream));
+  // The recursion stops itself on the device for each reliable update; the
+  // host answers by enqueueing the update (fold, FP64 residual, decision,
+  // rescale) without waiting for the device, and the decision kernel either
+  // resumes the recursion or ends the solve.
+  unsigned min_epoch = 0;
+  int iter0 = 0;
   for (;;) {
-    drive(s.iter, [&] {
+    const unsigned long long v = drive(iter0, [&] {
       if (dag) cg_iteration<float, T, true>(g, U32, kappa, ts, ws, xs, rs, ps, state, red(), stream, n);
       else cg_iteration<float, T, false>(g, U32, kappa, ts, ws, xs, rs, ps, state, red(), stream, n);
-    });
+    }, min_epoch, false);
+    unsigned act = (unsigned)(v >> 32);
+    int dev_iter = (int)(unsigned)v;
+    if (!act || (act >> 8) < min_epoch) {  // nothing posted for long: read the state
+      LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
+      sync();
+      s = *host_state;
+      dev_iter = s.iter;
+      if (s.done == kDoneRunning) {
+        iter0 = s.iter;
+        continue;
+      }
+      act = action_word(s.epoch, s.done == kDoneUpdateHeld ? kDoneUpdate : s.done);
+    }
+    const int code = (int)(act & 0xffu);
+    if (code == kDoneUpdate || code == kDoneUpdateHeld || code == kDoneBreakdown) {
+      LGT_HIP(launch_mixed_fold(n, xs, z, state, stream));
+      apply_mhat_dag_mhat64(dag, z, r64);          // r64 = A z
+      LGT_HIP(launch_xmy64(n, rhs, r64, stream));  // r64 = rhs - A z
+      LGT_HIP(launch_reliable_decide(n, r64, red(), state, stream));
+      LGT_HIP(launch_rescale_residual_dev<T>(n, r64, rs, ps, state, stream));
+      min_epoch = (act >> 8) + 1;
+      iter0 = dev_iter;
+      continue;
+    }
+    if (code == kDoneMaxIter) LGT_HIP(launch_mixed_fold(n, xs, z, state, stream));
     LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
     sync();
     s = *host_state;
-    if (s.done == kDoneRunning) continue;  // nothing posted for long (see drive)
-    if (s.done == kDoneMaxIter) {
-      LGT_HIP(launch_mixed_update(n, xs, z, 1.0 / sigma, stream));
-      stt.iters += s.iter;
-      return kDoneMaxIter;
-    }
-    // the recursion stopped for an update (or broke down): fold, recompute
-    // the FP64 residual, rescale
-    const int restart = s.done == kDoneBreakdown ? 1 : 0;
-    LGT_HIP(launch_mixed_update(n, xs, z, 1.0 / sigma, stream));
-    apply_mhat_dag_mhat64(dag, z, r64);          // r64 = A z
-    LGT_HIP(launch_xmy64(n, rhs, r64, stream));  // r64 = rhs - A z
-    LGT_HIP(launch_norm_dot(n, r64, nullptr, red(), 0, stream));
-    read_results(2);
-    const double rr64 = host_result[0];
-    stt.reliable += 1;
-    if (!std::isfinite(rr64)) return kDoneBreakdown;
-    if (rr64 <= rr_target) {
-      stt.iters += s.iter;
-      return kDoneConverged;
-    }
-    const double sigma_new = 1.0 / std::sqrt(rr64);
-    LGT_HIP(launch_rescale_residual(n, r64, sigma_new, rs, ps, restart, s.beta * sigma_new / sigma, stream));
-    sigma = sigma_new;
-    write_state(s.iter);
+    stt.iters += s.iter;
+    stt.reliable += s.nupd;
+    if (code == kDoneConverged) return kDoneConverged;
+    if (code == kDoneMaxIter) return kDoneMaxIter;
+    return kDoneBreakdown;
   }
 }
 
