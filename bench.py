@@ -201,6 +201,13 @@ def main():
                         "iters": st_eo["iters"], "true_rel_residual": st_eo["true_rel_residual"]}
     log(f"bench: even/odd-preconditioned action {eo_rec}")
 
+    # the forces of both paths against the oracle's values stored for this
+    # workload (oracle CG to 1e-13; sampled links and the full-field norm)
+    force_vs_oracle = _force_vs_oracle(lat, U, phi, kappa, {"mixed": p_mixed, "fp64": p_fp64})
+    log(f"bench: force vs oracle {force_vs_oracle}")
+    copy_gbs = _copy_ceiling()
+    log(f"bench: device copy ceiling {copy_gbs:.0f} GB/s")
+
     # dominant kernel: the even/odd hop (FP32 in the timed mixed path), HIP
     # events on the library stream; FP64 beside it
     hop_ms32 = lat.hop_benchmark(U, E, "mixed_fp32", 200)
@@ -252,9 +259,11 @@ def main():
         "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3),
         "eo_preconditioned_action": dict(eo_rec, note="S_eo = phi_o^dag (Mhat^dag Mhat)^-1 phi_o, same determinant "
                                                       "weight, one Schur solve per force; not the metric"),
+        "force_vs_oracle": force_vs_oracle,
         "roofline": {"kernel": "even/odd hop H_eo, FP32 (k_hop<float,false,EpiAxpy<float>>)", "bound": "hbm",
                      "achieved": round(gbs32, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs32 / HBM_PEAK_GBS, 4),
+                     "measured_copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(gbs32 / copy_gbs, 4),
                      "traffic": traffic("hop_fp32_16x16x16x16_traffic.json"),
                      "avg_launch_us": round(hop_ms32 * 1e3, 3), "algorithmic_bytes_per_launch": hop_bytes32,
                      "fp64": {"achieved": round(gbs64, 1), "frac": round(gbs64 / HBM_PEAK_GBS, 4),
@@ -266,6 +275,49 @@ def main():
         log("bench: cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(u, eta, kappa, tol, args.cpu_budget)
     print(json.dumps(rec), flush=True)
+
+
+def _force_vs_oracle(lat, U, phi, kappa, params):
+    """Relative error of the fermion force against the stored oracle values of
+    the 16^4 workload (tests/golden, written from the oracle alone): over the
+    sampled links, and of the full-field Frobenius norm."""
+    import numpy as np
+
+    path = os.path.join(ROOT, "tests", "golden", "c2_16x16x16x16.json")
+    try:
+        with open(path) as f:
+            gold = json.load(f)
+    except OSError:
+        return None
+    links = [tuple(l) for l in gold["links"]]
+    ref = np.array([[complex(*v) for v in m] for m in gold["F_fermion"]]).reshape(-1, 3, 3)
+    out = {"oracle_tol": gold["oracle_tol"], "sampled_links": len(links)}
+    for name, prm in params.items():
+        F = lat.fermion_force(U, phi, kappa, prm)[0].cpu().numpy()
+        got = np.stack([F[l] for l in links])
+        out[name] = {"sampled_rel_err": float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel())),
+                     "norm_rel_diff": float(abs(np.linalg.norm(F.ravel()) - gold["F_fermion_fro"])
+                                            / gold["F_fermion_fro"])}
+    return out
+
+
+def _copy_ceiling():
+    """Device-to-device copy of 1 GiB (read + write counted), best of 10: the
+    bandwidth ceiling a streaming kernel can reach on this GPU."""
+    import torch
+
+    a = torch.ones(128 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = 1e30
+    for _ in range(12):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return 2 * 1024 ** 3 / (best * 1e-3) / 1e9
 
 
 def _traffic(name):
@@ -329,6 +381,7 @@ def bench_c3(args):
     hop_bytes = 96 * 4 * V
     gbs = hop_bytes / (hop_ms * 1e-3) / 1e9
     t_mixed = res["mixed_fp32"]["ms_per_call"]
+    copy_gbs = _copy_ceiling()
     return {
         "metric": "fermion force (CG+adjoint) ms/call at 24^3x48, mixed vs FP64", "value": t_mixed,
         "unit": "ms/call", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 2), "ms_per_step": t_mixed,
@@ -341,6 +394,7 @@ def bench_c3(args):
         "speedup_mixed_vs_fp64": round(res["fp64"]["ms_per_call"] / t_mixed, 3),
         "roofline": {"kernel": "even/odd hop H_eo, FP32", "bound": "hbm", "achieved": round(gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "measured_copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(gbs / copy_gbs, 4),
                      "traffic": _traffic("hop_fp32_24x24x24x48_traffic.json"),
                      "avg_launch_us": round(hop_ms * 1e3, 3), "algorithmic_bytes_per_launch": hop_bytes},
     }
