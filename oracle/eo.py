@@ -74,8 +74,9 @@ def eo_action(u, phi_o, kappa, bc=-1, tol=1e-14):
     return float(np.vdot(phi_o.ravel(), x.ravel()).real)
 
 
-def eo_grad(u, phi_o, kappa, bc=-1, tol=1e-14):
-    """G = dS_eo/dRe U + i dS_eo/dIm U.
+def eo_grad(u, phi_o, kappa, bc=-1, tol=1e-14, shift=0.0):
+    """G = dS_eo/dRe U + i dS_eo/dIm U (with shift: of phi_o^dag (Dhat^dag Dhat + shift)^-1 phi_o,
+    whose variation is -X^dag d(Dhat^dag Dhat) X as well: the shift is constant).
 
     dS_eo = -2 Re[Y^dag dDhat X] with X = (Dhat^dag Dhat)^-1 phi_o, Y = Dhat X,
     and dDhat = -kappa^2 (dH_oe H_eo + H_oe dH_eo), so
@@ -85,7 +86,7 @@ def eo_grad(u, phi_o, kappa, bc=-1, tol=1e-14):
     I = Re a^dag D b = Re a^dag (1 - kappa H) b, dI = -kappa Re a^dag dH b, so
     dS_eo = -2 kappa dI: the bilinear gradient with coefficient -2 kappa.
     """
-    x = solve_normal(u, phi_o, kappa, bc, tol)
+    x = solve_normal(u, phi_o, kappa, bc, tol, shift=shift)
     y = schur(u, x, kappa, bc)
     a = hop_to(u, y, 0, bc, dagger=True) + y
     b = hop_to(u, x, 0, bc) + x
@@ -94,3 +95,30 @@ def eo_grad(u, phi_o, kappa, bc=-1, tol=1e-14):
 
 def eo_force(u, phi_o, kappa, bc=-1, tol=1e-14):
     return force_from_grad(u, eo_grad(u, phi_o, kappa, bc, tol))
+
+
+# ---- rational (RHMC) pseudofermion action ------------------------------------
+# A rational approximation in partial fractions, R(A) = a0 + sum_i a_i (A + sigma_i)^-1
+# with A = Dhat^dag Dhat (RHMC is among the algorithms Sec. I names), gives the action
+# S_R = phi_o^dag R(A) phi_o.  Its gradient is the residue-weighted sum of the shifted
+# even/odd gradients; a0 contributes no force.
+
+def rational_action(u, phi_o, kappa, a0, shifts, residues, bc=-1, tol=1e-14):
+    """S_R = a0 |phi_o|^2 + sum_i a_i phi_o^dag (Dhat^dag Dhat + sigma_i)^-1 phi_o."""
+    f = phi_o.ravel()
+    s = a0 * float(np.vdot(f, f).real)
+    for sig, a in zip(shifts, residues):
+        x = solve_normal(u, phi_o, kappa, bc, tol, shift=sig)
+        s += a * float(np.vdot(f, x.ravel()).real)
+    return s
+
+
+def rational_grad(u, phi_o, kappa, a0, shifts, residues, bc=-1, tol=1e-14):
+    g = np.zeros(u.shape, dtype=complex)
+    for sig, a in zip(shifts, residues):
+        g = g + a * eo_grad(u, phi_o, kappa, bc, tol, shift=sig)
+    return g
+
+
+def rational_force(u, phi_o, kappa, a0, shifts, residues, bc=-1, tol=1e-14):
+    return force_from_grad(u, rational_grad(u, phi_o, kappa, a0, shifts, residues, bc, tol))

@@ -140,3 +140,55 @@ def test_shifted_solve_large_shift_limit(f):
     a_eta = eo.schur_dag(u, eo.schur(u, eta_o, k), k)
     approx = eta_o / s - a_eta / s**2
     assert np.abs(x - approx).max() < 1e-11 * np.abs(eta_o / s).max()
+
+
+# ---- rational (RHMC) action ---------------------------------------------------
+
+RAT = dict(a0=0.3, shifts=(0.0, 0.05, 0.6, 4.0), residues=(0.7, -0.2, 1.3, 2.1))
+
+
+def _dense_schur(u, k):
+    d = dirac.dense_dirac(u, k)
+    odd = _odd_indices()
+    even = np.setdiff1d(np.arange(d.shape[0]), odd)
+    return d[np.ix_(odd, odd)] - d[np.ix_(odd, even)] @ np.linalg.solve(d[np.ix_(even, even)], d[np.ix_(even, odd)])
+
+
+def test_rational_action_against_dense(f):
+    """S_R = phi^dag [a0 + sum_i a_i (A + sigma_i)^-1] phi with A built from the
+    Schur complement of the loop-built dense D (no oracle operator involved)."""
+    u, eta_o, _ = f
+    k = 0.125
+    phi_o = eo.schur_dag(u, eta_o, k)
+    m = _dense_schur(u, k)
+    a = m.conj().T @ m
+    b = phi_o.ravel()[_odd_indices()]
+    ref = RAT["a0"] * np.vdot(b, b).real
+    for sig, r in zip(RAT["shifts"], RAT["residues"]):
+        ref += r * np.vdot(b, np.linalg.solve(a + sig * np.eye(a.shape[0]), b)).real
+    got = eo.rational_action(u, phi_o, k, RAT["a0"], RAT["shifts"], RAT["residues"])
+    assert abs(got - ref) < 1e-11 * abs(ref)
+
+
+def test_rational_force_lie_derivative(f):
+    u, eta_o, _ = f
+    k = 0.125
+    phi_o = eo.schur_dag(u, eta_o, k)
+    fo = eo.rational_force(u, phi_o, k, RAT["a0"], RAT["shifts"], RAT["residues"])
+    d = force.lie_derivatives(fo)
+    act = lambda v: eo.rational_action(v, phi_o, k, RAT["a0"], RAT["shifts"], RAT["residues"])  # noqa: E731
+    for site, mu, a in [((0, 1, 0, 1), 1, 0), ((3, 0, 1, 1), 3, 5), ((1, 1, 1, 0), 0, 7), ((2, 1, 0, 0), 2, 2)]:
+        fd = force.lie_fd(act, u, site, mu, a)
+        assert abs(d[site + (mu, a)] - fd) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_rational_force_of_a_large_shift_vanishes_as_its_square(f):
+    """a (A + s)^-1 = a/s - a A/s^2 + ...: the force of one term falls off as
+    1/s^2 (doubling s quarters it)."""
+    u, eta_o, _ = f
+    k = 0.125
+    phi_o = eo.schur_dag(u, eta_o, k)
+    f1 = eo.rational_force(u, phi_o, k, 0.0, (1e4,), (1.0,))
+    f2 = eo.rational_force(u, phi_o, k, 0.0, (2e4,), (1.0,))
+    ratio = np.linalg.norm(f1.ravel()) / np.linalg.norm(f2.ravel())
+    assert abs(ratio - 4.0) < 2e-3
