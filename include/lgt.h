@@ -371,6 +371,28 @@ LGT_API lgt_status lgt_cg_solve_multishift(lgt_ctx* ctx, const void* U, const vo
                                            int32_t nshift, const double* shifts, void* const* X,
                                            const lgt_solver_params* params, lgt_solver_stats* stats);
 
+/* Rational (RHMC) pseudofermion action on the even/odd operator and its
+ * force.  A rational approximation in partial fractions,
+ *   R(A) = a0 + sum_{i<nterms} residues[i] (A + shifts[i])^-1,
+ * A = Mhat^dag Mhat (the normal Schur operator of lgt_schur_dslash; RHMC
+ * is among the algorithms the method targets, Sec. I), defines
+ *   S_R = phi_o^dag R(A) phi_o  (odd sites of phi read).
+ * One lgt_cg_solve_multishift solve gives X_i = (A + shifts[i])^-1 phi_o;
+ * each term varies as -residues[i] X_i^dag dA X_i (the shift is
+ * constant), so the force is the sum over terms of the even/odd bilinear
+ * force of lgt_fermion_force_eo taken at X_i, weighted by residues[i]; a0
+ * adds no force.  mode/dt/out as lgt_fermion_force (out: canonical
+ * gauge-type field on U); S_or_null receives S_R, evaluated as
+ * a0|phi_o|^2 + sum_i residues[i] (2 Re phi_o^dag X_i - |Mhat X_i|^2 -
+ * shifts[i] |X_i|^2), which equals S_R at the solutions and is second order
+ * in their error.  nterms 1..32, shifts finite and >= 0, residues and a0
+ * finite (else INVALID_ARGUMENT); FP64 only (UNSUPPORTED otherwise);
+ * NOT_CONVERGED as lgt_cg_solve_multishift. */
+LGT_API lgt_status lgt_rational_force_eo(lgt_ctx* ctx, const void* U, const void* phi, double kappa, int32_t nterms,
+                                         const double* shifts, const double* residues, double a0,
+                                         const lgt_solver_params* params, int32_t mode, double dt, void* out,
+                                         double* S_or_null, lgt_solver_stats* stats);
+
 /* Measurement entry point: times nrep back-to-back launches of the
  * even/odd hop kernel H_eo (the dominant kernel of the CG; FP64 for
  * precision = LGT_FP64, FP32 otherwise) on links U and input spinor psi,

@@ -15,7 +15,7 @@ from .api import (Lattice, LGTError, LGTNonFinite, LGTNotConverged, Params,  # n
                   lgt_link_update,
                   lgt_md_step, lgt_md_step_eo, lgt_md_step_smeared, lgt_md_step_sw, lgt_schur_dslash,
                   lgt_fermion_force_eo, lgt_smeared_force, lgt_stout_backprop, lgt_stout_smear,
-                  lgt_cg_solve_multishift, stout_schedule)
+                  lgt_cg_solve_multishift, lgt_rational_force_eo, stout_schedule)
 from .autograd import LatticeAction, lattice_action  # noqa: E402
 
 __all__ = [
@@ -23,6 +23,6 @@ __all__ = [
     "lgt_create", "lgt_dslash", "lgt_cg_solve", "lgt_action", "lgt_fermion_force",
     "lgt_bilinear_force", "lgt_gauge_force", "lgt_link_update", "lgt_kinetic", "lgt_md_step",
     "lgt_hop_benchmark", "lgt_hop_benchmark_mrhs", "lgt_stout_smear", "lgt_stout_backprop", "lgt_smeared_force", "lgt_md_step_smeared", "lgt_md_step_sw",
-    "lgt_schur_dslash", "lgt_fermion_force_eo", "lgt_md_step_eo", "lgt_cg_solve_multishift", "stout_schedule",
+    "lgt_schur_dslash", "lgt_fermion_force_eo", "lgt_md_step_eo", "lgt_cg_solve_multishift", "lgt_rational_force_eo", "stout_schedule",
     "LatticeAction", "lattice_action",
 ]

@@ -376,6 +376,27 @@ class Lattice:
         _check(self.lib, self.ctx, st, stats)
         return Xs, stats.as_dict()
 
+    def rational_force_eo(self, U, phi, kappa: float, shifts, residues, a0: float = 0.0,
+                          params: Optional[Params] = None, mode: str = "force", dt: float = 0.0, out=None):
+        """lgt_rational_force_eo: force of phi_o^dag [a0 + sum_i r_i (A + s_i)^-1] phi_o; returns (out, S_R, stats)."""
+        params = params or Params()
+        n = len(shifts)
+        if len(residues) != n:
+            raise ValueError("one residue per shift")
+        out = self.empty_gauge() if out is None else out
+        sh = (ctypes.c_double * max(n, 1))(*[float(v) for v in shifts])
+        rs = (ctypes.c_double * max(n, 1))(*[float(v) for v in residues])
+        sr = ctypes.c_double()
+        stats = SolverStats()
+        cp = params.to_c()
+        self._bind_stream()
+        st = self.lib.lgt_rational_force_eo(self.ctx, self._field(U, "gauge", "U"), self._field(phi, "spinor", "phi"),
+                                            float(kappa), n, sh, rs, float(a0), ctypes.byref(cp), _MODES[mode],
+                                            float(dt), self._field(out, "gauge", "out"), ctypes.byref(sr),
+                                            ctypes.byref(stats))
+        _check(self.lib, self.ctx, st, stats)
+        return out, sr.value, stats.as_dict()
+
     def set_stout_checkpoints(self, max_stored_levels: int = -1):
         """lgt_set_stout_checkpoints: cap on the smearing levels kept for the reverse pass (-1: automatic)."""
         _check(self.lib, self.ctx, self.lib.lgt_set_stout_checkpoints(self.ctx, int(max_stored_levels)))
@@ -507,3 +528,8 @@ def lgt_md_step_sw(lat: Lattice, U, P, phi, beta, kappa, rho, nlevels, dt, nstep
 
 def lgt_cg_solve_multishift(lat: Lattice, U, phi, kappa, shifts, params=None):
     return lat.cg_solve_multishift(U, phi, kappa, shifts, params)
+
+
+def lgt_rational_force_eo(lat: Lattice, U, phi, kappa, shifts, residues, a0=0.0, params=None, mode="force", dt=0.0,
+                          out=None):
+    return lat.rational_force_eo(U, phi, kappa, shifts, residues, a0, params, mode, dt, out)

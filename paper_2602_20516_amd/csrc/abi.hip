@@ -708,6 +708,39 @@ lgt_status lgt_cg_solve_multishift(lgt_ctx* c, const void* U, const void* phi, d
   return s;
 }
 
+lgt_status lgt_rational_force_eo(lgt_ctx* c, const void* U, const void* phi, double kappa, int32_t nterms,
+                                 const double* shifts, const double* residues, double a0,
+                                 const lgt_solver_params* params, int32_t mode, double dt, void* out,
+                                 double* S_or_null, lgt_solver_stats* stats) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  bool nc = false;
+  lgt_status s = guarded(c, [&] {
+    require(U && phi && shifts && residues && out, "null pointer");
+    require(nterms >= 1 && nterms <= lgt_ctx_max_shifts(), "nterms out of range (1 to 32)");
+    require(mode >= LGT_OUT_FORCE && mode <= LGT_OUT_MOMENTUM, "unknown output mode");
+    require(std::isfinite(kappa) && std::isfinite(a0) && std::isfinite(dt), "kappa, a0 and dt must be finite");
+    for (int i = 0; i < nterms; ++i) {
+      require(std::isfinite(shifts[i]) && shifts[i] >= 0.0, "shifts must be finite and non-negative");
+      require(std::isfinite(residues[i]), "residues must be finite");
+    }
+    const SolverOpts o = parse(params);
+    if (o.precision != LGT_FP64) throw Error(LGT_ERR_UNSUPPORTED, "the rational force runs in FP64 only");
+    Timer tm(c);
+    pack_links(c, U, false);
+    pack_spinor(c, phi, c->f64(kPhi));
+    check_nonfinite(c, "U or phi");
+    c->kappa = kappa;
+    const SolveStats st = c->rational_force(c->f64(kPhi), nterms, shifts, residues, a0, o, mode, dt, out, S_or_null);
+    fill_stats(stats, st, tm.stop());
+    nc = !st.converged;
+  });
+  if (s == LGT_OK && nc) {
+    c->err = "solver did not reach the tolerance for every shift";
+    return LGT_ERR_NOT_CONVERGED;
+  }
+  return s;
+}
+
 lgt_status lgt_hop_benchmark(lgt_ctx* c, const void* U, const void* psi, int32_t precision, int32_t nrep,
                              double* avg_ms) {
   if (!c) return LGT_ERR_INVALID_ARGUMENT;

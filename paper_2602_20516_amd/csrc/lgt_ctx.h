@@ -185,6 +185,9 @@ struct lgt_ctx {
   MultiShiftWork* mshift = nullptr;
   lgt::SolveStats solve_multishift(const double2* phi, int ns, const double* shifts, void* const* Xout,
                                    const lgt::SolverOpts& o);
+  // rational even/odd action and force (multishift.hip); out: canonical gauge field
+  lgt::SolveStats rational_force(const double2* phi, int ns, const double* shifts, const double* residues, double a0,
+                                 const lgt::SolverOpts& o, int mode, double dt, void* out, double* S);
 
   double kappa = 0.0;  // hopping parameter of the current solve
  private:

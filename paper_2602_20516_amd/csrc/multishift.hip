@@ -175,7 +175,8 @@ static MultiShiftWork* mshift_work(lgt_ctx* c, int ns) {
 int lgt_ctx_max_shifts() { return kMaxShift; }
 
 // phi: packed full field (odd half read).  Xout[i]: the caller's canonical
-// full fields, written with X_i on the odd sites and zero on the even ones.
+// full fields, written with X_i on the odd sites and zero on the even ones
+// (Xout null: the solutions stay in the workspace, mshift->X + i V/2 * 12).
 // The shifted recursions stop at half the tolerance; the returned true_res
 // is the largest FP64 true residual ||phi_o - (A + sigma_i) X_i|| / ||phi_o||
 // over the shifts, and converged is false if it exceeds the tolerance.
@@ -189,6 +190,7 @@ SolveStats lgt_ctx::solve_multishift(const double2* phi, int ns, const double* s
   double2* stage = f64(kStageB);  // packed full field holding one output at a time
   LGT_HIP(launch_zero64(n, stage, stream));
   auto emit = [&](int i, const double2* xo) {
+    if (!Xout) return;
     LGT_HIP(launch_copy64(n, xo, stage + h, stream));
     LGT_HIP(launch_unpack(g, 12, stage, (double2*)Xout[i], stream));
   };
@@ -198,7 +200,9 @@ SolveStats lgt_ctx::solve_multishift(const double2* phi, int ns, const double* s
   if (!std::isfinite(bb)) throw Error(LGT_ERR_NONFINITE, "phi holds NaN or Inf");
   if (bb == 0.0) {
     LGT_HIP(launch_zero64(n, stage + h, stream));
-    for (int i = 0; i < ns; ++i) LGT_HIP(launch_unpack(g, 12, stage, (double2*)Xout[i], stream));
+    LGT_HIP(launch_zero64((int)(ns * h), w->X, stream));
+    for (int i = 0; i < ns; ++i)
+      if (Xout) LGT_HIP(launch_unpack(g, 12, stage, (double2*)Xout[i], stream));
     st.true_res = 0.0;
     return st;
   }
@@ -278,5 +282,60 @@ SolveStats lgt_ctx::solve_multishift(const double2* phi, int ns, const double* s
   }
   st.true_res = worst;
   if (worst > o.tol) st.converged = false;
+  return st;
+}
+
+// Rational (RHMC) even/odd pseudofermion action S_R = phi_o^dag R(A) phi_o,
+// R(A) = a0 + sum_i a_i (A + sigma_i)^-1, A = Mhat^dag Mhat, and its force.
+// With X_i = (A + sigma_i)^-1 phi_o from one multi-shift solve, the term i
+// varies as -a_i X_i^dag dA X_i = -2 a_i Re[Y_i^dag dMhat X_i], Y_i = Mhat X_i
+// (the shift is constant): the even/odd bilinear of each X_i with the
+// coefficient -2 kappa a_i, summed into one gradient.  S_R is evaluated as
+// a0 |phi_o|^2 + sum_i a_i (2 Re phi_o^dag X_i - |Y_i|^2 - sigma_i |X_i|^2),
+// equal to the action at the solutions and second order in their error.
+SolveStats lgt_ctx::rational_force(const double2* phi, int ns, const double* shifts, const double* residues,
+                                   double a0, const SolverOpts& o, int mode, double dt, void* out, double* S) {
+  SolveStats st = solve_multishift(phi, ns, shifts, nullptr, o);
+  MultiShiftWork* w = mshift;
+  const size_t h = half_elems();
+  const int n = (int)h;
+  const int ng = 72 * vh;  // complex elements of a gauge-type field
+  const double2* phio = phi + h;
+  double2* xf = f64(kStageA);  // (H_eo X_o, X_o)
+  double2* af = f64(kE);       // (H_oe^dag Y_o, Y_o)
+  double2* gsum = g64(12);
+  double2* gtmp = g64(13);
+  LGT_HIP(launch_zero64(ng, gsum, stream));
+  const double k2 = -kappa * kappa;
+  double sr = 0.0;
+  if (S) {
+    LGT_HIP(launch_norm_dot(n, phio, nullptr, red(), 0, stream));
+    read_results(1);
+    sr = a0 * host_result[0];
+  }
+  for (int i = 0; i < ns; ++i) {
+    const double2* xo = w->X + (size_t)i * h;
+    LGT_HIP(launch_copy64(n, xo, xf + h, stream));
+    const HopIn<double> hx{U64, xf + h, xf + h};
+    LGT_HIP((launch_hop_axpy<double, false>(g, 0, hx, xf, xf, nullptr, nullptr, 1.0, stream)));  // X_e = H_eo X_o
+    const HopIn<double> he{U64, xf, xf};
+    LGT_HIP((launch_hop_axpy<double, false>(g, 1, he, af + h, af + h, xf + h, xf + h, k2, stream)));  // Y_o
+    const HopIn<double> hy{U64, af + h, af + h};
+    LGT_HIP((launch_hop_axpy<double, true>(g, 0, hy, af, af, nullptr, nullptr, 1.0, stream)));  // H_oe^dag Y_o
+    LGT_HIP(launch_bilinear_force(g, U64, af, xf, kappa, -2.0 * kappa * residues[i], LGT_OUT_GRAD, 0.0, gtmp,
+                                  kPacked, stream));
+    LGT_HIP(launch_axpy64(ng, 1.0, gtmp, gsum, stream));
+    if (S) {
+      LGT_HIP(launch_norm_dot(n, xf + h, phio, red(), 0, stream));  // |X_i|^2, Re <X_i, phi_o>
+      LGT_HIP(launch_norm_dot(n, af + h, nullptr, red(), 2, stream));  // |Y_i|^2
+      read_results(4);
+      sr += residues[i] * (2.0 * host_result[1] - host_result[2] - shifts[i] * host_result[0]);
+    }
+  }
+  if (S) *S = sr;
+  // the output: overwritten (force, gradient) or updated in place (momentum)
+  if (mode != LGT_OUT_MOMENTUM) LGT_HIP(launch_zero64(ng, (double2*)out, stream));
+  const int acc = mode == LGT_OUT_FORCE ? 0 : (mode == LGT_OUT_GRAD ? 1 : 2);
+  LGT_HIP(launch_grad_to_force(g, U64, gsum, acc, dt, out, kCanonical, stream));
   return st;
 }

@@ -171,3 +171,69 @@ def test_multishift_full_size(lgt):
         r = _true_residual(u, phi_o, to_host(Xs[i]), k, shifts[i])
         say("  shift", shifts[i], "cpu residual", r)
         assert r <= 1.05e-10
+
+
+# ---- rational (RHMC) force ------------------------------------------------------
+
+RAT = dict(a0=0.3, shifts=[0.0, 0.05, 0.6, 4.0], residues=[0.7, -0.2, 1.3, 2.1])
+
+
+@pytest.mark.parametrize("mode", ["force", "grad", "momentum"])
+def test_rational_force_vs_oracle(lgt, mode):
+    dims = (4, 4, 4, 4)
+    k = 0.12
+    u, phi_o = _setup(dims, k, 271)
+    lat = lgt.Lattice(dims)
+    U, P = to_dev(u), to_dev(phi_o)
+    prm = lgt.Params(tol=1e-13)
+    g_ref = eo.rational_grad(u, phi_o, k, RAT["a0"], RAT["shifts"], RAT["residues"])
+    from oracle import force as oforce
+    if mode == "grad":
+        got, s_r, st = lat.rational_force_eo(U, P, k, RAT["shifts"], RAT["residues"], RAT["a0"], prm, "grad")
+        ref = g_ref
+    elif mode == "force":
+        got, s_r, st = lat.rational_force_eo(U, P, k, RAT["shifts"], RAT["residues"], RAT["a0"], prm, "force")
+        ref = oforce.force_from_grad(u, g_ref)
+    else:
+        p = li.random_momenta(dims, 272)
+        dt = 0.05
+        got, s_r, st = lat.rational_force_eo(U, P, k, RAT["shifts"], RAT["residues"], RAT["a0"], prm, "momentum",
+                                             dt, out=to_dev(p))
+        ref = p - dt * oforce.force_from_grad(u, g_ref)
+    say("rational", mode, st, rel_err(to_host(got), ref))
+    assert st["true_rel_residual"] <= 1e-13
+    assert rel_err(to_host(got), ref) < 1e-11
+    s_ref = eo.rational_action(u, phi_o, k, RAT["a0"], RAT["shifts"], RAT["residues"])
+    assert abs(s_r - s_ref) < 1e-12 * abs(s_ref)
+
+
+def test_rational_force_single_term_is_the_eo_force(lgt):
+    """One term, sigma = 0, residue 1, a0 = 0: the even/odd action and force."""
+    dims = (4, 4, 4, 6)
+    k = 0.12
+    u, phi_o = _setup(dims, k, 281)
+    lat = lgt.Lattice(dims)
+    U, P = to_dev(u), to_dev(phi_o)
+    prm = lgt.Params(tol=1e-13)
+    f_rat, s_rat, _ = lat.rational_force_eo(U, P, k, [0.0], [1.0], 0.0, prm)
+    f_eo, s_eo, _ = lat.fermion_force_eo(U, P, k, prm)
+    assert rel_err(to_host(f_rat), to_host(f_eo)) < 1e-11
+    assert abs(s_rat - s_eo) < 1e-12 * abs(s_eo)
+
+
+def test_rational_force_errors(lgt):
+    dims = (4, 4, 4, 4)
+    k = 0.12
+    u, phi_o = _setup(dims, k, 291)
+    lat = lgt.Lattice(dims)
+    U, P = to_dev(u), to_dev(phi_o)
+    with pytest.raises(lgt.LGTError):
+        lat.rational_force_eo(U, P, k, [0.1, -1.0], [1.0, 1.0])
+    with pytest.raises(lgt.LGTError):
+        lat.rational_force_eo(U, P, k, [0.1], [float("inf")])
+    with pytest.raises(lgt.LGTError):
+        lat.rational_force_eo(U, P, k, [0.1] * 33, [1.0] * 33)
+    with pytest.raises(lgt.LGTError):
+        lat.rational_force_eo(U, P, k, [0.1], [1.0], 0.0, lgt.Params(precision="mixed_fp32"))
+    f, s, st = lat.rational_force_eo(U, P, k, [0.1], [1.0], 0.0, lgt.Params(tol=1e-12))
+    assert st["true_rel_residual"] <= 1e-12
