@@ -32,7 +32,7 @@ struct SolverState {
   int max_iter;
   int done;         // a kDone* code
   int iter_prev;
-  int epoch;        // reliable updates done; tags the mailbox actions (see post_action)
+  int epoch;        // reliable updates done; tags the mailbox actions (see action_word)
   int restart;      // mixed precision: the next direction restarts from the residual
   int nupd;         // FP64 residual recomputations
   int pad;
@@ -60,11 +60,12 @@ struct HopIn {
 };
 
 // Host-visible progress of an iterative solve, in pinned host memory: the
-// finalize kernel of every CG step posts the device's iteration count (low
-// 32 bits) and whether the host has to act (high 32 bits: the recursion
-// stopped, converged, or the batch wants an update), so the host can keep a
-// few iterations queued ahead of the GPU instead of synchronising.  One
-// 64-bit store, so the host never sees a torn pair.
+// last kernel of every CG step (step or finalize kernel) posts the device's
+// iteration count (low 32 bits) and whether the host has to act (high 32
+// bits, nonzero: the recursion stopped, converged, or the batch wants an
+// update; for the single-field CG the action word of action_word), so the
+// host can keep a few iterations queued ahead of the GPU instead of
+// synchronising.  One 64-bit store, so the host never sees a torn pair.
 struct Mailbox {
   unsigned long long word;
 };
@@ -96,7 +97,7 @@ enum FinalizeMode {
   kFinResult1 = 0,   // result[slot] = sum (1 value per block)
   kFinResult2 = 1,   // result[slot], result[slot+1] = sums (2 values per block)
   kFinCgInit = 2,    // start a CG: rr = |b|^2, rr_stop = tol^2 |b|^2, ...
-  kFinCgStep = 3,    // end of a CG iteration: rr, beta, iteration count, convergence
+  kFinCgStep = 3,    // end of a batched CG iteration (k_mfinalize): rr, beta, iteration count, convergence
 };
 hipError_t launch_finalize(int mode, int nblk, Reduce red, SolverState* st, int slot, double tol, int max_iter,
                            hipStream_t s);

@@ -10,16 +10,17 @@
 // then Y is recomputed as D X and the FP64 residual phi - D^dag D X checked;
 // FP64 defect-correction passes follow until it meets the tolerance.
 //
-// The CG iteration is five stream-ordered kernels whose scalars (alpha,
-// beta, |r|^2, the convergence flag) stay on the device; the host only
-// reads the state at chunk boundaries and predicts the next chunk length
-// from the observed convergence rate.  Once converged, the remaining
-// launches of a chunk return immediately.
+// The CG iteration is five stream-ordered kernels (four hops and the step
+// kernel) whose scalars (alpha, beta, |r|^2, the stop code) stay on the
+// device; the host keeps a few iterations queued ahead of the GPU and learns
+// of a stop from the mailbox the step kernel posts to (see drive).  Once
+// stopped, the iterations still queued return immediately.
 //
 // Mixed precision: the same CG in FP32 (FP32 links and vectors) with
 // reliable updates: whenever the FP32 residual has dropped by reliable_delta
-// since the last update (checked at chunk boundaries), the FP32 solution is
-// folded into the FP64 one and the residual recomputed in FP64.
+// since the last update (tested on the device every iteration), the FP32
+// solution is folded into the FP64 one and the residual recomputed in FP64,
+// by kernels the host enqueues without waiting (see cg_normal_mixed).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -144,8 +145,7 @@ int lgt_ctx::cg_normal64(bool dag, double2* z, const double2* rhs, double tol, i
 // residual is recomputed, and the search direction is rescaled to the new
 // units.  The recursion stops itself on the device, in the iteration where
 // |r|^2 first falls below delta^2 times its largest value since the last
-// update (or below the target), after that iteration's direction update,
-// and posts the stop to the host (see drive).  Letting it run on until the
+// update (or below the target), and posts the stop to the host (see drive).  Letting it run on until the
 // host looks would let a fast-converging recursion go orders of magnitude
 // past the accuracy FP32 can hold, after which the kept direction no longer
 // matches the true residual and CG diverges.  The stopping iteration skips
