@@ -184,6 +184,15 @@ def main():
     torch.cuda.synchronize()
     t_fp64 = (time.perf_counter() - t0) / args.steps
     log(f"bench: fp64 {t_fp64 * 1e3:.3f} ms/call {st_fp64}")
+    # beside them (not the metric): the inner recursion with BF16-stored vectors
+    p_bf16 = lgt.Params(precision="mixed_bf16", tol=tol)
+    run(p_bf16, max(1, args.warmup))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_bf16 = run(p_bf16, args.steps)
+    torch.cuda.synchronize()
+    t_bf16 = (time.perf_counter() - t0) / args.steps
+    log(f"bench: mixed bf16 {t_bf16 * 1e3:.3f} ms/call {st_bf16}")
 
     # beside it (not the metric): the even/odd-preconditioned action, whose
     # force needs one Schur solve instead of two (same determinant weight)
@@ -203,7 +212,7 @@ def main():
 
     # the forces of both paths against the oracle's values stored for this
     # workload (oracle CG to 1e-13; sampled links and the full-field norm)
-    force_vs_oracle = _force_vs_oracle(lat, U, phi, kappa, {"mixed": p_mixed, "fp64": p_fp64})
+    force_vs_oracle = _force_vs_oracle(lat, U, phi, kappa, {"mixed": p_mixed, "fp64": p_fp64, "mixed_bf16": p_bf16})
     log(f"bench: force vs oracle {force_vs_oracle}")
     copy_gbs = _copy_ceiling()
     log(f"bench: device copy ceiling {copy_gbs:.0f} GB/s")
@@ -257,6 +266,10 @@ def main():
                  "true_rel_residual": st_fp64["true_rel_residual"],
                  "effective_GBs": round(eff_gbs(st_fp64, 8, t_fp64), 1)},
         "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3),
+        "mixed_bf16": {"ms_per_call": round(t_bf16 * 1e3, 4), "iters": st_bf16["iters"],
+                       "reliable_updates": st_bf16["reliable_updates"],
+                       "true_rel_residual": st_bf16["true_rel_residual"],
+                       "note": "FP32 arithmetic with BF16-stored inner vectors; not the metric"},
         "eo_preconditioned_action": dict(eo_rec, note="S_eo = phi_o^dag (Mhat^dag Mhat)^-1 phi_o, same determinant "
                                                       "weight, one Schur solve per force; not the metric"),
         "force_vs_oracle": force_vs_oracle,
