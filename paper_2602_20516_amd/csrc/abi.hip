@@ -259,6 +259,7 @@ lgt_status lgt_action(lgt_ctx* c, const void* U, const void* phi, double beta, d
   bool nc = false;
   lgt_status s = guarded(c, [&] {
     require(U != nullptr, "null U");
+    require(std::isfinite(kappa), "kappa must be finite");
     require(!S_F || phi, "S_F requested without phi");
     const SolverOpts o = parse(params);
     Timer tm(c);
@@ -289,6 +290,7 @@ lgt_status lgt_fermion_force(lgt_ctx* c, const void* U, const void* phi, double 
   bool nc = false;
   lgt_status s = guarded(c, [&] {
     require(U && phi && out, "null field pointer");
+    require(std::isfinite(kappa), "kappa must be finite");
     require(mode >= LGT_OUT_FORCE && mode <= LGT_OUT_MOMENTUM, "unknown output mode");
     const SolverOpts o = parse(params);
     Timer tm(c);
@@ -314,6 +316,7 @@ lgt_status lgt_bilinear_force(lgt_ctx* c, const void* U, const void* a, const vo
   if (!c) return LGT_ERR_INVALID_ARGUMENT;
   return guarded(c, [&] {
     require(U && a && b && out, "null field pointer");
+    require(std::isfinite(kappa), "kappa must be finite");
     require(mode >= LGT_OUT_FORCE && mode <= LGT_OUT_MOMENTUM, "unknown output mode");
     pack_links(c, U, false);
     pack_spinor(c, a, c->f64(kStageA));
@@ -365,7 +368,8 @@ static lgt_status md_run(lgt_ctx* c, void* U, void* P, const void* phi, double b
     require(nsteps >= 1, "nsteps must be >= 1");
     require(nlevels >= 0 && nlevels <= kMaxStoutLevels, "nlevels must be in 0..256");
     require(n_inner >= 1, "n_inner must be >= 1");
-    require(std::isfinite(dt) && std::isfinite(rho), "dt and rho must be finite");
+    require(std::isfinite(dt) && std::isfinite(rho) && std::isfinite(kappa) && std::isfinite(beta),
+            "dt, rho, kappa and beta must be finite");
     const SolverOpts o = parse(params);
     const bool ferm = phi != nullptr && kappa != 0.0;
     const bool mixed = ferm && o.precision != LGT_FP64;
@@ -523,6 +527,7 @@ lgt_status lgt_fermion_force_eo(lgt_ctx* c, const void* U, const void* phi, doub
   bool nc = false;
   lgt_status s = guarded(c, [&] {
     require(U && phi && out, "null field pointer");
+    require(std::isfinite(kappa), "kappa must be finite");
     require(mode >= LGT_OUT_FORCE && mode <= LGT_OUT_MOMENTUM, "unknown output mode");
     const SolverOpts o = parse(params);
     Timer tm(c);
@@ -585,6 +590,7 @@ lgt_status lgt_smeared_force(lgt_ctx* c, const void* U, const void* phi, double 
   bool nc = false;
   lgt_status s = guarded(c, [&] {
     require(U && phi && out, "null field pointer");
+    require(std::isfinite(kappa), "kappa must be finite");
     require(mode >= LGT_OUT_FORCE && mode <= LGT_OUT_MOMENTUM, "unknown output mode");
     require(nlevels >= 0 && nlevels <= kMaxStoutLevels && std::isfinite(rho), "invalid smearing parameters");
     const SolverOpts o = parse(params);
