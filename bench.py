@@ -221,7 +221,7 @@ def main():
     # events on the library stream; FP64 beside it
     hop_ms32 = lat.hop_benchmark(U, E, "mixed_fp32", 200)
     hop_ms64 = lat.hop_benchmark(U, E, "fp64", 200)
-    hop_bytes32 = 96 * 4 * V
+    hop_bytes32 = 72 * 4 * V  # two-row FP32 links (48 reals per site) + input and output half spinors
     hop_bytes64 = 96 * 8 * V
     gbs32 = hop_bytes32 / (hop_ms32 * 1e-3) / 1e9
     gbs64 = hop_bytes64 / (hop_ms64 * 1e-3) / 1e9
@@ -273,7 +273,8 @@ def main():
         "eo_preconditioned_action": dict(eo_rec, note="S_eo = phi_o^dag (Mhat^dag Mhat)^-1 phi_o, same determinant "
                                                       "weight, one Schur solve per force; not the metric"),
         "force_vs_oracle": force_vs_oracle,
-        "roofline": {"kernel": "even/odd hop H_eo, FP32 (k_hop<float,false,EpiAxpy<float>>)", "bound": "hbm",
+        "roofline": {"kernel": "even/odd hop H_eo, FP32, two-row SU(3) links (k_hop<float,false,EpiAxpy<float>>)",
+                     "bound": "hbm",
                      "achieved": round(gbs32, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs32 / HBM_PEAK_GBS, 4),
                      "measured_copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(gbs32 / copy_gbs, 4),
@@ -391,7 +392,7 @@ def bench_c3(args):
         if prec in forces:
             res[prec]["force_rel_diff_vs_fp64"] = _rel(forces[prec], forces["fp64"])
     hop_ms = lat.hop_benchmark(U, E, "mixed_fp32", 100)
-    hop_bytes = 96 * 4 * V
+    hop_bytes = 72 * 4 * V  # two-row FP32 links + half spinors
     gbs = hop_bytes / (hop_ms * 1e-3) / 1e9
     t_mixed = res["mixed_fp32"]["ms_per_call"]
     copy_gbs = _copy_ceiling()
@@ -405,7 +406,8 @@ def bench_c3(args):
                    "dims": list(dims), "kappa": kappa, "tol": tol},
         "results": res,
         "speedup_mixed_vs_fp64": round(res["fp64"]["ms_per_call"] / t_mixed, 3),
-        "roofline": {"kernel": "even/odd hop H_eo, FP32", "bound": "hbm", "achieved": round(gbs, 1),
+        "roofline": {"kernel": "even/odd hop H_eo, FP32, two-row SU(3) links", "bound": "hbm",
+                     "achieved": round(gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "measured_copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(gbs / copy_gbs, 4),
                      "traffic": _traffic("hop_fp32_24x24x24x48_traffic.json"),

@@ -334,6 +334,31 @@ hipError_t launch_convert_64_32(int n, const double2* x, float2* y, hipStream_t 
 }
 
 // x (FP64) += scale * xs (FP32); xs = 0
+__global__ __launch_bounds__(256) void k_compress_links(int vh, const float2* __restrict__ U, float2* __restrict__ Uc,
+                                                        int* flag) {
+  const int t = blockIdx.x * 256 + threadIdx.x;  // link (parity, mu) slowest, site fastest
+  if (t >= 8 * vh) return;
+  const int pm = t / vh, cb = t - pm * vh;
+  const float2* src = U + (size_t)pm * 9 * vh + cb;
+  float2* dst = Uc + (size_t)pm * 6 * vh + cb;
+  C<float> m[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) m[k] = ld<float>(src + (size_t)k * vh);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) st<float>(dst + (size_t)k * vh, m[k]);
+  const C<float> r6 = conj(m[1] * m[5] - m[2] * m[4]);
+  const C<float> r7 = conj(m[2] * m[3] - m[0] * m[5]);
+  const C<float> r8 = conj(m[0] * m[4] - m[1] * m[3]);
+  const float dev = fmaxf(fmaxf(fabsf(r6.re - m[6].re) + fabsf(r6.im - m[6].im),
+                                fabsf(r7.re - m[7].re) + fabsf(r7.im - m[7].im)),
+                          fabsf(r8.re - m[8].re) + fabsf(r8.im - m[8].im));
+  if (!(dev <= 1e-5f)) *flag = 1;  // also for NaN
+}
+hipError_t launch_compress_links(const Geom& g, const float2* U32, float2* Uc, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_compress_links, dim3((8 * g.vh + 255) / 256), dim3(256), 0, s, g.vh, U32, Uc, flag);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_mixed_fold(int n, float2* xs, double2* __restrict__ x,
                                                     const SolverState* st) {
   const double scale = 1.0 / st->sigma;

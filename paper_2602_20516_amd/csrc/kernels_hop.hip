@@ -163,10 +163,10 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, In hi
     cb_coords(g, p, cb, c);
     const auto in = make_loader<R>(hin, g, p, 1);
     switch (mu) {
-      case 0: hop_dir<R, 0, DAG>(g, hin.gauge, in, p, cb, c, acc, 0); break;
-      case 1: hop_dir<R, 1, DAG>(g, hin.gauge, in, p, cb, c, acc, 0); break;
-      case 2: hop_dir<R, 2, DAG>(g, hin.gauge, in, p, cb, c, acc, 0); break;
-      default: hop_dir<R, 3, DAG>(g, hin.gauge, in, p, cb, c, acc, 0); break;
+      case 0: hop_dir<R, 0, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, 0); break;
+      case 1: hop_dir<R, 1, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, 0); break;
+      case 2: hop_dir<R, 2, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, 0); break;
+      default: hop_dir<R, 3, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, 0); break;
     }
   }
 #pragma unroll

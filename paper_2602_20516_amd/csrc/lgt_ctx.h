@@ -68,9 +68,11 @@ struct lgt_ctx {
   int device = 0;
   std::string err;
 
-  // packed links: FP64 [2][4][9][vh], FP32 copy (mixed precision)
+  // packed links: FP64 [2][4][9][vh], FP32 copy (mixed precision), and the
+  // FP32 copy's first two rows [2][4][6][vh] for the inner solver's hops
   double2* U64 = nullptr;
   float2* U32 = nullptr;
+  float2* U32c = nullptr;
   // packed momenta for the MD driver
   double2* P64 = nullptr;
 
@@ -102,6 +104,9 @@ struct lgt_ctx {
   double2* g64(int i);   // packed FP64 gauge-type scratch i (allocated on demand)
   float2* h32(int i);    // half FP32 spinor scratch i
   void ensure_u32();
+  // Enqueues the two-row copy of U32 and the check that its links are SU(3),
+  // whose result (host_flags[1] == 0) is valid after the caller's next sync.
+  void compress_links();
   void ensure_p64();
 
   // solver (solver.hip)

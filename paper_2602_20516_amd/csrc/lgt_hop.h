@@ -116,35 +116,52 @@ __device__ __forceinline__ void apply_bc(const Geom& g, C<R>* w) {
   for (int k = 0; k < 6; ++k) w[k] = b * w[k];
 }
 
+// Link U_mu(x) of parity p at checkerboard site cb from a packed field of
+// nk complex components per link: all nine, or the first two rows of an
+// SU(3) matrix, whose third row is the conjugate cross product of the two
+// (one load per component through a buffer resource; uniform branch).
+template <typename R>
+__device__ __forceinline__ M3<R> load_link(const R2<R>* __restrict__ gauge, int nk, const Geom& g, int p, int mu,
+                                           int cb) {
+  constexpr unsigned E = sizeof(R2<R>);
+  const unsigned gs = (unsigned)g.vh * E;
+  const BufRsrc ru = make_rsrc(gauge + (size_t)((p * 4 + mu) * nk) * g.vh, (size_t)nk * gs);
+  M3<R> U;
+  if (nk == 9) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) U.m[k] = ld_buf<R>(ru, (unsigned)cb * E, k * gs);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) U.m[k] = ld_buf<R>(ru, (unsigned)cb * E, k * gs);
+    U.m[6] = conj(U.m[1] * U.m[5] - U.m[2] * U.m[4]);
+    U.m[7] = conj(U.m[2] * U.m[3] - U.m[0] * U.m[5]);
+    U.m[8] = conj(U.m[0] * U.m[4] - U.m[1] * U.m[3]);
+  }
+  return U;
+}
+
 // The hop from x + mu (forward) or x - mu (backward) along MU for output
 // site (p, cb) with coordinates c, right-hand side n of the loader's field,
 // added to acc.
 template <typename R, int MU, bool DAG, typename L>
-__device__ __forceinline__ void hop_fwd(const Geom& g, const R2<R>* __restrict__ gauge, const L& in, int p, int cb,
-                                        const int c[4], C<R>* acc, int n) {
+__device__ __forceinline__ void hop_fwd(const Geom& g, const R2<R>* __restrict__ gauge, int nk, const L& in, int p,
+                                        int cb, const int c[4], C<R>* acc, int n) {
   constexpr int SF = DAG ? +1 : -1;  // forward projector 1 + SF gamma
-  constexpr unsigned E = sizeof(R2<R>);
-  const unsigned gs = (unsigned)g.vh * E;  // link element stride in bytes (uniform)
   C<R> psi[12], h[6], w[6];
   // (1 + SF gamma) U_mu(x) psi(x + mu)
   const unsigned of = in.off(cb_shift(g, c, MU, +1), n);
 #pragma unroll
   for (int k = 0; k < 12; ++k) psi[k] = in.ld(of, k);
   project<R, MU, SF>(psi, h);
-  const BufRsrc ru = make_rsrc(gptr<R>(gauge, g, p, MU), (size_t)9 * gs);
-  M3<R> U;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) U.m[k] = ld_buf<R>(ru, (unsigned)cb * E, k * gs);
+  const M3<R> U = load_link<R>(gauge, nk, g, p, MU, cb);
   umul(U, h, w);
   if (MU == 3 && c[3] == g.L[3] - 1) apply_bc(g, w);
   reconstruct<R, MU, SF>(w, acc);
 }
 template <typename R, int MU, bool DAG, typename L>
-__device__ __forceinline__ void hop_bwd(const Geom& g, const R2<R>* __restrict__ gauge, const L& in, int p,
+__device__ __forceinline__ void hop_bwd(const Geom& g, const R2<R>* __restrict__ gauge, int nk, const L& in, int p,
                                         const int c[4], C<R>* acc, int n) {
   constexpr int SB = DAG ? -1 : +1;  // backward projector 1 + SB gamma
-  constexpr unsigned E = sizeof(R2<R>);
-  const unsigned gs = (unsigned)g.vh * E;
   C<R> psi[12], h[6], w[6];
   // (1 + SB gamma) U_mu(x - mu)^dag psi(x - mu)
   const int nb = cb_shift(g, c, MU, -1);
@@ -152,10 +169,7 @@ __device__ __forceinline__ void hop_bwd(const Geom& g, const R2<R>* __restrict__
 #pragma unroll
   for (int k = 0; k < 12; ++k) psi[k] = in.ld(ob, k);
   project<R, MU, SB>(psi, h);
-  const BufRsrc ru = make_rsrc(gptr<R>(gauge, g, 1 - p, MU), (size_t)9 * gs);
-  M3<R> U;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) U.m[k] = ld_buf<R>(ru, (unsigned)nb * E, k * gs);
+  const M3<R> U = load_link<R>(gauge, nk, g, 1 - p, MU, nb);
   umul_dag(U, h, w);
   if (MU == 3 && c[3] == 0) apply_bc(g, w);
   reconstruct<R, MU, SB>(w, acc);
@@ -163,10 +177,10 @@ __device__ __forceinline__ void hop_bwd(const Geom& g, const R2<R>* __restrict__
 
 // Both hops along MU (forward first), right-hand side n.
 template <typename R, int MU, bool DAG, typename L>
-__device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__ gauge, const L& in, int p, int cb,
-                                        const int c[4], C<R>* acc, int n) {
-  hop_fwd<R, MU, DAG>(g, gauge, in, p, cb, c, acc, n);
-  hop_bwd<R, MU, DAG>(g, gauge, in, p, c, acc, n);
+__device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__ gauge, int nk, const L& in, int p,
+                                        int cb, const int c[4], C<R>* acc, int n) {
+  hop_fwd<R, MU, DAG>(g, gauge, nk, in, p, cb, c, acc, n);
+  hop_bwd<R, MU, DAG>(g, gauge, nk, in, p, c, acc, n);
 }
 
 // The same with the two links already loaded (Uf = U_mu(x), Ub = U_mu(x-mu))

@@ -54,9 +54,11 @@ enum Layout { kCanonical = 0, kPacked = 1 };
 // input spinor (R2<R>, or Bf16c for BF16-stored spinors).
 template <typename R, typename T = R2<R>>
 struct HopIn {
-  const R2<R>* gauge;  // packed links [2][4][9][vh]
+  const R2<R>* gauge;  // packed links [2][4][nk][vh]
   const T* in_even;
   const T* in_odd;
+  int nk = 9;          // 9: full links; 6: the first two rows of SU(3) links (the third
+                       // is rebuilt as the conjugate cross product of the two)
 };
 
 // Host-visible progress of an iterative solve, in pinned host memory: the
@@ -178,6 +180,11 @@ hipError_t launch_xmy64(int n, const double2* x, double2* y, hipStream_t s);    
 hipError_t launch_zero64(int n, double2* y, hipStream_t s);
 hipError_t launch_zero32(int n, float2* y, hipStream_t s);
 hipError_t launch_convert_64_32(int n, const double2* x, float2* y, hipStream_t s);
+// FP32 links in two-row form: Uc[p][mu][6][vh] = rows 0 and 1 of U32, and
+// flag set to 1 (never cleared here) if for some link the third row stored
+// in U32 is not the conjugate cross product of the first two (to 1e-5), i.e.
+// the links are not SU(3) and must not be compressed.
+hipError_t launch_compress_links(const Geom& g, const float2* U32, float2* Uc, int* flag, hipStream_t s);
 // mixed precision helpers
 // Device-side reliable update, enqueued without a host round trip:
 //   launch_mixed_fold:       x += xs / st->sigma; xs = 0

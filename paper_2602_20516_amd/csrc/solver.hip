@@ -51,6 +51,13 @@ void lgt_ctx::ensure_u32() {
   if (!U32) LGT_HIP(hipMalloc(&U32, (size_t)72 * vh * sizeof(float2)));
 }
 
+void lgt_ctx::compress_links() {
+  if (!U32c) LGT_HIP(hipMalloc(&U32c, (size_t)48 * vh * sizeof(float2)));
+  LGT_HIP(hipMemsetAsync(flags + 1, 0, sizeof(int), stream));
+  LGT_HIP(launch_compress_links(g, U32, U32c, flags + 1, stream));
+  LGT_HIP(hipMemcpyAsync(host_flags + 1, flags + 1, sizeof(int), hipMemcpyDeviceToHost, stream));
+}
+
 void lgt_ctx::ensure_p64() {
   if (!P64) LGT_HIP(hipMalloc(&P64, (size_t)72 * vh * sizeof(double2)));
 }
@@ -101,14 +108,14 @@ void lgt_ctx::apply_mhat_dag_mhat64(bool dag, const double2* x, double2* out) {
 // (scalars, stop test, direction update).  t, w, p stored as T; x, r as R2<R>.
 template <typename R, typename T, bool DAG>
 static void cg_iteration(const Geom& g, const R2<R>* gauge, double kappa, T* t, T* w, R2<R>* x, R2<R>* r, T* p,
-                         SolverState* st, Reduce red, hipStream_t s, int n) {
+                         SolverState* st, Reduce red, hipStream_t s, int n, int nk = 9) {
   const double k2 = -kappa * kappa;
-  LGT_HIP((launch_hop_axpy<R, DAG, T>(g, 0, HopIn<R, T>{gauge, p, p}, t, t, nullptr, nullptr, 1.0, s, st)));
-  LGT_HIP((launch_hop_schur_norm<R, T, DAG>(g, HopIn<R, T>{gauge, t, t}, w, p, k2, st, red, s)));
+  LGT_HIP((launch_hop_axpy<R, DAG, T>(g, 0, HopIn<R, T>{gauge, p, p, nk}, t, t, nullptr, nullptr, 1.0, s, st)));
+  LGT_HIP((launch_hop_schur_norm<R, T, DAG>(g, HopIn<R, T>{gauge, t, t, nk}, w, p, k2, st, red, s)));
   // block 0 also forms alpha from the |w|^2 partials
-  LGT_HIP((launch_hop_axpy<R, !DAG, T>(g, 0, HopIn<R, T>{gauge, w, w}, t, t, nullptr, nullptr, 1.0, s, st,
+  LGT_HIP((launch_hop_axpy<R, !DAG, T>(g, 0, HopIn<R, T>{gauge, w, w, nk}, t, t, nullptr, nullptr, 1.0, s, st,
                                          red.partials)));
-  LGT_HIP((launch_hop_schur_cg<R, T, !DAG>(g, HopIn<R, T>{gauge, t, t}, w, x, r, p, k2, st, red, s)));
+  LGT_HIP((launch_hop_schur_cg<R, T, !DAG>(g, HopIn<R, T>{gauge, t, t, nk}, w, x, r, p, k2, st, red, s)));
   LGT_HIP((launch_cg_step<R, T>(n, r, p, st, red, hop_blocks(g, 1), s)));
 }
 
@@ -168,8 +175,15 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
   T* ps = reinterpret_cast<T*>(h32(4));
   double2* r64 = f64(kW2) + half_elems();
   LGT_HIP(launch_zero64(n, z, stream));
+  compress_links();
   LGT_HIP(launch_norm_dot(n, rhs, nullptr, red(), 0, stream));
   read_results(2);
+  // the inner hops read two-row links when the links are SU(3) (the third
+  // row is rebuilt in registers: a third less link traffic); the FP64
+  // residuals of the reliable updates always use the full FP64 links
+  const bool c12 = host_flags[1] == 0;
+  const float2* links = c12 ? U32c : U32;
+  const int nk = c12 ? 6 : 9;
   const double bb = host_result[0];
   if (!std::isfinite(bb)) return kDoneBreakdown;
   if (bb == 0.0) return kDoneConverged;
@@ -197,8 +211,8 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
   int iter0 = 0;
   for (;;) {
     const unsigned long long v = drive(iter0, [&] {
-      if (dag) cg_iteration<float, T, true>(g, U32, kappa, ts, ws, xs, rs, ps, state, red(), stream, n);
-      else cg_iteration<float, T, false>(g, U32, kappa, ts, ws, xs, rs, ps, state, red(), stream, n);
+      if (dag) cg_iteration<float, T, true>(g, links, kappa, ts, ws, xs, rs, ps, state, red(), stream, n, nk);
+      else cg_iteration<float, T, false>(g, links, kappa, ts, ws, xs, rs, ps, state, red(), stream, n, nk);
     }, min_epoch, false);
     unsigned act = (unsigned)(v >> 32);
     int dev_iter = (int)(unsigned)v;
