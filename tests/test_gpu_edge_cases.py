@@ -102,3 +102,18 @@ def test_non_finite_links_and_bad_arguments(lgt, f):
         lat.fermion_force(U, E, float("nan"), lgt.Params())
     X, _, st = lat.cg_solve(U, E, 0.12, lgt.Params(tol=1e-10))  # still usable
     assert st["true_rel_residual"] <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
+def test_mixed_solve_with_links_outside_su3(lgt, f, precision):
+    """Links scaled by 0.9 are not SU(3): the inner solver must read them in
+    full (no third-row reconstruction) and still reach the FP64 answer."""
+    u, eta, lat = f
+    U, E = to_dev(0.9 * u), to_dev(eta)
+    X, _, st = lat.cg_solve(U, E, 0.12, lgt.Params(precision=precision, tol=1e-11))
+    X64, _, st64 = lat.cg_solve(U, E, 0.12, lgt.Params(precision="fp64", tol=1e-11))
+    assert st["true_rel_residual"] <= 1e-11
+    assert rel_err(to_host(X), to_host(X64)) < 1e-9
+    # with the exact operator the inner recursion converges as the FP64 CG
+    # does (a wrongly rebuilt third row would cost many more iterations)
+    assert st["iters"] <= st64["iters"] + 5
