@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4, 5))
     ap.add_argument("--multishift", action="store_true")
     ap.add_argument("--stout-depth", type=int, default=0, help="stout levels of the checkpointing benchmark")
+    ap.add_argument("--hop-shapes", action="store_true",
+                    help="time the two work shapes of the hop kernel (hop alone and inside the force)")
     ap.add_argument("--study", default=None, choices=("dh-vs-dt",))
     ap.add_argument("--therm", type=int, default=100, help="thermalisation trajectories of the study")
     ap.add_argument("--meas", type=int, default=40, help="measured trajectories per step size in the study")
@@ -134,6 +136,9 @@ def main():
         return
     if args.multishift:
         print(json.dumps(bench_multishift(args)), flush=True)
+        return
+    if args.hop_shapes:
+        print(json.dumps(bench_hop_shapes(args)), flush=True)
         return
     if args.stout_depth:
         print(json.dumps(bench_stout_depth(args)), flush=True)
@@ -543,6 +548,51 @@ def bench_multishift(args):
         "note": "the shifted updates (x_i, p_i for every unconverged shift) move 4 x 12 V/2 x 16 B per shift "
                 "and iteration; kernel durations in the committed rocprofv3 summary",
     }
+
+
+def bench_hop_shapes(args):
+    """The single-field hop with 32 and with 64 sites per block (lgt_set_hop_block_sites): one
+    launch alone (HIP events over 300 launches), and the whole force call (10 calls), at
+    lattice sizes around the automatic switch (32 up to 8192 sites per parity)."""
+    import torch
+
+    import lgt_inputs as li
+    import paper_2602_20516_amd as lgt
+
+    rows = []
+    for dims in [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (16, 16, 16, 32), (24, 24, 24, 48)]:
+        U = torch.from_numpy(li.random_links(dims, 0.3, 11)).to("cuda")
+        E = torch.from_numpy(li.gaussian_spinor(dims, 12)).to("cuda")
+        lat = lgt.Lattice(dims)
+        phi = lat.dslash(U, E, 0.125, dagger=True)
+        vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+        for prec in ("mixed_fp32", "fp64"):
+            r = {"dims": list(dims), "sites_per_parity": vh, "precision": prec,
+                 "automatic": 32 if vh <= 8192 else 64}
+            for ns in (32, 64):
+                lat.set_hop_block_sites(ns)
+                r[f"hop_us_{ns}"] = round(1e3 * lat.hop_benchmark(U, E, prec, 300), 3)
+                if vh <= 65536:
+                    prm = lgt.Params(precision=prec, tol=1e-10)
+                    for _ in range(2):
+                        lat.fermion_force(U, phi, 0.125, prm)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(10):
+                        _, st = lat.fermion_force(U, phi, 0.125, prm)
+                    torch.cuda.synchronize()
+                    r[f"force_ms_{ns}"] = round(1e3 * (time.perf_counter() - t0) / 10, 3)
+                    r[f"force_iters_{ns}"] = st["iters"]
+            log("bench hop shapes:", json.dumps(r))
+            rows.append(r)
+        del lat, U, E, phi
+        torch.cuda.empty_cache()
+    return {"metric": "hop kernel work shape: 32 vs 64 sites per block", "unit": "us (hop), ms (force)",
+            "n_gpus": 1, "higher_is_better": False, "dtype": "f32 / f64",
+            "data": "synthetic (seeded SU(3) links eps=0.3, Gaussian eta; phi = D^dag eta, kappa 0.125)",
+            "config": {"workload": "one even/odd hop launch (FP32 two-row links / FP64), and the force call "
+                                   "(mixed FP32 / FP64 CG to 1e-10) up to 16^3x32"},
+            "rows": rows}
 
 
 def bench_stout_depth(args):

@@ -399,7 +399,8 @@ LGT_API lgt_status lgt_rational_force_eo(lgt_ctx* ctx, const void* U, const void
  * with HIP events on the context stream, and returns the mean duration of
  * one launch in *avg_ms.  The algorithmic traffic of one launch is
  * 96 reals per lattice site (all 4V links, the input and output half
- * spinors). */
+ * spinors); 72 in FP32 when the links are SU(3), which the FP32 hop then
+ * reads as their first two rows. */
 LGT_API lgt_status lgt_hop_benchmark(lgt_ctx* ctx, const void* U, const void* psi, int32_t precision,
                                      int32_t nrep, double* avg_ms);
 
@@ -410,6 +411,16 @@ LGT_API lgt_status lgt_hop_benchmark(lgt_ctx* ctx, const void* U, const void* ps
  * its algorithmic traffic is 72 + 24 * nrhs reals per lattice site. */
 LGT_API lgt_status lgt_hop_benchmark_mrhs(lgt_ctx* ctx, const void* U, const void* psi, int32_t nrhs,
                                           int32_t precision, int32_t nrep, double* avg_ms);
+
+/* Work shape of the single-field hop kernel (the Wilson hop of eq. S3.1 in
+ * every solve, force and dslash call of the context): sites = 64 gives each
+ * 256-thread block 64 sites, each wave both hops along one direction;
+ * sites = 32 gives a block 32 sites, each half-wave one of the two hops, so
+ * a small lattice runs twice as many waves.  0 (the default) takes 32 up to
+ * 8192 sites per parity and 64 above.  The two shapes add the eight hop
+ * terms of a site in different orders, so results may differ by rounding;
+ * each is deterministic.  INVALID_ARGUMENT for any other value. */
+LGT_API lgt_status lgt_set_hop_block_sites(lgt_ctx* ctx, int32_t sites);
 
 #ifdef __cplusplus
 }

@@ -401,6 +401,10 @@ class Lattice:
         """lgt_set_stout_checkpoints: cap on the smearing levels kept for the reverse pass (-1: automatic)."""
         _check(self.lib, self.ctx, self.lib.lgt_set_stout_checkpoints(self.ctx, int(max_stored_levels)))
 
+    def set_hop_block_sites(self, sites: int = 0):
+        """lgt_set_hop_block_sites: sites per hop block, 32 or 64 (0: by volume)."""
+        _check(self.lib, self.ctx, self.lib.lgt_set_hop_block_sites(self.ctx, int(sites)))
+
     def stout_last_schedule(self) -> dict:
         """lgt_stout_last_schedule: levels kept and passes recomputed by the last reverse pass."""
         s, p = ctypes.c_int32(), ctypes.c_int64()

@@ -151,6 +151,7 @@ lgt_status lgt_create(const lgt_geom* geom, void* hip_stream, lgt_ctx** out) {
     c->vh = (int)(V / 2);
     c->g.vh = c->vh;
     c->g.bc = geom->fermion_t_bc;
+    c->g.hop_ns = 0;
     c->stream = (hipStream_t)hip_stream;
     LGT_HIP(hipGetDevice(&c->device));
     LGT_HIP(hipMalloc(&c->U64, (size_t)72 * c->vh * sizeof(double2)));
@@ -617,6 +618,14 @@ lgt_status lgt_set_stout_checkpoints(lgt_ctx* c, int32_t max_stored_levels) {
   return guarded(c, [&] {
     require(max_stored_levels >= -1, "max_stored_levels must be -1 (automatic) or >= 0");
     c->stout_slot_cap = max_stored_levels;
+  });
+}
+
+lgt_status lgt_set_hop_block_sites(lgt_ctx* c, int32_t sites) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(sites == 0 || sites == 32 || sites == 64, "hop block sites must be 0 (automatic), 32 or 64");
+    c->g.hop_ns = sites;
   });
 }
 

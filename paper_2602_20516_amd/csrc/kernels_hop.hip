@@ -14,6 +14,8 @@
 // per-direction partial spinors meet in LDS and wave w then owns spin
 // component w of the 64 output sites for the epilogue, so every global load
 // and store is a unit-stride 64-lane access in the [12][vh] SoA layout.
+// Small lattices use 32-site blocks instead, whose half-waves take the
+// forward and the backward hop (unit-stride 32-lane halves).
 // Blocks are numbered XCD-contiguously (see xcd_block).
 #include "lgt_internal.h"
 #include "lgt_hop.h"
@@ -141,10 +143,16 @@ struct EpiResidual {  // r = phi - (self + coef * acc) over both parities, block
 
 // ---------------------------------------------------------------------------
 // The hop kernel.  Grid: nbp blocks per parity (p_fixed >= 0) or 2*nbp
-// (p_fixed < 0, parity = logical block / nbp).
+// (p_fixed < 0, parity = logical block / nbp).  NS = 64: wave mu computes
+// both hops along mu for 64 sites.  NS = 32 (small lattices, where 64-site
+// blocks leave two waves per SIMD): wave mu computes the forward hop of 32
+// sites on lanes 0-31 and their backward hop on lanes 32-63, so twice as
+// many waves share the latency; waves 0 and 1 then run the epilogue, one
+// (site, spin) pair per lane.
 // ---------------------------------------------------------------------------
-template <typename R, bool DAG, typename Epi, typename In>
+template <typename R, bool DAG, typename Epi, typename In, int NS>
 __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, In hin, Epi epi, double* partials) {
+  static_assert(NS == 64 || NS == 32, "64 or 32 sites per block");
   if (epi.skip()) return;
   __shared__ R2<R> lds[4][12][64];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -152,7 +160,8 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, In hi
   const int blk = p_fixed >= 0 ? lb : lb % nbp;
   const int lane = threadIdx.x & 63;
   const int mu = threadIdx.x >> 6;
-  const int cb = blk * 64 + lane;
+  const bool bwd = NS == 32 && lane >= 32;
+  const int cb = blk * NS + (NS == 64 ? lane : lane & 31);
   const bool active = cb < g.vh;
 
   C<R> acc[12];
@@ -162,11 +171,20 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, In hi
     int c[4];
     cb_coords(g, p, cb, c);
     const auto in = make_loader<R>(hin, g, p, 1);
-    switch (mu) {
-      case 0: hop_dir<R, 0, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, 0); break;
-      case 1: hop_dir<R, 1, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, 0); break;
-      case 2: hop_dir<R, 2, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, 0); break;
-      default: hop_dir<R, 3, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, 0); break;
+    if constexpr (NS == 64) {
+      switch (mu) {
+        case 0: hop_dir<R, 0, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, 0); break;
+        case 1: hop_dir<R, 1, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, 0); break;
+        case 2: hop_dir<R, 2, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, 0); break;
+        default: hop_dir<R, 3, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, 0); break;
+      }
+    } else {
+      switch (mu) {
+        case 0: hop_one<R, 0, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, bwd); break;
+        case 1: hop_one<R, 1, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, bwd); break;
+        case 2: hop_one<R, 2, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, bwd); break;
+        default: hop_one<R, 3, DAG>(g, hin.gauge, hin.nk, in, p, cb, c, acc, bwd); break;
+      }
     }
   }
 #pragma unroll
@@ -177,17 +195,38 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, In hi
     lds[mu][k][lane] = v;
   }
   __syncthreads();
-  // wave `mu` now owns spin component `mu` of the 64 sites
-  const int spin = mu;
-  C<R> out[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int k = 3 * spin + i;
-    R2<R> a = lds[0][k][lane], b = lds[1][k][lane], cc = lds[2][k][lane], d = lds[3][k][lane];
-    out[i] = cmk<R>(((a.x + b.x) + cc.x) + d.x, ((a.y + b.y) + cc.y) + d.y);
-  }
   double red = 0.0;
-  if (active) epi.apply(p, cb, spin, out, red);
+  if constexpr (NS == 64) {
+    // wave `mu` now owns spin component `mu` of the 64 sites
+    const int spin = mu;
+    C<R> out[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int k = 3 * spin + i;
+      R2<R> a = lds[0][k][lane], b = lds[1][k][lane], cc = lds[2][k][lane], d = lds[3][k][lane];
+      out[i] = cmk<R>(((a.x + b.x) + cc.x) + d.x, ((a.y + b.y) + cc.y) + d.y);
+    }
+    if (active) epi.apply(p, cb, spin, out, red);
+  } else if (mu < 2) {
+    // lane -> site lane & 31, spin 2 mu + lane / 32; eight partial hops
+    const int site = lane & 31;
+    const int spin = 2 * mu + (lane >> 5);
+    const int cbo = blk * 32 + site;
+    C<R> out[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int k = 3 * spin + i;
+      R sx = R(0), sy = R(0);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const R2<R> f = lds[m][k][site], b = lds[m][k][32 + site];
+        sx += f.x + b.x;
+        sy += f.y + b.y;
+      }
+      out[i] = cmk<R>(sx, sy);
+    }
+    if (cbo < g.vh) epi.apply(p, cbo, spin, out, red);
+  }
   if constexpr (Epi::kReduce) {
     double v[1] = {red};
     block_partials<256, 1>(v, partials, lb);
@@ -195,7 +234,16 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, In hi
   epi.template tail<256>();
 }
 
-static inline int nblk_parity(const Geom& g) { return (g.vh + 63) / 64; }
+// Sites per hop block: the context's choice, else 32 on small lattices
+// (kHopHalfWaveMaxVh sites per parity and below), 64 above.
+static inline int hop_sites_per_block(const Geom& g) {
+  if (g.hop_ns == 32 || g.hop_ns == 64) return g.hop_ns;
+  return g.vh <= kHopHalfWaveMaxVh ? 32 : 64;
+}
+static inline int nblk_parity(const Geom& g) {
+  const int ns = hop_sites_per_block(g);
+  return (g.vh + ns - 1) / ns;
+}
 
 template <typename R, bool DAG, typename Epi, typename In>
 static hipError_t launch(const Geom& g, int p_out, const In& hin, const Epi& epi, double* partials, hipStream_t s,
@@ -203,7 +251,10 @@ static hipError_t launch(const Geom& g, int p_out, const In& hin, const Epi& epi
   const int nbp = nblk_parity(g);
   const int nb = p_out >= 0 ? nbp : 2 * nbp;
   if (Epi::kReduce && nb > capacity) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_hop<R, DAG, Epi, In>), dim3(nb), dim3(256), 0, s, g, nbp, p_out, hin, epi, partials);
+  if (hop_sites_per_block(g) == 32)
+    hipLaunchKernelGGL((k_hop<R, DAG, Epi, In, 32>), dim3(nb), dim3(256), 0, s, g, nbp, p_out, hin, epi, partials);
+  else
+    hipLaunchKernelGGL((k_hop<R, DAG, Epi, In, 64>), dim3(nb), dim3(256), 0, s, g, nbp, p_out, hin, epi, partials);
   return hipGetLastError();
 }
 

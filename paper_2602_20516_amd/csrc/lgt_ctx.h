@@ -87,7 +87,7 @@ struct lgt_ctx {
   double* partials = nullptr;
   double* result = nullptr;      // device results
   double* host_result = nullptr; // pinned mirror
-  int* flags = nullptr;          // device: [0] non-finite input
+  int* flags = nullptr;          // device: [0] non-finite input, [1] links not SU(3)
   int* host_flags = nullptr;     // pinned
   lgt::SolverState* host_state = nullptr;  // pinned
   lgt::Mailbox* mbox_host = nullptr;        // pinned, coherent: progress posted by CG steps

@@ -239,6 +239,7 @@ struct Geom {
   int hx;     // Lx / 2
   int vh;     // V / 2 (sites per parity)
   int bc;     // fermion temporal boundary sign
+  int hop_ns; // sites per hop block: 32 or 64, or 0 to choose by volume
 };
 
 __device__ __forceinline__ void cb_coords(const Geom& g, int p, int cb, int c[4]) {

@@ -10,13 +10,13 @@
 
 namespace lgt {
 
-// h = u + S * B_mu d  for one spinor (comp = 3*spin + colour); S = +-1.
-template <typename R, int MU, int S>
-__device__ __forceinline__ void project(const C<R>* psi, C<R>* h) {
+// h = u + s * B_mu d  for one spinor (comp = 3*spin + colour); s = +-1
+// (a per-lane value in the half-wave hop, a constant otherwise).
+template <typename R, int MU>
+__device__ __forceinline__ void project_s(const C<R>* psi, const R s, C<R>* h) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const C<R> u0 = psi[i], u1 = psi[3 + i], d0 = psi[6 + i], d1 = psi[9 + i];
-    const R s = R(S);
     if constexpr (MU == 0) {         // B = -i sigma_1: B d = (-i d1, -i d0)
       h[i] = u0 - s * itimes(d1);
       h[3 + i] = u1 - s * itimes(d0);
@@ -32,14 +32,17 @@ __device__ __forceinline__ void project(const C<R>* psi, C<R>* h) {
     }
   }
 }
-
-// acc_up += w ; acc_dn += S * B_mu^dag w
 template <typename R, int MU, int S>
-__device__ __forceinline__ void reconstruct(const C<R>* w, C<R>* acc) {
+__device__ __forceinline__ void project(const C<R>* psi, C<R>* h) {
+  project_s<R, MU>(psi, R(S), h);
+}
+
+// acc_up += w ; acc_dn += s * B_mu^dag w
+template <typename R, int MU>
+__device__ __forceinline__ void reconstruct_s(const C<R>* w, const R s, C<R>* acc) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const C<R> w0 = w[i], w1 = w[3 + i];
-    const R s = R(S);
     acc[i] += w0;
     acc[3 + i] += w1;
     if constexpr (MU == 0) {         // B^dag = i sigma_1: (i w1, i w0)
@@ -56,6 +59,10 @@ __device__ __forceinline__ void reconstruct(const C<R>* w, C<R>* acc) {
       acc[9 + i] += s * w1;
     }
   }
+}
+template <typename R, int MU, int S>
+__device__ __forceinline__ void reconstruct(const C<R>* w, C<R>* acc) {
+  reconstruct_s<R, MU>(w, R(S), acc);
 }
 
 // Input loaders: off(site, n) gives the per-lane byte offset of (site, rhs n)
@@ -181,6 +188,50 @@ __device__ __forceinline__ void hop_dir(const Geom& g, const R2<R>* __restrict__
                                         int cb, const int c[4], C<R>* acc, int n) {
   hop_fwd<R, MU, DAG>(g, gauge, nk, in, p, cb, c, acc, n);
   hop_bwd<R, MU, DAG>(g, gauge, nk, in, p, c, acc, n);
+}
+
+// One of the two hops along MU, chosen per lane (bwd): the form of the
+// half-wave hop kernel, whose lanes 0-31 take the forward and lanes 32-63 the
+// backward hop of the same 32 sites.  Both halves run the same instructions:
+// the neighbour, the link's parity and site, the projector sign, the dagger
+// and the boundary test are per-lane values, and the link resource spans
+// both parities so that its base stays uniform (the host keeps the gauge
+// field of a lattice this kernel runs on far below 4 GiB).
+template <typename R, int MU, bool DAG, typename L>
+__device__ __forceinline__ void hop_one(const Geom& g, const R2<R>* __restrict__ gauge, int nk, const L& in, int p,
+                                        int cb, const int c[4], C<R>* acc, bool bwd) {
+  constexpr int SF = DAG ? +1 : -1;  // forward projector 1 + SF gamma, backward 1 - SF gamma
+  constexpr unsigned E = sizeof(R2<R>);
+  const R s = bwd ? R(-SF) : R(SF);
+  const int nb = cb_shift(g, c, MU, bwd ? -1 : +1);
+  C<R> psi[12], h[6], w[6];
+  const unsigned o = in.off(nb, 0);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) psi[k] = in.ld(o, k);
+  project_s<R, MU>(psi, s, h);
+  // U_mu(x) of parity p at cb, or U_mu(x - mu) of parity 1 - p at nb
+  const unsigned gs = (unsigned)g.vh * E;
+  const BufRsrc ru = make_rsrc(gauge, (size_t)8 * nk * gs);
+  const unsigned lo = ((unsigned)(((bwd ? 1 - p : p) * 4 + MU) * nk) * (unsigned)g.vh + (unsigned)(bwd ? nb : cb)) * E;
+  M3<R> U;
+  if (nk == 9) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) U.m[k] = ld_buf<R>(ru, lo, k * gs);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) U.m[k] = ld_buf<R>(ru, lo, k * gs);
+    U.m[6] = conj(U.m[1] * U.m[5] - U.m[2] * U.m[4]);
+    U.m[7] = conj(U.m[2] * U.m[3] - U.m[0] * U.m[5]);
+    U.m[8] = conj(U.m[0] * U.m[4] - U.m[1] * U.m[3]);
+  }
+  M3<R> A;  // U, or U^dag on the backward lanes
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) A.m[3 * i + j] = bwd ? conj(U.m[3 * j + i]) : U.m[3 * i + j];
+  umul(A, h, w);
+  if (MU == 3 && c[3] == (bwd ? 0 : g.L[3] - 1)) apply_bc(g, w);
+  reconstruct_s<R, MU>(w, s, acc);
 }
 
 // The same with the two links already loaded (Uf = U_mu(x), Ub = U_mu(x-mu))

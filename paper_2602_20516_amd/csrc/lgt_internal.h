@@ -106,10 +106,15 @@ hipError_t launch_finalize(int mode, int nblk, Reduce red, SolverState* st, int 
 // number of blocks of a hop launch (p_out >= 0: one parity, -1: both)
 int hop_blocks(const Geom& g, int p_out);
 
+// Lattices with at most this many sites per parity run the hop with 32
+// sites per block (half-wave hops), larger ones with 64.
+constexpr int kHopHalfWaveMaxVh = 8192;
+
 // Reduction capacity needed for a lattice with vh sites per parity: the
-// largest reducing grid is the both-parity hop (2 * ceil(vh/64) blocks).
+// largest reducing grid is the both-parity hop (2 * ceil(vh/32) blocks at
+// most).
 inline int reduce_capacity(int vh) {
-  const int nb = 2 * ((vh + 63) / 64);
+  const int nb = 2 * ((vh + 31) / 32);
   return nb < 1024 ? 1024 : nb;
 }
 

@@ -1,0 +1,116 @@
+"""Both work shapes of the single-field hop kernel against the oracle.
+
+The hop runs with 64 sites per block (each wave both hops along one
+direction) or 32 (each half-wave one hop), chosen by volume unless the
+context fixes it (lgt_set_hop_block_sites).  Most lattices the oracle handles
+in a test are small enough for the automatic choice to be 32, so this file
+forces each shape on the same inputs: D and D^dag (FP64, 1e-13 as the other
+deterministic maps), the force in all three solver precisions (whose CG
+launches the hop with every epilogue: Schur norm, CG update, residual), and
+the multi-shift solve.  Shapes: a lattice smaller than one block, lattices
+whose per-parity site count leaves a ragged last block for both shapes, and
+an unragged one."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import lgt_inputs as li
+from oracle import dirac, eo, force
+
+from gpu_common import max_rel_err, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SITES = [32, 64]
+# sites per parity: 16 (below one block), 432 (ragged for 32 and 64),
+# 1080 (ragged for both), 384 (a whole number of blocks for both)
+DIMS = [(2, 2, 2, 4), (6, 6, 6, 4), (10, 6, 6, 6), (8, 4, 6, 4)]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lgt():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2602_20516_amd as m
+    return m
+
+
+def _lattice(lgt, dims, sites):
+    lat = lgt.Lattice(dims)
+    lat.set_hop_block_sites(sites)
+    return lat
+
+
+@pytest.mark.parametrize("sites", SITES)
+@pytest.mark.parametrize("dims", DIMS)
+def test_dslash_both_shapes(lgt, dims, sites):
+    say("dslash", dims, "sites per block", sites)
+    u, psi = li.random_links(dims, 0.5, 501), li.gaussian_spinor(dims, 502)
+    lat = _lattice(lgt, dims, sites)
+    U, PSI = to_dev(u), to_dev(psi)
+    for dag in (False, True):
+        got = to_host(lat.dslash(U, PSI, 0.13, dag))
+        ref = (dirac.dslash_dag if dag else dirac.dslash)(u, psi, 0.13)
+        assert rel_err(got, ref) < 1e-13
+        assert max_rel_err(got, ref) < 1e-13
+
+
+@functools.lru_cache(maxsize=1)
+def _force_case():
+    dims = (6, 6, 6, 4)
+    u, eta = li.random_links(dims, 0.5, 511), li.gaussian_spinor(dims, 512)
+    phi = dirac.dslash_dag(u, eta, 0.12)
+    return dims, u, phi, force.fermion_force(u, phi, 0.12, tol=1e-14)
+
+
+@pytest.mark.parametrize("sites", SITES)
+@pytest.mark.parametrize("precision,gate", [("fp64", 1e-11), ("mixed_fp32", 1e-9), ("mixed_bf16", 1e-9)])
+def test_force_both_shapes(lgt, precision, gate, sites):
+    dims, u, phi, ref = _force_case()
+    k = 0.12
+    lat = _lattice(lgt, dims, sites)
+    got, st = lat.fermion_force(to_dev(u), to_dev(phi), k, lgt.Params(precision=precision, tol=1e-13))
+    e = rel_err(to_host(got), ref)
+    say("force", precision, "sites per block", sites, "iters", st["iters"], "rel err", e)
+    assert st["true_rel_residual"] <= 1e-13
+    assert e < gate
+
+
+@pytest.mark.parametrize("sites", SITES)
+def test_multishift_both_shapes(lgt, sites):
+    dims = (6, 6, 6, 4)
+    k = 0.125
+    u, eta = li.random_links(dims, 0.5, 521), li.gaussian_spinor(dims, 522)
+    phi_o = eo.schur_dag(u, eo.parity_mask(dims, 1) * eta, k)
+    shifts = [0.0, 0.02, 1.5]
+    lat = _lattice(lgt, dims, sites)
+    Xs, st = lat.cg_solve_multishift(to_dev(u), to_dev(phi_o), k, shifts, lgt.Params(tol=1e-13))
+    assert st["true_rel_residual"] <= 1e-13
+    for s, X in zip(shifts, Xs):
+        assert rel_err(to_host(X), eo.solve_normal(u, phi_o, k, shift=s, tol=1e-15)) < 1e-11
+
+
+def test_shapes_agree_and_setting_is_checked(lgt):
+    """The two shapes sum the eight hop terms in different orders: FP64
+    results agree to rounding, and each shape repeats its own bits."""
+    dims = (10, 6, 6, 6)
+    u, psi = li.random_links(dims, 0.5, 531), li.gaussian_spinor(dims, 532)
+    lat = lgt.Lattice(dims)
+    U, PSI = to_dev(u), to_dev(psi)
+    out = {}
+    for sites in (32, 64, 0):
+        lat.set_hop_block_sites(sites)
+        a = to_host(lat.dslash(U, PSI, 0.13))
+        assert np.array_equal(a, to_host(lat.dslash(U, PSI, 0.13)))
+        out[sites] = a
+    assert rel_err(out[32], out[64]) < 1e-15
+    assert np.array_equal(out[0], out[32])  # 1080 sites per parity: automatic choice is 32
+    for bad in (-1, 16, 48, 128):
+        with pytest.raises(lgt.LGTError):
+            lat.set_hop_block_sites(bad)
