@@ -123,7 +123,7 @@ def main():
     ap.add_argument("--stout-depth", type=int, default=0, help="stout levels of the checkpointing benchmark")
     ap.add_argument("--hop-shapes", action="store_true",
                     help="time the two work shapes of the hop kernel (hop alone and inside the force)")
-    ap.add_argument("--study", default=None, choices=("dh-vs-dt",))
+    ap.add_argument("--study", default=None, choices=("dh-vs-dt", "reliable-delta"))
     ap.add_argument("--therm", type=int, default=100, help="thermalisation trajectories of the study")
     ap.add_argument("--meas", type=int, default=40, help="measured trajectories per step size in the study")
     args = ap.parse_args()
@@ -133,6 +133,9 @@ def main():
         sys.exit(2)
     if args.study == "dh-vs-dt":
         print(json.dumps(study_dh_vs_dt(args)), flush=True)
+        return
+    if args.study == "reliable-delta":
+        print(json.dumps(study_reliable_delta(args)), flush=True)
         return
     if args.multishift:
         print(json.dumps(bench_multishift(args)), flush=True)
@@ -706,6 +709,47 @@ def bench_c5(args):
         "iters": st["iters"], "reliable_updates": st["reliable_updates"],
         "max_true_rel_residual": st["true_rel_residual"], "V": int(np.prod(dims)),
     }
+
+
+def study_reliable_delta(args):
+    """The mixed-precision force call over the reliable-update threshold delta (lgt_solver_params
+    reliable_delta) at 16^4 and 24^3x48: time, inner iterations, FP64 updates, true residual."""
+    import torch
+
+    import lgt_inputs as li
+    import paper_2602_20516_amd as lgt
+
+    rows = []
+    for cfg in (2, 3):
+        c = li.config(cfg)
+        dims, kappa = c["dims"], c["kappa"]
+        U = torch.from_numpy(li.random_links(dims, c["eps"], c["seeds"]["links"])).to("cuda")
+        E = torch.from_numpy(li.gaussian_spinor(dims, c["seeds"]["eta"])).to("cuda")
+        lat = lgt.Lattice(dims)
+        phi = lat.dslash(U, E, kappa, dagger=True)
+        reps = 5 if cfg == 2 else 2
+        for prec in ("mixed_fp32", "mixed_bf16"):
+            for d in (3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5):
+                prm = lgt.Params(precision=prec, tol=c["tol"], reliable_delta=d)
+                lat.fermion_force(U, phi, kappa, prm)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    _, st = lat.fermion_force(U, phi, kappa, prm)
+                torch.cuda.synchronize()
+                r = {"dims": list(dims), "precision": prec, "delta": d,
+                     "ms": round(1e3 * (time.perf_counter() - t0) / reps, 3), "iters": st["iters"],
+                     "reliable_updates": st["reliable_updates"], "true_rel_residual": st["true_rel_residual"]}
+                log("study reliable delta:", json.dumps(r))
+                rows.append(r)
+        del lat, U, E, phi
+        torch.cuda.empty_cache()
+    return {"metric": "mixed-precision force call vs the reliable-update threshold", "unit": "ms/call",
+            "n_gpus": 1, "higher_is_better": False, "dtype": "f32+f64",
+            "data": "synthetic (the 16^4 and 24^3x48 force workloads' seeded links and pseudofermions)",
+            "config": {"workload": "lgt_fermion_force, FP32 inner with FP32- or BF16-stored vectors, FP64 true "
+                                   "residual 1e-10, delta from 3e-2 to 1e-5"},
+            "rows": rows}
 
 
 def study_dh_vs_dt(args):

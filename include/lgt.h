@@ -122,8 +122,10 @@ typedef struct lgt_solver_params {
   int32_t max_iter;      /* cap on inner CG iterations per solve (<= 0: 20000) */
   double reliable_delta; /* mixed precision: FP64 residual update when the inner
                             residual norm drops by this factor (outside (0, 1):
-                            0.001 for LGT_MIXED_FP32, 0.01 for LGT_MIXED_BF16,
-                            whose recursion drifts faster) */
+                            3e-4 for LGT_MIXED_FP32, 0.01 for LGT_MIXED_BF16,
+                            whose recursion drifts faster; with BF16 storage,
+                            values other than the default can cost twice the
+                            iterations) */
 } lgt_solver_params;
 
 typedef struct lgt_solver_stats {

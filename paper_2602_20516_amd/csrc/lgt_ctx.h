@@ -48,7 +48,7 @@ struct SolverOpts {
   int precision = LGT_FP64;
   double tol = 1e-10;
   int max_iter = 20000;
-  double delta = 0.001;
+  double delta = 3e-4;
 };
 
 }  // namespace lgt
