@@ -24,7 +24,10 @@
 namespace lgt {
 
 // ---------------------------------------------------------------------------
-// Epilogues (element (k, n, cb) of the hop result, offset o).
+// Epilogues (element (k, n, cb) of the hop result, offset o).  rhs_active(n)
+// false: nothing of right-hand side n in this launch is used (its CG has
+// stopped: converged, or idle until the next reliable update), so the
+// kernel skips its hop and writes 0 for its partial.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct MEpiAxpy {  // out = self + coef_n * acc
@@ -37,6 +40,7 @@ struct MEpiAxpy {  // out = self + coef_n * acc
   int pap_nblk;
   BatchState* state;
   __device__ bool skip() const { return guard && guard->all_done; }
+  __device__ bool rhs_active(int n) const { return !guard || guard->done[n] == kDoneRunning; }
   __device__ void apply(int p, size_t o, int n, C<R> a, double&) const {
     C<R> v = R(coef[n]) * a;
     if (self[p]) v += ld<R>(self[p] + o);
@@ -70,6 +74,7 @@ struct MEpiSchurNorm {  // w = x + coef_n acc, per-RHS |w|^2
   const double* coef;
   const BatchState* state;
   __device__ bool skip() const { return state->all_done; }
+  __device__ bool rhs_active(int n) const { return state->done[n] == kDoneRunning; }
   __device__ void apply(int, size_t o, int n, C<R> a, double& red) const {
     const C<R> v = ld<R>(x + o) + R(coef[n]) * a;
     st<R>(w + o, v);
@@ -88,6 +93,7 @@ struct MEpiSchurCG {  // q = w + coef_n acc; x += alpha_n p; r -= alpha_n q (unl
   const double* coef;
   const BatchState* state;
   __device__ bool skip() const { return state->all_done; }
+  __device__ bool rhs_active(int n) const { return state->done[n] == kDoneRunning; }
   __device__ void apply(int, size_t o, int n, C<R> a, double& red) const {
     C<R> rv = ld<R>(r + o);
     if (!state->done[n]) {
@@ -109,6 +115,7 @@ struct MEpiResidual {  // r = phi - (self + coef_n acc), per-RHS |r|^2 (both par
   double2* r[2];
   const double* coef;
   __device__ bool skip() const { return false; }
+  __device__ bool rhs_active(int) const { return true; }
   __device__ void apply(int p, size_t o, int n, C<double> a, double& red) const {
     const C<double> v = ld<double>(phi[p] + o) - (ld<double>(self[p] + o) + coef[n] * a);
     st<double>(r[p] + o, v);
@@ -155,6 +162,18 @@ __global__ __launch_bounds__(256) void k_hop_mrhs(Geom g, int nr, int G, int nbp
   const int mu = threadIdx.x >> 6;
   const int cb = blk * 64 + lane;
   const bool active = cb < g.vh;
+  // the group's running right-hand sides, read once per block so that every
+  // thread skips the same ones (a later write to the state by another block
+  // concerns a right-hand side whose results this launch no longer needs)
+  __shared__ unsigned s_act;
+  if (threadIdx.x == 0) {
+    unsigned m = 0;
+    for (int n = n0; n < n1; ++n) m |= (epi.rhs_active(n) ? 1u : 0u) << (n - n0);
+    s_act = m;
+  }
+  if (threadIdx.x < 4 * kMaxRhs) wred[threadIdx.x / kMaxRhs][threadIdx.x % kMaxRhs] = 0.0;
+  __syncthreads();
+  const unsigned act = s_act;
   constexpr unsigned E = sizeof(R2<R>);
   const unsigned gs = (unsigned)g.vh * E;
   const unsigned ns = (unsigned)g.vh * E;
@@ -172,7 +191,7 @@ __global__ __launch_bounds__(256) void k_hop_mrhs(Geom g, int nr, int G, int nbp
   M3<R> Uf, Ub;
 #pragma unroll
   for (int k = 0; k < 9; ++k) Uf.m[k] = Ub.m[k] = czero<R>();
-  if (kKeepLinks && active) {
+  if (kKeepLinks && active && act) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       Uf.m[k] = ld_buf<R>(ruf, (unsigned)cb * E, k * gs);
@@ -180,6 +199,7 @@ __global__ __launch_bounds__(256) void k_hop_mrhs(Geom g, int nr, int G, int nbp
     }
   }
   for (int n = n0; n < n1; ++n) {
+    if (!((act >> (n - n0)) & 1u)) continue;  // uniform: the block's mask
     C<R> acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = czero<R>();
