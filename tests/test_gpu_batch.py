@@ -93,3 +93,35 @@ def test_batch_rejects_bf16_storage(lgt):
     with pytest.raises(lgt.LGTError):
         lat.cg_solve_batch(to_dev(u), [to_dev(e) for _, e in items[:2]], [k for k, _ in items[:2]],
                            lgt.Params(precision="mixed_bf16"))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_batch_with_systems_that_stop_at_once(lgt, precision):
+    """A zero right-hand side (stopped before the first iteration) and kappa = 0
+    (D = 1: converged after one) in the same group as systems that run on: the
+    batched hop skips the stopped ones, which keep their exact answers
+    (X = Y = 0; X = Y = phi), and the others still match the oracle."""
+    dims = (6, 4, 4, 8)
+    u = li.random_links(dims, 0.3, 411)
+    etas = [li.gaussian_spinor(dims, s) for s in (412, 413, 414)]
+    kappas = [0.12, 0.0, 0.13, 0.125]
+    phis = [dirac.dslash_dag(u, etas[0], kappas[0]), etas[1], np.zeros_like(etas[0]),
+            dirac.dslash_dag(u, etas[2], kappas[3])]
+    lat = lgt.Lattice(dims)
+    Xs, Ys, st = lat.cg_solve_batch(to_dev(u), [to_dev(p) for p in phis], kappas,
+                                    lgt.Params(precision=precision, tol=1e-12))
+    say("batch stops", precision, [s["iters"] for s in st])
+    assert np.abs(to_host(Xs[2])).max() == 0.0 and np.abs(to_host(Ys[2])).max() == 0.0
+    assert st[2]["iters"] == 0
+    # D = 1: the true residual is phi - X itself
+    assert st[1]["true_rel_residual"] <= 1e-12
+    assert rel_err(to_host(Xs[1]), etas[1]) < 2e-12 and rel_err(to_host(Ys[1]), etas[1]) < 2e-12
+    if precision == "fp64":
+        # (a mixed batch counts a system's iterations up to the reliable update
+        # that verifies it, and a stopped system waits for the batch's update)
+        assert st[1]["iters"] <= 2
+    for i, eta in ((0, etas[0]), (3, etas[2])):
+        assert st[i]["true_rel_residual"] <= 1e-12
+        x_ref, _, _, _ = solver.solve_ddag_d(u, phis[i], kappas[i], tol=1e-14)
+        assert rel_err(to_host(Xs[i]), x_ref) < 1e-9
+        assert rel_err(to_host(Ys[i]), eta) < 1e-9
