@@ -308,11 +308,15 @@ SolveStats lgt_ctx::solve_ddagd(const double2* phi, double2* X, double2* Y, cons
     st.true_res = std::sqrt(host_result[0] / pp);
     if (!std::isfinite(st.true_res)) throw Error(LGT_ERR_NONFINITE, "non-finite residual");
     if (st.true_res <= o.tol || !st.converged || pass >= 4) break;
-    // defect correction: D^dag D e = r, X += e
+    // defect correction: D^dag D e = r, X += e.  r only has to shrink by the
+    // factor tol / true_res (with the first pass's margin), not by tol: a
+    // pass that missed the target by 2x needs a few iterations, not a full
+    // solve that would overshoot to ~tol^2
+    const double tol_corr = std::min(0.25, std::max(tol_in, 0.25 * o.tol / st.true_res));
     double2* ytmp = f64(kYtmp);
     double2* e = f64(kE);
-    solve_M(true, ytmp, r, tol_in, o.max_iter, o.precision, o.delta, st);
-    solve_M(false, e, ytmp, tol_in, o.max_iter, o.precision, o.delta, st);
+    solve_M(true, ytmp, r, tol_corr, o.max_iter, o.precision, o.delta, st);
+    solve_M(false, e, ytmp, tol_corr, o.max_iter, o.precision, o.delta, st);
     LGT_HIP(launch_axpy64(nf, 1.0, e, X, stream));
   }
   if (st.true_res > o.tol) st.converged = false;
@@ -352,16 +356,16 @@ SolveStats lgt_ctx::solve_eo(const double2* phi, double2* X, double2* A, const S
     return st;
   }
   const double tol_in = o.tol * 0.5;
-  auto schur_solve = [&](double2* z, const double2* rhs) {
-    const int code = o.precision == LGT_MIXED_FP32   ? cg_normal_mixed<float2>(false, z, rhs, tol_in, o.max_iter,
+  auto schur_solve = [&](double2* z, const double2* rhs, double t) {
+    const int code = o.precision == LGT_MIXED_FP32   ? cg_normal_mixed<float2>(false, z, rhs, t, o.max_iter,
                                                                              o.delta, st)
-                     : o.precision == LGT_MIXED_BF16 ? cg_normal_mixed<Bf16c>(false, z, rhs, tol_in, o.max_iter,
+                     : o.precision == LGT_MIXED_BF16 ? cg_normal_mixed<Bf16c>(false, z, rhs, t, o.max_iter,
                                                                             o.delta, st)
-                                                     : cg_normal64(false, z, rhs, tol_in, o.max_iter, st);
+                                                     : cg_normal64(false, z, rhs, t, o.max_iter, st);
     if (code == kDoneBreakdown) throw Error(LGT_ERR_NONFINITE, "CG breakdown (non-finite or zero curvature)");
     if (code == kDoneMaxIter) st.converged = false;
   };
-  schur_solve(xo, phio);
+  schur_solve(xo, phio, tol_in);
   double2* r = f64(kRes) + h;
   double2* e = f64(kE) + h;
   for (int pass = 0;; ++pass) {
@@ -372,7 +376,8 @@ SolveStats lgt_ctx::solve_eo(const double2* phi, double2* X, double2* A, const S
     st.true_res = std::sqrt(host_result[0] / pp);
     if (!std::isfinite(st.true_res)) throw Error(LGT_ERR_NONFINITE, "non-finite residual");
     if (st.true_res <= o.tol || !st.converged || pass >= 4) break;
-    schur_solve(e, r);
+    // a correction only has to shrink r by tol / true_res (as in solve_ddagd)
+    schur_solve(e, r, std::min(0.5, std::max(tol_in, 0.5 * o.tol / st.true_res)));
     LGT_HIP(launch_axpy64(n, 1.0, e, xo, stream));
   }
   if (st.true_res > o.tol) st.converged = false;

@@ -117,3 +117,21 @@ def test_mixed_solve_with_links_outside_su3(lgt, f, precision):
     # with the exact operator the inner recursion converges as the FP64 CG
     # does (a wrongly rebuilt third row would cost many more iterations)
     assert st["iters"] <= st64["iters"] + 5
+
+
+def test_defect_correction_asks_only_for_the_missing_factor(lgt):
+    """24^3x48 (the workload of the 24^3x48 force benchmark) with BF16-stored
+    inner vectors and reliable_delta 1e-3: the first pass of the two Schur
+    solves ends just short of the requested true residual, so an FP64
+    defect-correction pass follows.  That pass only has to shrink the
+    residual by tol / true_res; solved to the full relative tolerance it
+    doubled the iteration count (892 against about 400)."""
+    c = li.config(3)
+    dims = c["dims"]
+    lat = lgt.Lattice(dims)
+    U = to_dev(li.random_links(dims, c["eps"], c["seeds"]["links"]))
+    phi = lat.dslash(U, to_dev(li.gaussian_spinor(dims, c["seeds"]["eta"])), c["kappa"], dagger=True)
+    _, st = lat.fermion_force(U, phi, c["kappa"], lgt.Params(precision="mixed_bf16", tol=c["tol"],
+                                                              reliable_delta=1e-3))
+    assert st["true_rel_residual"] <= c["tol"]
+    assert st["iters"] < 600
