@@ -392,14 +392,20 @@ struct BatchSolver {
                                          c->stream));
       read_results(nr);
       bool ok = true;
+      double worst = 0.0;  // largest true residual still above the target
       for (int k = 0; k < nr; ++k) {
         st[k].true_res = pp[k] > 0.0 ? std::sqrt(c->host_result[k] / pp[k]) : 0.0;
         if (!std::isfinite(st[k].true_res)) throw Error(LGT_ERR_NONFINITE, "non-finite residual");
-        ok = ok && (st[k].true_res <= o.tol || !st[k].converged);
+        const bool done_k = st[k].true_res <= o.tol || !st[k].converged;
+        ok = ok && done_k;
+        if (!done_k) worst = std::max(worst, st[k].true_res);
       }
       if (ok || pass >= 4) break;
-      solve_M(true, F(bYtmp), F(bRes), tol_in);
-      solve_M(false, F(bE), F(bYtmp), tol_in);
+      // a correction only has to shrink each residual by tol / true_res (the
+      // single solve's rule, for the worst right-hand side)
+      const double tol_corr = std::min(0.25, std::max(tol_in, 0.25 * o.tol / worst));
+      solve_M(true, F(bYtmp), F(bRes), tol_corr);
+      solve_M(false, F(bE), F(bYtmp), tol_corr);
       LGT_HIP(launch_axpy64((int)nfull, 1.0, F(bE), F(bX), c->stream));
     }
     for (int k = 0; k < nr; ++k)
