@@ -421,7 +421,8 @@ LGT_API lgt_status lgt_hop_benchmark_mrhs(lgt_ctx* ctx, const void* U, const voi
  * a small lattice runs twice as many waves.  0 (the default) takes 32 up to
  * 8192 sites per parity and 64 above.  The two shapes add the eight hop
  * terms of a site in different orders, so results may differ by rounding;
- * each is deterministic.  INVALID_ARGUMENT for any other value. */
+ * each is deterministic.  INVALID_ARGUMENT for any other value, and for 32
+ * on a lattice whose FP64 gauge field is 4 GiB or more (V above 7456540). */
 LGT_API lgt_status lgt_set_hop_block_sites(lgt_ctx* ctx, int32_t sites);
 
 #ifdef __cplusplus

@@ -628,6 +628,10 @@ lgt_status lgt_set_hop_block_sites(lgt_ctx* c, int32_t sites) {
   if (!c) return LGT_ERR_INVALID_ARGUMENT;
   return guarded(c, [&] {
     require(sites == 0 || sites == 32 || sites == 64, "hop block sites must be 0 (automatic), 32 or 64");
+    // the 32-site kernel addresses both parities' links through one buffer
+    // resource with 32-bit offsets
+    require(sites != 32 || (size_t)72 * c->vh * sizeof(double2) < ((size_t)1 << 32),
+            "32-site hop blocks need a gauge field below 4 GiB (V at most 7456540 sites)");
     c->g.hop_ns = sites;
   });
 }

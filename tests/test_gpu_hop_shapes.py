@@ -114,3 +114,18 @@ def test_shapes_agree_and_setting_is_checked(lgt):
     for bad in (-1, 16, 48, 128):
         with pytest.raises(lgt.LGTError):
             lat.set_hop_block_sites(bad)
+
+
+def test_32_site_blocks_refused_above_4_gib_of_links(lgt):
+    """The 32-site kernel reads both parities' links through one buffer
+    resource with 32-bit offsets: a lattice whose FP64 gauge field reaches
+    4 GiB (here 40^3 x 120, 4.4 GB of links) must refuse it, and keep the
+    64-site kernel."""
+    import torch
+    lat = lgt.Lattice((40, 40, 40, 120))
+    with pytest.raises(lgt.LGTError):
+        lat.set_hop_block_sites(32)
+    lat.set_hop_block_sites(64)
+    lat.set_hop_block_sites(0)
+    del lat
+    torch.cuda.empty_cache()
