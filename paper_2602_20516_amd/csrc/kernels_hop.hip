@@ -144,10 +144,10 @@ struct EpiResidual {  // r = phi - (self + coef * acc) over both parities, block
 // ---------------------------------------------------------------------------
 // The hop kernel.  Grid: nbp blocks per parity (p_fixed >= 0) or 2*nbp
 // (p_fixed < 0, parity = logical block / nbp).  NS = 64: wave mu computes
-// both hops along mu for 64 sites.  NS = 32 (small lattices, where 64-site
-// blocks leave two waves per SIMD): wave mu computes the forward hop of 32
-// sites on lanes 0-31 and their backward hop on lanes 32-63, so twice as
-// many waves share the latency; waves 0 and 1 then run the epilogue, one
+// both hops along mu for 64 sites.  NS = 32 (small lattices, whose 64-site
+// grid would not give every SIMD a wave): wave mu computes the forward hop
+// of 32 sites on lanes 0-31 and their backward hop on lanes 32-63, so twice
+// as many waves share the latency; waves 0 and 1 then run the epilogue, one
 // (site, spin) pair per lane.
 // ---------------------------------------------------------------------------
 template <typename R, bool DAG, typename Epi, typename In, int NS>
