@@ -556,7 +556,9 @@ def bench_multishift(args):
 def bench_hop_shapes(args):
     """The single-field hop with 32 and with 64 sites per block (lgt_set_hop_block_sites): one
     launch alone (HIP events over 300 launches), and the whole force call (10 calls), at
-    lattice sizes around the automatic switch (32 up to 8192 sites per parity)."""
+    lattice sizes around the automatic switch (32 up to 8192 sites per parity); and the
+    64-site hop in site order and t-fastest (lgt_set_hop_block_order; automatic: t-fastest
+    above 131072 sites per parity)."""
     import torch
 
     import lgt_inputs as li
@@ -586,6 +588,13 @@ def bench_hop_shapes(args):
                     torch.cuda.synchronize()
                     r[f"force_ms_{ns}"] = round(1e3 * (time.perf_counter() - t0) / 10, 3)
                     r[f"force_iters_{ns}"] = st["iters"]
+            # the 64-site kernel in site order (1) and t-fastest (2)
+            lat.set_hop_block_sites(64)
+            for order in (1, 2):
+                lat.set_hop_block_order(order)
+                r[f"hop_us_64_order{order}"] = round(1e3 * lat.hop_benchmark(U, E, prec, 300), 3)
+            lat.set_hop_block_order(0)
+            lat.set_hop_block_sites(0)
             log("bench hop shapes:", json.dumps(r))
             rows.append(r)
         del lat, U, E, phi
@@ -594,7 +603,8 @@ def bench_hop_shapes(args):
             "n_gpus": 1, "higher_is_better": False, "dtype": "f32 / f64",
             "data": "synthetic (seeded SU(3) links eps=0.3, Gaussian eta; phi = D^dag eta, kappa 0.125)",
             "config": {"workload": "one even/odd hop launch (FP32 two-row links / FP64), and the force call "
-                                   "(mixed FP32 / FP64 CG to 1e-10) up to 16^3x32"},
+                                   "(mixed FP32 / FP64 CG to 1e-10) up to 16^3x32; the 64-site hop in both "
+                                   "block orders"},
             "rows": rows}
 
 

@@ -425,6 +425,17 @@ LGT_API lgt_status lgt_hop_benchmark_mrhs(lgt_ctx* ctx, const void* U, const voi
  * on a lattice whose FP64 gauge field is 4 GiB or more (V above 7456540). */
 LGT_API lgt_status lgt_set_hop_block_sites(lgt_ctx* ctx, int32_t sites);
 
+/* Order in which the 64-site hop kernel takes its blocks (see
+ * lgt_set_hop_block_sites): 1 = site order (x fastest); 2 = t-fastest within
+ * groups of 8 (else 4 or 2) t-slices, so that a block's t-neighbours are read
+ * a few blocks apart instead of a whole slice apart, which keeps them in the
+ * L2 of large lattices; 0 (the default) takes 2 above 131072 sites per
+ * parity and 1 below.  Order 2 applies only where a t-slice holds a whole
+ * number of 64-site blocks (Lx Ly Lz / 128 integer), else site order is
+ * used.  Results do not depend on the order except through the summation
+ * order of the kernels' reductions.  INVALID_ARGUMENT for other values. */
+LGT_API lgt_status lgt_set_hop_block_order(lgt_ctx* ctx, int32_t order);
+
 #ifdef __cplusplus
 }
 #endif

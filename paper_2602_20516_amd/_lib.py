@@ -96,6 +96,7 @@ PROTOTYPES = {
                              ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
     "lgt_set_stout_checkpoints": (_st, [_vp, _i]),
     "lgt_set_hop_block_sites": (_st, [_vp, _i]),
+    "lgt_set_hop_block_order": (_st, [_vp, _i]),
     "lgt_stout_last_schedule": (_st, [_vp, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_int64)]),
     "lgt_stout_schedule": (_st, [_i, _i, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "lgt_rational_force_eo": (_st, [_vp, _vp, _vp, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d), _d,

@@ -405,6 +405,10 @@ class Lattice:
         """lgt_set_hop_block_sites: sites per hop block, 32 or 64 (0: by volume)."""
         _check(self.lib, self.ctx, self.lib.lgt_set_hop_block_sites(self.ctx, int(sites)))
 
+    def set_hop_block_order(self, order: int = 0):
+        """lgt_set_hop_block_order: 64-site block order, 1 site order, 2 t-fastest (0: by volume)."""
+        _check(self.lib, self.ctx, self.lib.lgt_set_hop_block_order(self.ctx, int(order)))
+
     def stout_last_schedule(self) -> dict:
         """lgt_stout_last_schedule: levels kept and passes recomputed by the last reverse pass."""
         s, p = ctypes.c_int32(), ctypes.c_int64()

@@ -155,6 +155,7 @@ lgt_status lgt_create(const lgt_geom* geom, void* hip_stream, lgt_ctx** out) {
     c->g.vh = c->vh;
     c->g.bc = geom->fermion_t_bc;
     c->g.hop_ns = 0;
+    c->g.hop_order = 0;
     c->stream = (hipStream_t)hip_stream;
     LGT_HIP(hipGetDevice(&c->device));
     LGT_HIP(hipMalloc(&c->U64, (size_t)72 * c->vh * sizeof(double2)));
@@ -633,6 +634,14 @@ lgt_status lgt_set_hop_block_sites(lgt_ctx* c, int32_t sites) {
     require(sites != 32 || (size_t)72 * c->vh * sizeof(double2) < ((size_t)1 << 32),
             "32-site hop blocks need a gauge field below 4 GiB (V at most 7456540 sites)");
     c->g.hop_ns = sites;
+  });
+}
+
+lgt_status lgt_set_hop_block_order(lgt_ctx* c, int32_t order) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(order == 0 || order == 1 || order == 2, "hop block order must be 0 (automatic), 1 or 2");
+    c->g.hop_order = order;
   });
 }
 

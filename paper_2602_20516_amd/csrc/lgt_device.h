@@ -240,6 +240,7 @@ struct Geom {
   int vh;     // V / 2 (sites per parity)
   int bc;     // fermion temporal boundary sign
   int hop_ns; // sites per hop block: 32 or 64, or 0 to choose by volume
+  int hop_order;  // order of the 64-site blocks: 1 site order, 2 t-fastest groups, 0 by volume
 };
 
 __device__ __forceinline__ void cb_coords(const Geom& g, int p, int cb, int c[4]) {

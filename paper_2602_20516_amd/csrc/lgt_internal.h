@@ -109,6 +109,9 @@ int hop_blocks(const Geom& g, int p_out);
 // Lattices with at most this many sites per parity run the hop with 32
 // sites per block (half-wave hops), larger ones with 64.
 constexpr int kHopHalfWaveMaxVh = 8192;
+// Above this many sites per parity the 64-site hop takes its blocks
+// t-fastest (when a t-slice holds a whole number of blocks).
+constexpr int kHopTOrderMinVh = 131072;
 
 // Reduction capacity needed for a lattice with vh sites per parity: the
 // largest reducing grid is the both-parity hop (2 * ceil(vh/32) blocks at

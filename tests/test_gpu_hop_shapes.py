@@ -1,10 +1,13 @@
-"""Both work shapes of the single-field hop kernel against the oracle.
+"""Both work shapes of the single-field hop kernel, and both orders of the
+64-site blocks, against the oracle.
 
 The hop runs with 64 sites per block (each wave both hops along one
 direction) or 32 (each half-wave one hop), chosen by volume unless the
-context fixes it (lgt_set_hop_block_sites).  Most lattices the oracle handles
-in a test are small enough for the automatic choice to be 32, so this file
-forces each shape on the same inputs: D and D^dag (FP64, 1e-13 as the other
+context fixes it (lgt_set_hop_block_sites); the 64-site blocks run in site
+order or t-fastest in groups of t-slices (lgt_set_hop_block_order), again by
+volume.  The lattices the oracle handles in a test are too small for the
+automatic choice to take the larger shape's t-fastest order, so this file
+forces each kernel configuration on the same inputs: D and D^dag (FP64, 1e-13 as the other
 deterministic maps), the force in all three solver precisions (whose CG
 launches the hop with every epilogue: Schur norm, CG update, residual), and
 the multi-shift solve.  Shapes: a lattice smaller than one block, lattices
@@ -23,10 +26,14 @@ from gpu_common import max_rel_err, rel_err, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
+# (sites per block, order of the 64-site blocks)
+SHAPES = [(32, 0), (64, 1), (64, 2)]
 SITES = [32, 64]
 # sites per parity: 16 (below one block), 432 (ragged for 32 and 64),
-# 1080 (ragged for both), 384 (a whole number of blocks for both)
-DIMS = [(2, 2, 2, 4), (6, 6, 6, 4), (10, 6, 6, 6), (8, 4, 6, 4)]
+# 1080 (ragged for both), 384 (a whole number of blocks for both); then
+# lattices whose t-slices hold whole 64-site blocks, where the 64-site
+# kernel takes its blocks t-fastest in groups of 2, 8 and 4 slices
+DIMS = [(2, 2, 2, 4), (6, 6, 6, 4), (10, 6, 6, 6), (8, 4, 6, 4), (8, 4, 8, 6), (16, 4, 4, 8), (8, 8, 8, 12)]
 
 
 def say(*a):
@@ -41,18 +48,19 @@ def lgt():
     return m
 
 
-def _lattice(lgt, dims, sites):
+def _lattice(lgt, dims, sites, order=0):
     lat = lgt.Lattice(dims)
     lat.set_hop_block_sites(sites)
+    lat.set_hop_block_order(order)
     return lat
 
 
-@pytest.mark.parametrize("sites", SITES)
+@pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("dims", DIMS)
-def test_dslash_both_shapes(lgt, dims, sites):
-    say("dslash", dims, "sites per block", sites)
+def test_dslash_both_shapes(lgt, dims, shape):
+    say("dslash", dims, "sites per block, order", shape)
     u, psi = li.random_links(dims, 0.5, 501), li.gaussian_spinor(dims, 502)
-    lat = _lattice(lgt, dims, sites)
+    lat = _lattice(lgt, dims, *shape)
     U, PSI = to_dev(u), to_dev(psi)
     for dag in (False, True):
         got = to_host(lat.dslash(U, PSI, 0.13, dag))
@@ -80,6 +88,26 @@ def test_force_both_shapes(lgt, precision, gate, sites):
     say("force", precision, "sites per block", sites, "iters", st["iters"], "rel err", e)
     assert st["true_rel_residual"] <= 1e-13
     assert e < gate
+
+
+@functools.lru_cache(maxsize=1)
+def _force_case_ordered():
+    dims = (16, 4, 4, 8)
+    u, eta = li.random_links(dims, 0.5, 541), li.gaussian_spinor(dims, 542)
+    phi = dirac.dslash_dag(u, eta, 0.12)
+    return dims, u, phi, force.fermion_force(u, phi, 0.12, tol=1e-14)
+
+
+@pytest.mark.parametrize("precision,gate", [("fp64", 1e-11), ("mixed_fp32", 1e-9)])
+def test_force_t_fastest_block_order(lgt, precision, gate):
+    """The force with the 64-site kernel on a lattice where it takes its
+    blocks t-fastest (16 x 4 x 4 x 8: two blocks per t-slice, groups of 8
+    slices), so every epilogue of the CG runs under that order."""
+    dims, u, phi, ref = _force_case_ordered()
+    lat = _lattice(lgt, dims, 64, 2)
+    got, st = lat.fermion_force(to_dev(u), to_dev(phi), 0.12, lgt.Params(precision=precision, tol=1e-13))
+    assert st["true_rel_residual"] <= 1e-13
+    assert rel_err(to_host(got), ref) < gate
 
 
 @pytest.mark.parametrize("sites", SITES)
@@ -114,6 +142,9 @@ def test_shapes_agree_and_setting_is_checked(lgt):
     for bad in (-1, 16, 48, 128):
         with pytest.raises(lgt.LGTError):
             lat.set_hop_block_sites(bad)
+    for bad in (-1, 3):
+        with pytest.raises(lgt.LGTError):
+            lat.set_hop_block_order(bad)
 
 
 def test_32_site_blocks_refused_above_4_gib_of_links(lgt):
