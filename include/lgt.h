@@ -126,6 +126,13 @@ typedef struct lgt_solver_params {
                             whose recursion drifts faster; with BF16 storage,
                             values other than the default can cost twice the
                             iterations) */
+  double first_pass_factor; /* the first pass of the solve aims its CG at
+                            first_pass_factor * tol (<= 0: 0.25 where two Schur
+                            solves are chained, 0.5 for one Schur solve), so
+                            that the FP64 true residual usually meets tol
+                            without a correction pass; a pass that misses is
+                            followed by defect-correction passes sized from the
+                            measured miss */
 } lgt_solver_params;
 
 typedef struct lgt_solver_stats {
@@ -133,6 +140,8 @@ typedef struct lgt_solver_stats {
   int32_t reliable_updates; /* FP64 residual recomputations (mixed precision) */
   double true_rel_residual; /* ||phi - D^dag D X|| / ||phi|| in FP64 at exit */
   double ms;                /* wall time of the call on the stream, milliseconds */
+  int32_t corrections;      /* FP64 defect-correction passes after the first solve */
+  int32_t reserved;         /* 0 */
 } lgt_solver_stats;
 
 typedef struct lgt_ctx lgt_ctx;

@@ -35,7 +35,8 @@ class Geom(ctypes.Structure):
 
 class SolverParams(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("even_odd", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("reliable_delta", ctypes.c_double)]
+                ("max_iter", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
+                ("first_pass_factor", ctypes.c_double)]
 
 
 class BatchItem(ctypes.Structure):
@@ -45,11 +46,12 @@ class BatchItem(ctypes.Structure):
 
 class SolverStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
-                ("true_rel_residual", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("true_rel_residual", ctypes.c_double), ("ms", ctypes.c_double),
+                ("corrections", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"iters": self.iters, "reliable_updates": self.reliable_updates,
-                "true_rel_residual": self.true_rel_residual, "ms": self.ms}
+                "true_rel_residual": self.true_rel_residual, "ms": self.ms, "corrections": self.corrections}
 
 
 _vp = ctypes.c_void_p

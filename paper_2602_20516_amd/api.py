@@ -45,10 +45,11 @@ class Params:
     max_iter: int = 20000
     reliable_delta: float = 0.0  # 0: the library's default for the precision
     even_odd: int = 1
+    first_pass_factor: float = 0.0  # 0: the library's default
 
     def to_c(self) -> SolverParams:
         return SolverParams(_PRECISIONS[self.precision], self.even_odd, float(self.tol),
-                            int(self.max_iter), float(self.reliable_delta))
+                            int(self.max_iter), float(self.reliable_delta), float(self.first_pass_factor))
 
 
 def _check(lib, ctx, status: int, stats: Optional[SolverStats] = None):

@@ -60,6 +60,8 @@ SolverOpts parse(const lgt_solver_params* p) {
   // sensitive to delta, and 1e-2 was the best setting at both sizes
   const double dflt = p->precision == LGT_MIXED_BF16 ? 0.01 : 3e-4;
   o.delta = p->reliable_delta > 0.0 && p->reliable_delta < 1.0 ? p->reliable_delta : dflt;
+  require(std::isfinite(p->first_pass_factor), "first_pass_factor must be finite");
+  o.first_pass = p->first_pass_factor > 0.0 ? p->first_pass_factor : 0.0;
   return o;
 }
 
@@ -87,6 +89,8 @@ void fill_stats(lgt_solver_stats* out, const SolveStats& s, double ms) {
   out->reliable_updates = s.reliable;
   out->true_rel_residual = s.true_res;
   out->ms = ms;
+  out->corrections = s.corrections;
+  out->reserved = 0;
 }
 
 struct Timer {
@@ -110,6 +114,7 @@ double gauge_action(lgt_ctx* c, double beta, const double2* links = nullptr) {
 void merge(SolveStats& acc, const SolveStats& s) {
   acc.iters += s.iters;
   acc.reliable += s.reliable;
+  acc.corrections += s.corrections;
   acc.true_res = std::max(acc.true_res, s.true_res);
   acc.converged = acc.converged && s.converged;
 }

@@ -382,9 +382,11 @@ struct BatchSolver {
     std::vector<double> pp(c->host_result, c->host_result + nr);
     for (double v : pp)
       if (!std::isfinite(v)) throw Error(LGT_ERR_NONFINITE, "phi holds NaN or Inf");
-    const double tol_in = o.tol * 0.25;
+    const double tol_in = o.tol * (o.first_pass > 0.0 ? o.first_pass : 0.25);
     solve_M(true, F(bY), phi, tol_in);
     solve_M(false, F(bX), F(bY), tol_in);
+    double tol_used = tol_in;                   // CG tolerance of the last pass
+    std::vector<double> res_start(nr, 1.0);     // each residual when that pass started
     for (int pass = 0;; ++pass) {
       dslash_full(F(bX), F(bY), false);
       HopIn<double> hin{c->U64, F(bY), F(bY) + halfn()};
@@ -392,21 +394,30 @@ struct BatchSolver {
                                          c->stream));
       read_results(nr);
       bool ok = true;
-      double worst = 0.0;  // largest true residual still above the target
+      double tol_corr = 0.5;  // the tightest any right-hand side still above the target needs
+      unsigned finished = 0;  // right-hand sides that take no correction
       for (int k = 0; k < nr; ++k) {
         st[k].true_res = pp[k] > 0.0 ? std::sqrt(c->host_result[k] / pp[k]) : 0.0;
         if (!std::isfinite(st[k].true_res)) throw Error(LGT_ERR_NONFINITE, "non-finite residual");
         const bool done_k = st[k].true_res <= o.tol || !st[k].converged;
         ok = ok && done_k;
-        if (!done_k) worst = std::max(worst, st[k].true_res);
+        if (done_k) finished |= 1u << k;
+        else tol_corr = std::min(tol_corr, correction_tol(o.tol, st[k].true_res, tol_used, res_start[k]));
       }
       if (ok || pass >= 4) break;
-      // a correction only has to shrink each residual by tol / true_res (the
-      // single solve's rule, for the worst right-hand side)
-      const double tol_corr = std::min(0.25, std::max(tol_in, 0.25 * o.tol / worst));
+      // a correction only has to shrink each residual by about tol / true_res
+      // (the single solve's rule, correction_tol); the right-hand sides that
+      // already meet the target get a zero residual, so their CG stops at
+      // once and their solution stays as it is
+      LGT_HIP(launch_mzero_rhs(c->vh, 24, nr, F(bRes), finished, c->stream));
       solve_M(true, F(bYtmp), F(bRes), tol_corr);
       solve_M(false, F(bE), F(bYtmp), tol_corr);
       LGT_HIP(launch_axpy64((int)nfull, 1.0, F(bE), F(bX), c->stream));
+      tol_used = tol_corr;
+      for (int k = 0; k < nr; ++k) {
+        res_start[k] = st[k].true_res;
+        if (!((finished >> k) & 1u)) ++st[k].corrections;
+      }
     }
     for (int k = 0; k < nr; ++k)
       if (st[k].true_res > o.tol) st[k].converged = false;

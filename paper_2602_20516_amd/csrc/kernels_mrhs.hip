@@ -566,6 +566,21 @@ hipError_t launch_mfinalize(int mode, int nblk, int nr, Reduce red, BatchState* 
   return hipGetLastError();
 }
 
+// element (k, n, site) of a multi-RHS field is at (k nr + n) vh + site
+__global__ __launch_bounds__(256) void k_mzero_rhs(size_t tot, int vh, int nr, double2* __restrict__ f,
+                                                   unsigned mask) {
+  const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= tot) return;
+  const int n = (int)((t / (size_t)vh) % (size_t)nr);
+  if ((mask >> n) & 1u) f[t] = make_double2(0.0, 0.0);
+}
+hipError_t launch_mzero_rhs(int vh, int ncomp, int nr, double2* f, unsigned mask, hipStream_t s) {
+  if (!mask) return hipSuccess;
+  const size_t tot = (size_t)ncomp * nr * vh;
+  hipLaunchKernelGGL(k_mzero_rhs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, tot, vh, nr, f, mask);
+  return hipGetLastError();
+}
+
 // canonical spinor [V][4][3] of right-hand side n <-> full multi-RHS field
 __global__ __launch_bounds__(256) void k_mpack(Geom g, int nr, int n, const double2* __restrict__ canon,
                                                double2* __restrict__ packed) {

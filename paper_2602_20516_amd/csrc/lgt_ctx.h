@@ -1,6 +1,8 @@
 // Host-side context: geometry, stream, device workspace, and the solver.
 #pragma once
 
+#include <algorithm>
+
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -33,6 +35,7 @@ struct Error : std::runtime_error {
 struct SolveStats {
   int iters = 0;
   int reliable = 0;
+  int corrections = 0;
   double true_res = 0.0;
   bool converged = true;
 };
@@ -49,7 +52,20 @@ struct SolverOpts {
   double tol = 1e-10;
   int max_iter = 20000;
   double delta = 3e-4;
+  double first_pass = 0.0;  // first-pass CG tolerance / tol (0: the solver's default)
 };
+
+// Tolerance of the next defect-correction pass.  The last pass ran its CG to
+// tol_used relative to the residual it started from (res_start, relative to
+// ||phi||) and left the FP64 true residual true_res, so the solve chain
+// magnified its stopping residual by A = true_res / (tol_used res_start).
+// A pass on r with CG tolerance t leaves about A t true_res; t is chosen to
+// land at half the target.
+inline double correction_tol(double tol, double true_res, double tol_used, double res_start) {
+  const double A = true_res / (tol_used * res_start);
+  const double t = 0.5 * tol / (A * true_res);
+  return std::min(0.5, std::max(t, 1e-15));
+}
 
 }  // namespace lgt
 

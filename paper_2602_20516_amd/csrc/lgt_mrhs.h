@@ -56,6 +56,8 @@ hipError_t launch_mrescale(int vh, int nr, const double2* r64, const double* sig
                            const int* restart, const double* pscale, hipStream_t s);
 hipError_t launch_mcg_init64(int vh, int nr, const double2* b, double2* r, double2* p, double2* x,
                              BatchState* st, Reduce red, double tol, int max_iter, hipStream_t s);
+// zero right-hand side n of a multi-RHS FP64 field of ncomp components for every bit n of mask
+hipError_t launch_mzero_rhs(int vh, int ncomp, int nr, double2* f, unsigned mask, hipStream_t s);
 hipError_t launch_mpack(const Geom& g, int nr, int n, const double2* canon, double2* packed, hipStream_t s);
 hipError_t launch_munpack(const Geom& g, int nr, int n, const double2* packed, double2* canon, hipStream_t s);
 

@@ -293,12 +293,13 @@ SolveStats lgt_ctx::solve_ddagd(const double2* phi, double2* X, double2* Y, cons
   }
   // inner tolerance: the two Schur solves and D^dag D compound their
   // residuals, so each aims a little below the requested true residual
-  const double tol_in = o.tol * 0.25;
+  const double tol_in = o.tol * (o.first_pass > 0.0 ? o.first_pass : 0.25);
   solve_M(true, Y, phi, tol_in, o.max_iter, o.precision, o.delta, st);
   solve_M(false, X, Y, tol_in, o.max_iter, o.precision, o.delta, st);
   double2* r = f64(kRes);
   HopIn<double> hin{U64, nullptr, nullptr};
   const size_t h = half_elems();
+  double tol_used = tol_in, res_start = 1.0;  // the last pass's CG tolerance and starting residual
   for (int pass = 0;; ++pass) {
     dslash_full(X, Y, kappa, false);
     hin.in_even = Y;
@@ -308,16 +309,20 @@ SolveStats lgt_ctx::solve_ddagd(const double2* phi, double2* X, double2* Y, cons
     st.true_res = std::sqrt(host_result[0] / pp);
     if (!std::isfinite(st.true_res)) throw Error(LGT_ERR_NONFINITE, "non-finite residual");
     if (st.true_res <= o.tol || !st.converged || pass >= 4) break;
-    // defect correction: D^dag D e = r, X += e.  r only has to shrink by the
-    // factor tol / true_res (with the first pass's margin), not by tol: a
-    // pass that missed the target by 2x needs a few iterations, not a full
-    // solve that would overshoot to ~tol^2
-    const double tol_corr = std::min(0.25, std::max(tol_in, 0.25 * o.tol / st.true_res));
+    // defect correction: D^dag D e = r, X += e.  r only has to shrink by
+    // about tol / true_res, not by tol (a pass that missed the target by 2x
+    // needs a few iterations, not a full solve that would overshoot to
+    // ~tol^2); the CG tolerance of the pass also divides out the
+    // magnification the last pass showed (correction_tol)
+    const double tol_corr = correction_tol(o.tol, st.true_res, tol_used, res_start);
+    tol_used = tol_corr;
+    res_start = st.true_res;
     double2* ytmp = f64(kYtmp);
     double2* e = f64(kE);
     solve_M(true, ytmp, r, tol_corr, o.max_iter, o.precision, o.delta, st);
     solve_M(false, e, ytmp, tol_corr, o.max_iter, o.precision, o.delta, st);
     LGT_HIP(launch_axpy64(nf, 1.0, e, X, stream));
+    ++st.corrections;
   }
   if (st.true_res > o.tol) st.converged = false;
   return st;
@@ -355,7 +360,7 @@ SolveStats lgt_ctx::solve_eo(const double2* phi, double2* X, double2* A, const S
     st.true_res = 0.0;
     return st;
   }
-  const double tol_in = o.tol * 0.5;
+  const double tol_in = o.tol * (o.first_pass > 0.0 ? o.first_pass : 0.5);
   auto schur_solve = [&](double2* z, const double2* rhs, double t) {
     const int code = o.precision == LGT_MIXED_FP32   ? cg_normal_mixed<float2>(false, z, rhs, t, o.max_iter,
                                                                              o.delta, st)
@@ -368,6 +373,7 @@ SolveStats lgt_ctx::solve_eo(const double2* phi, double2* X, double2* A, const S
   schur_solve(xo, phio, tol_in);
   double2* r = f64(kRes) + h;
   double2* e = f64(kE) + h;
+  double tol_used = tol_in, res_start = 1.0;
   for (int pass = 0;; ++pass) {
     apply_mhat_dag_mhat64(false, xo, r);
     LGT_HIP(launch_xmy64(n, phio, r, stream));  // r = phi_o - Mhat^dag Mhat X_o
@@ -376,9 +382,13 @@ SolveStats lgt_ctx::solve_eo(const double2* phi, double2* X, double2* A, const S
     st.true_res = std::sqrt(host_result[0] / pp);
     if (!std::isfinite(st.true_res)) throw Error(LGT_ERR_NONFINITE, "non-finite residual");
     if (st.true_res <= o.tol || !st.converged || pass >= 4) break;
-    // a correction only has to shrink r by tol / true_res (as in solve_ddagd)
-    schur_solve(e, r, std::min(0.5, std::max(tol_in, 0.5 * o.tol / st.true_res)));
+    // a correction only has to shrink r by about tol / true_res (as in solve_ddagd)
+    const double tol_corr = correction_tol(o.tol, st.true_res, tol_used, res_start);
+    tol_used = tol_corr;
+    res_start = st.true_res;
+    schur_solve(e, r, tol_corr);
     LGT_HIP(launch_axpy64(n, 1.0, e, xo, stream));
+    ++st.corrections;
   }
   if (st.true_res > o.tol) st.converged = false;
   const double k2 = -kappa * kappa;

@@ -1,14 +1,15 @@
-"""Write the stored expected values of the 16^4 workload, from the oracle only.
+"""Write the stored expected values of a full-size workload, from the oracle only.
 
-The 16^4 lattice (eps = 0.3 links, beta = 6.0, kappa = 0.125, pseudofermion
-phi = D^dag eta) is too slow for the NumPy oracle inside a test (an
-unpreconditioned CG takes minutes), so this script solves it once, tightly,
-and stores: the actions, the fermion and gauge forces on a seeded sample of
-links (every 16th site class plus all boundary-crossing t-links of one
-column), and norms of the full force fields.  Only ``oracle`` and the input
-generator are used.
+The 16^4 lattice (eps = 0.3 links, beta = 6.0, kappa = 0.125) and the
+24^3x48 lattice (eps = 0.2, beta = 6.0, kappa = 0.13), each with the
+pseudofermion phi = D^dag eta, are too slow for the NumPy oracle inside a
+test (an unpreconditioned CG takes minutes to hours), so this script solves
+each once, tightly, and stores: the actions, the fermion and gauge forces on
+a seeded sample of links (random site classes plus boundary-crossing t-links
+of one column), and norms of the full force fields.  Only ``oracle`` and the
+input generator are used.
 
-Usage:  python tests/golden/make_golden.py  [--tol 1e-13]
+Usage:  python tests/golden/make_golden.py  [--config 2|3] [--tol 1e-15]
 """
 from __future__ import annotations
 
@@ -44,10 +45,11 @@ def sample_links(dims, n=96, seed=7):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--tol", type=float, default=1e-13)
-    ap.add_argument("--out", default=os.path.join(HERE, "c2_16x16x16x16.json"))
+    ap.add_argument("--config", type=int, default=2, choices=(2, 3))
+    ap.add_argument("--tol", type=float, default=1e-15)
+    ap.add_argument("--out", default=None)
     args = ap.parse_args()
-    c = li.config(2)
+    c = li.config(args.config)
     dims, eps, beta, k = c["dims"], c["eps"], c["beta"], c["kappa"]
     t0 = time.time()
     u = li.random_links(dims, eps, c["seeds"]["links"])
@@ -60,9 +62,11 @@ def main():
     sf = float(np.real(np.vdot(phi.ravel(), chi.ravel())))
     sg = action.gauge_action(u, beta)
     links = sample_links(dims)
+    name = "x".join(str(d) for d in dims)
+    out = args.out or os.path.join(HERE, f"c{args.config}_{name}.json")
     rec = {
-        "what": "16^4 workload (eps 0.3 links seed 201, eta seed 202, beta 6.0, kappa 0.125, antiperiodic t), "
-                "oracle values",
+        "what": f"{name} workload (eps {eps} links seed {c['seeds']['links']}, eta seed {c['seeds']['eta']}, "
+                f"beta {beta}, kappa {k}, antiperiodic t), oracle values",
         "writer": "tests/golden/make_golden.py (oracle only)",
         "dims": list(dims), "eps": eps, "beta": beta, "kappa": k, "fermion_bc": -1,
         "seeds": c["seeds"], "oracle_tol": args.tol, "oracle_iters": iters, "oracle_true_residual": res,
@@ -74,9 +78,9 @@ def main():
         "F_gauge": [[[float(v.real), float(v.imag)] for v in fg[l].ravel()] for l in links],
         "X_samples": [[[float(v.real), float(v.imag)] for v in chi[l[:4]].ravel()] for l in links[:16]],
     }
-    with open(args.out, "w") as f:
+    with open(out, "w") as f:
         json.dump(rec, f, indent=0)
-    print(f"wrote {args.out} in {time.time() - t0:.0f} s", flush=True)
+    print(f"wrote {out} in {time.time() - t0:.0f} s", flush=True)
 
 
 if __name__ == "__main__":

@@ -37,16 +37,18 @@ def test_struct_layout_matches_c(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "lgt.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(lgt_geom),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(lgt_geom),"
         " sizeof(lgt_solver_params), offsetof(lgt_solver_params, tol),"
         " offsetof(lgt_solver_params, reliable_delta), sizeof(lgt_solver_stats),"
-        " offsetof(lgt_solver_stats, true_rel_residual), offsetof(lgt_solver_stats, ms));return 0;}\n")
+        " offsetof(lgt_solver_stats, true_rel_residual), offsetof(lgt_solver_stats, ms),"
+        " offsetof(lgt_solver_params, first_pass_factor), offsetof(lgt_solver_stats, corrections));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert out == [ctypes.sizeof(_lib.Geom), ctypes.sizeof(_lib.SolverParams), _lib.SolverParams.tol.offset,
                    _lib.SolverParams.reliable_delta.offset, ctypes.sizeof(_lib.SolverStats),
-                   _lib.SolverStats.true_rel_residual.offset, _lib.SolverStats.ms.offset]
+                   _lib.SolverStats.true_rel_residual.offset, _lib.SolverStats.ms.offset,
+                   _lib.SolverParams.first_pass_factor.offset, _lib.SolverStats.corrections.offset]
 
 
 @pytest.mark.parametrize("dims,bc", [((4, 4, 3, 4), -1), ((0, 4, 4, 4), -1), ((4, 4, 4, 4), 0),

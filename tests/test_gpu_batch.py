@@ -35,23 +35,24 @@ def workload(dims, seeds=(402, 403)):
     return u, items
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
-def test_batch_vs_oracle_4x4(lgt, precision):
+@pytest.mark.parametrize("precision,tol,gate", [("fp64", 1e-14, 1e-12), ("mixed_fp32", 1e-14, 1e-12),
+                                                ("mixed_fp32", 1e-11, 1e-9)])
+def test_batch_vs_oracle_4x4(lgt, precision, tol, gate, margin):
     dims = (4, 4, 4, 4)
     u, items = workload(dims)
     phis = [dirac.dslash_dag(u, eta, k) for k, eta in items]
     lat = lgt.Lattice(dims)
     Xs, Ys, st = lat.cg_solve_batch(to_dev(u), [to_dev(p) for p in phis], [k for k, _ in items],
-                                    lgt.Params(precision=precision, tol=1e-12))
+                                    lgt.Params(precision=precision, tol=tol))
     say("batch", precision, [s["iters"] for s in st], max(s["true_rel_residual"] for s in st))
     for (k, eta), phi, X, Y, s in zip(items, phis, Xs, Ys, st):
-        assert s["true_rel_residual"] <= 1e-12
-        x_ref, y_ref, _, _ = solver.solve_ddag_d(u, phi, k, tol=1e-14)
-        assert rel_err(to_host(X), x_ref) < 1e-9
-        assert rel_err(to_host(Y), eta) < 1e-9
+        assert s["true_rel_residual"] <= tol
+        x_ref, y_ref, _, _ = solver.solve_ddag_d(u, phi, k, tol=1e-15)
+        margin(f"batched X vs oracle, kappa {k} ({precision}, tol {tol:g})", rel_err(to_host(X), x_ref), gate)
+        margin(f"batched Y vs eta, kappa {k} ({precision}, tol {tol:g})", rel_err(to_host(Y), eta), gate)
 
 
-def test_batch_ragged_and_small(lgt):
+def test_batch_ragged_and_small(lgt, margin):
     """Ragged tail (V/2 * nr not a multiple of 64), a batch of one, and five items."""
     for dims, n in (((6, 6, 6, 6), 5), ((2, 2, 2, 4), 1), ((6, 4, 4, 8), 7)):
         u, items = workload(dims)
@@ -62,11 +63,11 @@ def test_batch_ragged_and_small(lgt):
                                         lgt.Params(tol=1e-12))
         for (k, eta), Y, s in zip(items, Ys, st):
             assert s["true_rel_residual"] <= 1e-12
-            assert rel_err(to_host(Y), eta) < 1e-9
+            margin("rel_err(to_host(Y), eta)", rel_err(to_host(Y), eta), 1e-9)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
-def test_batch_matches_single_solves_16(lgt, precision):
+def test_batch_matches_single_solves_16(lgt, precision, margin):
     """16^4 with the 12 right-hand sides: each item equals its own single solve."""
     import torch
     dims = (16, 16, 16, 16)
@@ -82,8 +83,8 @@ def test_batch_matches_single_solves_16(lgt, precision):
         k = items[i][0]
         X1, Y1, s1 = lat.cg_solve(U, phis[i], k, prm)
         assert st[i]["true_rel_residual"] <= 1e-10
-        assert rel_err(to_host(Xs[i]), to_host(X1)) < 1e-8
-        assert rel_err(to_host(Ys[i]), items[i][1]) < 1e-8
+        margin("rel_err(to_host(Xs[i]), to_host(X1))", rel_err(to_host(Xs[i]), to_host(X1)), 1e-8)
+        margin("rel_err(to_host(Ys[i]), items[i][1])", rel_err(to_host(Ys[i]), items[i][1]), 1e-8)
 
 
 def test_batch_rejects_bf16_storage(lgt):
@@ -96,7 +97,7 @@ def test_batch_rejects_bf16_storage(lgt):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
-def test_batch_with_systems_that_stop_at_once(lgt, precision):
+def test_batch_with_systems_that_stop_at_once(lgt, precision, margin):
     """A zero right-hand side (stopped before the first iteration) and kappa = 0
     (D = 1: converged after one) in the same group as systems that run on: the
     batched hop skips the stopped ones, which keep their exact answers
@@ -115,7 +116,7 @@ def test_batch_with_systems_that_stop_at_once(lgt, precision):
     assert st[2]["iters"] == 0
     # D = 1: the true residual is phi - X itself
     assert st[1]["true_rel_residual"] <= 1e-12
-    assert rel_err(to_host(Xs[1]), etas[1]) < 2e-12 and rel_err(to_host(Ys[1]), etas[1]) < 2e-12
+    margin("rel_err(to_host(Xs[1]), etas[1]) < 2e-12 and rel_err(to_host(Ys[1]), etas[1])", rel_err(to_host(Xs[1]), etas[1]) < 2e-12 and rel_err(to_host(Ys[1]), etas[1]), 2e-12)
     if precision == "fp64":
         # (a mixed batch counts a system's iterations up to the reliable update
         # that verifies it, and a stopped system waits for the batch's update)
@@ -123,5 +124,5 @@ def test_batch_with_systems_that_stop_at_once(lgt, precision):
     for i, eta in ((0, etas[0]), (3, etas[2])):
         assert st[i]["true_rel_residual"] <= 1e-12
         x_ref, _, _, _ = solver.solve_ddag_d(u, phis[i], kappas[i], tol=1e-14)
-        assert rel_err(to_host(Xs[i]), x_ref) < 1e-9
-        assert rel_err(to_host(Ys[i]), eta) < 1e-9
+        margin("rel_err(to_host(Xs[i]), x_ref)", rel_err(to_host(Xs[i]), x_ref), 1e-9)
+        margin("rel_err(to_host(Ys[i]), eta)", rel_err(to_host(Ys[i]), eta), 1e-9)

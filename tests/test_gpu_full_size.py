@@ -1,10 +1,20 @@
-"""GPU parity at the 16^4 benchmark size, in the launch configuration bench.py times.
+"""GPU parity at the 16^4 and 24^3x48 workload sizes, in the launch
+configuration bench.py times.
 
-The oracle cannot solve 16^4 inside a test, so the expected values come from
-tests/golden/c2_16x16x16x16.json (written by tests/golden/make_golden.py from
-the oracle alone, solved to a true residual of 1e-13).  Deterministic maps
-(D, the staple force, the bilinear adjoint) are compared on the whole lattice
+The oracle cannot solve these lattices inside a test, so the expected values
+come from tests/golden/c2_16x16x16x16.json (oracle solved to a recursive
+residual of 1e-15) and tests/golden/c3_24x24x24x48.json (1e-14), written by
+tests/golden/make_golden.py from the oracle alone.  Deterministic maps (D, the
+staple force, the bilinear adjoint) are compared on the whole 16^4 lattice
 against the oracle run here.
+
+Force gates (relative Frobenius error over the sampled links, and of the
+full-field norm; the link-level measure of Sec. III A, eq. 9):
+* FP64 path, and mixed precision driven to the same FP64 true residual
+  (1e-14): 1e-12;
+* mixed precision at an outer tolerance of 1e-11: 1e-9.  At the workloads'
+  own tolerance of 1e-10 the solver error alone is about 1e-9 (FP64 and
+  mixed alike), so that case is recorded against 1e-8.
 """
 import json
 import os
@@ -21,6 +31,7 @@ from gpu_common import link_errors, rel_err, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c2_16x16x16x16.json")
+GOLDEN3 = os.path.join(os.path.dirname(__file__), "golden", "c3_24x24x24x48.json")
 
 
 def say(*a):
@@ -51,55 +62,99 @@ def sample(field, links):
     return np.stack([field[l] for l in links])
 
 
-def test_heat_bath_and_actions(c2):
+def test_heat_bath_and_actions(c2, margin):
     g, lat = c2["gold"], c2["lat"]
     phi_ref = dirac.dslash_dag(c2["u"], c2["eta"], g["kappa"])
-    assert rel_err(to_host(c2["phi"]), phi_ref) < 1e-14
+    margin("rel_err(to_host(c2['phi']), phi_ref)", rel_err(to_host(c2["phi"]), phi_ref), 1e-14)
     lgt = c2["lgt"]
     sg, sf, st = lat.action(c2["U"], c2["phi"], g["beta"], g["kappa"], lgt.Params(tol=1e-10))
     say("16^4 action", sg, sf, st)
-    assert abs(sg - g["S_G"]) / g["S_G"] < 1e-13
+    margin("abs(sg - g['S_G']) / g['S_G']", abs(sg - g["S_G"]) / g["S_G"], 1e-13)
     # variational S_f is second order in the solver error: the tolerance-1e-10
     # solve already gives the exact value to ~1e-15
-    assert abs(sf - g["S_F"]) / g["S_F"] < 1e-12
-    assert abs(sf - g["eta_norm2"]) / g["eta_norm2"] < 1e-12
+    margin("abs(sf - g['S_F']) / g['S_F']", abs(sf - g["S_F"]) / g["S_F"], 1e-12)
+    margin("abs(sf - g['eta_norm2']) / g['eta_norm2']", abs(sf - g["eta_norm2"]) / g["eta_norm2"], 1e-12)
 
 
-def test_gauge_force_full(c2):
+def test_gauge_force_full(c2, margin):
     g = c2["gold"]
     got = to_host(c2["lat"].gauge_force(c2["U"], g["beta"]))
-    assert rel_err(sample(got, c2["links"]), c2["fg"]) < 1e-13
-    assert abs(np.linalg.norm(got.ravel()) - g["F_gauge_fro"]) / g["F_gauge_fro"] < 1e-13
+    margin("rel_err(sample(got, c2['links']), c2['fg'])", rel_err(sample(got, c2["links"]), c2["fg"]), 1e-13)
+    margin("abs(np.linalg.norm(got.ravel()) - g['F_gauge_fro']) / g['F_gauge_fro']", abs(np.linalg.norm(got.ravel()) - g["F_gauge_fro"]) / g["F_gauge_fro"], 1e-13)
     ref = force.gauge_force(c2["u"], g["beta"])
-    assert rel_err(got, ref) < 1e-13
+    margin("rel_err(got, ref)", rel_err(got, ref), 1e-13)
 
 
-def test_bilinear_adjoint_full(c2):
+def test_bilinear_adjoint_full(c2, margin):
     """The adjoint kernel on the full 16^4 lattice for given spinors (no solve)."""
     g = c2["gold"]
     a = li.gaussian_spinor(tuple(g["dims"]), 901)
     b = li.gaussian_spinor(tuple(g["dims"]), 902)
     got = to_host(c2["lat"].bilinear_force(c2["U"], to_dev(a), to_dev(b), g["kappa"], -2.0))
     ref = force.force_from_grad(c2["u"], -2.0 * force.bilinear_grad(c2["u"], a, b, g["kappa"]))
-    assert rel_err(got, ref) < 1e-13
+    margin("rel_err(got, ref)", rel_err(got, ref), 1e-13)
 
 
-@pytest.mark.parametrize("precision,tol,gate", [
-    ("fp64", 1e-13, 1e-11),        # both sides solved to 1e-13: the gate of the FP64 path
-    ("mixed_fp32", 1e-13, 1e-11),  # mixed precision reaches the same FP64 residual
-    ("fp64", 1e-10, 1e-8),         # at the workload's own tolerance (solver-limited, reported)
+FORCE_CASES = [
+    ("fp64", 1e-14, 1e-12),        # both sides solved far below the gate: the FP64 bar
+    ("mixed_fp32", 1e-14, 1e-12),  # mixed precision driven to the same FP64 true residual
+    ("mixed_fp32", 1e-11, 1e-9),   # the mixed bar, at the tolerance that meets it
+    ("mixed_bf16", 1e-11, 1e-9),   # BF16-stored inner spinors, same outer tolerance
+    ("fp64", 1e-10, 1e-8),         # the workload's own tolerance (solver-limited, recorded)
     ("mixed_fp32", 1e-10, 1e-8),
-    ("mixed_bf16", 1e-13, 1e-11),  # BF16-stored inner spinors: same FP64 residual, same gate
-])
-def test_fermion_force_vs_stored_oracle(c2, precision, tol, gate):
-    g, lgt = c2["gold"], c2["lgt"]
-    out, st = c2["lat"].fermion_force(c2["U"], c2["phi"], g["kappa"], lgt.Params(precision=precision, tol=tol))
+]
+
+
+def check_force(lat, U, phi, kappa, gold, links, ref, lgt, precision, tol, gate, margin, tag):
+    out, st = lat.fermion_force(U, phi, kappa, lgt.Params(precision=precision, tol=tol))
     got = to_host(out)
-    s = sample(got, c2["links"])
-    err = rel_err(s, c2["ff"])
-    norm_err = abs(np.linalg.norm(got.ravel()) - g["F_fermion_fro"]) / g["F_fermion_fro"]
-    say(f"16^4 force {precision} tol {tol}: sample rel err {err:.3e}, per-link (median, 99%, max) "
-        f"{link_errors(s, c2['ff'])}, norm err {norm_err:.2e}, stats {st}")
+    s = sample(got, links)
+    err = rel_err(s, ref)
+    norm_err = abs(np.linalg.norm(got.ravel()) - gold["F_fermion_fro"]) / gold["F_fermion_fro"]
+    say(f"{tag} force {precision} tol {tol}: sample rel err {err:.3e}, per-link (median, 99%, max) "
+        f"{link_errors(s, ref)}, norm err {norm_err:.2e}, stats {st}")
     assert st["true_rel_residual"] <= tol
-    assert err < gate
-    assert norm_err < gate
+    margin(f"{tag} {precision} tol {tol:g}: sampled force vs oracle", err, gate)
+    margin(f"{tag} {precision} tol {tol:g}: force norm vs oracle", norm_err, gate)
+
+
+@pytest.mark.parametrize("precision,tol,gate", FORCE_CASES)
+def test_fermion_force_vs_stored_oracle(c2, precision, tol, gate, margin):
+    g = c2["gold"]
+    check_force(c2["lat"], c2["U"], c2["phi"], g["kappa"], g, c2["links"], c2["ff"], c2["lgt"], precision, tol, gate,
+                margin, "16^4")
+
+
+@pytest.fixture(scope="module")
+def c3():
+    import paper_2602_20516_amd as lgt
+    if not os.path.exists(GOLDEN3):
+        pytest.skip("no stored oracle values for 24^3x48")
+    with open(GOLDEN3) as f:
+        gold = json.load(f)
+    dims = tuple(gold["dims"])
+    u = li.random_links(dims, gold["eps"], gold["seeds"]["links"])
+    eta = li.gaussian_spinor(dims, gold["seeds"]["eta"])
+    lat = lgt.Lattice(dims)
+    U, E = to_dev(u), to_dev(eta)
+    phi = lat.dslash(U, E, gold["kappa"], dagger=True)
+    links = [tuple(l) for l in gold["links"]]
+    ff = np.array([[complex(*v) for v in m] for m in gold["F_fermion"]]).reshape(-1, 3, 3)
+    fg = np.array([[complex(*v) for v in m] for m in gold["F_gauge"]]).reshape(-1, 3, 3)
+    return dict(lgt=lgt, gold=gold, lat=lat, U=U, phi=phi, links=links, ff=ff, fg=fg)
+
+
+def test_c3_actions_and_gauge_force(c3, margin):
+    g, lat, lgt = c3["gold"], c3["lat"], c3["lgt"]
+    sg, sf, st = lat.action(c3["U"], c3["phi"], g["beta"], g["kappa"], lgt.Params(tol=1e-10))
+    margin("24^3x48 S_G vs oracle", abs(sg - g["S_G"]) / g["S_G"], 1e-13)
+    margin("24^3x48 S_F vs oracle", abs(sf - g["S_F"]) / g["S_F"], 1e-12)
+    got = to_host(lat.gauge_force(c3["U"], g["beta"]))
+    margin("24^3x48 sampled gauge force vs oracle", rel_err(sample(got, c3["links"]), c3["fg"]), 1e-13)
+
+
+@pytest.mark.parametrize("precision,tol,gate", FORCE_CASES)
+def test_c3_fermion_force_vs_stored_oracle(c3, precision, tol, gate, margin):
+    g = c3["gold"]
+    check_force(c3["lat"], c3["U"], c3["phi"], g["kappa"], g, c3["links"], c3["ff"], c3["lgt"], precision, tol, gate,
+                margin, "24^3x48")

@@ -31,7 +31,7 @@ def lgt():
 
 
 @pytest.mark.parametrize("dims,nlev", [((4, 4, 4, 4), 6), ((2, 2, 2, 4), 40)])
-def test_backprop_every_schedule_same_bits(lgt, dims, nlev):
+def test_backprop_every_schedule_same_bits(lgt, dims, nlev, margin):
     u = li.random_links(dims, 0.5, 31)
     gt = li.random_links(dims, 1.0, 32) + 0.3 * li.random_links(dims, 1.0, 33)
     lat = lgt.Lattice(dims)
@@ -48,10 +48,10 @@ def test_backprop_every_schedule_same_bits(lgt, dims, nlev):
         assert np.array_equal(g, outs[0]), cap
     ref = stout.stout_vjp(u, gt, RHO, nlev)
     say("deep backprop", dims, nlev, rel_err(outs[-1], ref))
-    assert rel_err(outs[-1], ref) < 1e-12
+    margin("rel_err(outs[-1], ref)", rel_err(outs[-1], ref), 1e-12)
 
 
-def test_stout_at_full_block_size(lgt):
+def test_stout_at_full_block_size(lgt, margin):
     """8^4: 32 full 64-site blocks per parity (the small lattices fill one
     block partially); forward and reverse against the oracle."""
     dims = (8, 8, 8, 8)
@@ -59,12 +59,12 @@ def test_stout_at_full_block_size(lgt):
     gt = li.random_links(dims, 1.0, 72)
     lat = lgt.Lattice(dims)
     U = to_dev(u)
-    assert rel_err(to_host(lat.stout_smear(U, RHO, 2)), stout.stout(u, RHO, 2)) < 1e-13
+    margin("rel_err(to_host(lat.stout_smear(U, RHO, 2)), stout.stout(u, RHO, 2))", rel_err(to_host(lat.stout_smear(U, RHO, 2)), stout.stout(u, RHO, 2)), 1e-13)
     got = to_host(lat.stout_backprop(U, to_dev(gt), RHO, 2))
-    assert rel_err(got, stout.stout_vjp(u, gt, RHO, 2)) < 1e-12
+    margin("rel_err(got, stout.stout_vjp(u, gt, RHO, 2))", rel_err(got, stout.stout_vjp(u, gt, RHO, 2)), 1e-12)
 
 
-def test_deep_smeared_force_vs_oracle(lgt):
+def test_deep_smeared_force_vs_oracle(lgt, margin):
     dims = (4, 4, 4, 4)
     nlev = 6
     u, eta = li.random_links(dims, 0.5, 41), li.gaussian_spinor(dims, 42)
@@ -83,7 +83,7 @@ def test_deep_smeared_force_vs_oracle(lgt):
             lgt.stout_schedule(nlev, nlev - 1 if cap < 0 else cap)["recompute_passes"]
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
     say("deep smeared force", rel_err(outs[-1], ref))
-    assert rel_err(outs[-1], ref) < 1e-10
+    margin("rel_err(outs[-1], ref)", rel_err(outs[-1], ref), 1e-10)
 
 
 def test_deep_trajectory_schedule_independent(lgt):
@@ -104,7 +104,7 @@ def test_deep_trajectory_schedule_independent(lgt):
     assert res[0][2] == res[1][2]
 
 
-def test_checkpoint_arguments(lgt):
+def test_checkpoint_arguments(lgt, margin):
     lat = lgt.Lattice((4, 4, 4, 4))
     with pytest.raises(lgt.LGTError):
         lat.set_stout_checkpoints(-2)
@@ -113,4 +113,4 @@ def test_checkpoint_arguments(lgt):
         lat.stout_smear(U, RHO, 257)
     lat.set_stout_checkpoints(3)
     out = lat.stout_smear(U, RHO, 2)  # the context still works
-    assert rel_err(to_host(out), stout.stout(to_host(U), RHO, 2)) < 1e-13
+    margin("rel_err(to_host(out), stout.stout(to_host(U), RHO, 2))", rel_err(to_host(out), stout.stout(to_host(U), RHO, 2)), 1e-13)
