@@ -160,7 +160,8 @@ LGT_API lgt_status lgt_destroy(lgt_ctx* ctx);
 
 /* Message describing the last failing call on ctx ("" if none).  The
  * pointer stays valid until the next call on ctx.  ctx == NULL gives the
- * message of the last failing lgt_create. */
+ * message of the last failing call that takes no context (lgt_create,
+ * lgt_dslash_noalloc). */
 LGT_API const char* lgt_last_error(const lgt_ctx* ctx);
 
 /* Rebind the context to another HIP stream (NULL = default stream). */
@@ -174,6 +175,23 @@ LGT_API int64_t lgt_volume(const lgt_ctx* ctx);
  * U: gauge field; in, out: spinors; kappa: hopping parameter. */
 LGT_API lgt_status lgt_dslash(lgt_ctx* ctx, const void* U, const void* in, void* out,
                       double kappa, int32_t dagger);
+
+/* lgt_dslash for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same operator, kernels and results, with no context and no allocation.
+ * geom: the lattice (as lgt_create); hip_stream: the stream the work is
+ * enqueued on (NULL = default stream); U, in, out, kappa, dagger as
+ * lgt_dslash (device pointers, canonical layouts).  Working storage (packed
+ * links and spinors, 960 bytes per site) is a device array built into the
+ * library, one copy per GPU, held until the process ends; it limits the
+ * lattice to V <= 65536 sites (16^4).  Every call on one GPU uses that GPU's
+ * copy: calls that overlap in time on one GPU (different streams or threads)
+ * race, calls ordered on one stream do not.  Returns once the work is
+ * enqueued; no NaN/Inf check of the inputs (non-finite values reach out).
+ * Errors: INVALID_ARGUMENT (null pointer, odd or < 2 extent, bc not +-1,
+ * non-finite kappa, V > 65536), DEVICE; message via lgt_last_error(NULL). */
+LGT_API lgt_status lgt_dslash_noalloc(const lgt_geom* geom, void* hip_stream, const void* U, const void* in,
+                                      void* out, double kappa, int32_t dagger);
 
 /* Solve (D^dag D) X = phi (eq. S3.5) and return Y = D X (the paper's
  * eta = D chi below eq. S3.10).  The solve is not differentiated (S3,

@@ -11,6 +11,7 @@ _lib.load()
 
 from .api import (Lattice, LGTError, LGTNonFinite, LGTNotConverged, Params,  # noqa: E402
                   lgt_action, lgt_bilinear_force, lgt_cg_solve, lgt_cg_solve_batch, lgt_create, lgt_dslash,
+                  lgt_dslash_noalloc,
                   lgt_fermion_force, lgt_gauge_force, lgt_hop_benchmark, lgt_hop_benchmark_mrhs, lgt_kinetic,
                   lgt_link_update,
                   lgt_md_step, lgt_md_step_eo, lgt_md_step_smeared, lgt_md_step_sw, lgt_schur_dslash,
@@ -20,7 +21,7 @@ from .autograd import LatticeAction, lattice_action  # noqa: E402
 
 __all__ = [
     "Lattice", "Params", "LGTError", "LGTNotConverged", "LGTNonFinite", "lgt_cg_solve_batch",
-    "lgt_create", "lgt_dslash", "lgt_cg_solve", "lgt_action", "lgt_fermion_force",
+    "lgt_create", "lgt_dslash", "lgt_dslash_noalloc", "lgt_cg_solve", "lgt_action", "lgt_fermion_force",
     "lgt_bilinear_force", "lgt_gauge_force", "lgt_link_update", "lgt_kinetic", "lgt_md_step",
     "lgt_hop_benchmark", "lgt_hop_benchmark_mrhs", "lgt_stout_smear", "lgt_stout_backprop", "lgt_smeared_force", "lgt_md_step_smeared", "lgt_md_step_sw",
     "lgt_schur_dslash", "lgt_fermion_force_eo", "lgt_md_step_eo", "lgt_cg_solve_multishift", "lgt_rational_force_eo", "stout_schedule",

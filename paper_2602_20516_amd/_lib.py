@@ -67,6 +67,7 @@ PROTOTYPES = {
     "lgt_set_stream": (_st, [_vp, _vp]),
     "lgt_volume": (ctypes.c_int64, [_vp]),
     "lgt_dslash": (_st, [_vp, _vp, _vp, _vp, _d, _i]),
+    "lgt_dslash_noalloc": (_st, [ctypes.POINTER(Geom), _vp, _vp, _vp, _vp, _d, _i]),
     "lgt_cg_solve": (_st, [_vp, _vp, _vp, _vp, _vp, _d, ctypes.POINTER(SolverParams),
                            ctypes.POINTER(SolverStats)]),
     "lgt_action": (_st, [_vp, _vp, _vp, _d, _d, ctypes.POINTER(SolverParams), ctypes.POINTER(_d),

@@ -450,6 +450,25 @@ def stout_schedule(nlevels: int, stored_levels: int) -> dict:
     return {"recompute_passes": passes.value, "checkpoints": [cp[i] for i in range(ncp.value)]}
 
 
+def lgt_dslash_noalloc(dims, U, psi, out, kappa: float, dagger: bool = False, fermion_bc: int = -1):
+    """lgt_dslash_noalloc: D psi (or D^dag psi) into the caller's out, with
+    no context and no device allocation (library-held scratch, V <= 16^4)."""
+    lib = _lib.load()
+    dims = tuple(int(d) for d in dims)
+    lx, ly, lz, lt = dims
+    shapes = {"U": (lt, lz, ly, lx, 4, 3, 3), "psi": (lt, lz, ly, lx, 4, 3), "out": (lt, lz, ly, lx, 4, 3)}
+    for name, t in (("U", U), ("psi", psi), ("out", out)):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or tuple(t.shape) != shapes[name] \
+                or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous complex128 device tensor of shape {shapes[name]}")
+    geom = _lib.Geom((ctypes.c_int32 * 4)(*dims), int(fermion_bc))
+    st = lib.lgt_dslash_noalloc(ctypes.byref(geom), ctypes.c_void_p(_stream_ptr()), ctypes.c_void_p(U.data_ptr()),
+                                ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(out.data_ptr()), float(kappa),
+                                int(bool(dagger)))
+    _check(lib, None, st)
+    return out
+
+
 def lgt_create(dims, fermion_bc: int = -1) -> Lattice:
     return Lattice(dims, fermion_bc)
 

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "liblgt.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["kernels_hop.hip", "kernels_field.hip", "kernels_force.hip", "kernels_stout.hip", "kernels_mrhs.hip",
-           "solver.hip", "smear.hip", "batch.hip", "multishift.hip", "abi.hip"]
+           "solver.hip", "smear.hip", "batch.hip", "multishift.hip", "noalloc.hip", "abi.hip"]
 
 ARCH = "gfx950"
 HIPCC_FLAGS = [

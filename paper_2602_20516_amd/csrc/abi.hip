@@ -834,3 +834,5 @@ lgt_status lgt_hop_benchmark_mrhs(lgt_ctx* c, const void* U, const void* psi, in
 }
 
 }  // extern "C"
+
+void lgt_set_global_error(const std::string& msg) { g_create_error = msg; }

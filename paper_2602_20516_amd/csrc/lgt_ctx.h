@@ -73,6 +73,8 @@ struct BatchWork;       // batched-solver workspace (batch.hip)
 struct MultiShiftWork;  // multi-shift solver workspace (multishift.hip)
 struct lgt_ctx;
 void lgt_ctx_free_batch(lgt_ctx* c);
+// message lgt_last_error(NULL) returns (calls without a context)
+void lgt_set_global_error(const std::string& msg);
 void lgt_ctx_free_multishift(lgt_ctx* c);
 int lgt_ctx_max_shifts();
 
