@@ -359,23 +359,51 @@ LGT_API lgt_status lgt_md_step_eo(lgt_ctx* ctx, void* U, void* P, const void* ph
                                   double dt, int32_t nsteps, int32_t n_inner, const lgt_solver_params* params,
                                   double* dH_or_null, lgt_solver_stats* stats);
 
+/* ---- Batched solves over several lattices --------------------------------
+ * A batch object orders the work of lgt_cg_solve_batch on the caller's
+ * stream.  It owns one extra HIP stream per lattice of a call (default
+ * priority), on which the lattices' solves run at the same time. */
+typedef struct lgt_batch lgt_batch;
+
+/* Create a batch object bound to hip_stream (NULL = the default stream) on
+ * the current device.  Errors: INVALID_ARGUMENT (null out), DEVICE. */
+LGT_API lgt_status lgt_batch_create(void* hip_stream, lgt_batch** out);
+/* Release it (synchronises its streams). */
+LGT_API lgt_status lgt_batch_destroy(lgt_batch* b);
+/* Message of the last failing call on b ("" if none); valid until the next call. */
+LGT_API const char* lgt_batch_last_error(const lgt_batch* b);
+/* Rebind the batch object to another HIP stream (NULL = default stream). */
+LGT_API lgt_status lgt_batch_set_stream(lgt_batch* b, void* hip_stream);
+
 /* One right-hand side of a batched solve. */
 typedef struct lgt_batch_item {
+  lgt_ctx* ctx;    /* the lattice of this right-hand side (its context) */
+  const void* U;   /* gauge field of that lattice: the same pointer for every item of one context */
   const void* phi; /* spinor (input) */
   void* X;         /* spinor (output): (D^dag D)^-1 phi at this item's kappa */
   void* Y_or_null; /* spinor (output) D X, or NULL */
   double kappa;    /* hopping parameter of this item */
 } lgt_batch_item;
 
-/* Batched solve of n (1..16) pseudofermion fields on one lattice, each with
- * its own kappa: every item gets the result lgt_cg_solve would give it (same
- * method and stopping rule), but all right-hand sides run through the same
- * launches, so each link load serves all of them and each keeps its own CG
- * scalars, stopping once converged.  stats_per_item (may be NULL) receives n
- * entries; ms is the time of the whole batch.  NOT_CONVERGED if any item
- * missed the tolerance (all outputs are written).  INVALID_ARGUMENT also
- * when the batched FP64 field (12 * V/2 * n complex) reaches 4 GiB. */
-LGT_API lgt_status lgt_cg_solve_batch(lgt_ctx* ctx, const void* U, int32_t n, const lgt_batch_item* items,
+/* Batched solve of n pseudofermion fields (the solve of eq. S3.5 for each,
+ * as lgt_cg_solve: same method and stopping rule) spread over up to 8
+ * lattices of any sizes, each item with its own lattice and kappa: the
+ * workload of many pseudofermions, kappa values and lattice sizes in one
+ * call.  Items of one context (1..16 of them) are solved together: every
+ * launch of that lattice covers all of its right-hand sides, so one link
+ * load serves all of them, and each keeps its own CG scalars and stops
+ * once converged.  The lattices run at the same time, each on a stream of
+ * the batch object that waits for the work already on the caller's stream;
+ * the caller's stream waits for all of them before the call returns (the
+ * call synchronises).  The contexts' own streams are not used during the
+ * call.  stats_per_item (may be NULL) receives n entries in item order; ms
+ * is the time of the whole call.  NOT_CONVERGED if any item missed the
+ * tolerance (all outputs are written).  INVALID_ARGUMENT: null pointers,
+ * n < 1, more than 16 items or two gauge fields for one context, more than
+ * 8 contexts, or a batched FP64 field (12 * V/2 * items complex) of 4 GiB
+ * or more; UNSUPPORTED for LGT_MIXED_BF16.  The message of a failure inside
+ * one lattice's solve names that lattice. */
+LGT_API lgt_status lgt_cg_solve_batch(lgt_batch* b, int32_t n, const lgt_batch_item* items,
                                       const lgt_solver_params* params, lgt_solver_stats* stats_per_item);
 
 /* Multi-shift solve, the building block of a rational (RHMC) pseudofermion
@@ -462,6 +490,30 @@ LGT_API lgt_status lgt_set_hop_block_sites(lgt_ctx* ctx, int32_t sites);
  * used.  Results do not depend on the order except through the summation
  * order of the kernels' reductions.  INVALID_ARGUMENT for other values. */
 LGT_API lgt_status lgt_set_hop_block_order(lgt_ctx* ctx, int32_t order);
+
+/* out[k] = D(U) in[k] (dagger = 0) or D(U)^dag in[k] (dagger = 1) with
+ * kappa = kappas[k], for n (1..16) spinors on this context's lattice, in one
+ * launch of the batched multi-right-hand-side hop (each link load serves
+ * all n fields): the operator of eq. S3.1 as lgt_dslash, batched.
+ * precision LGT_FP64: FP64 throughout; LGT_MIXED_FP32: the FP32 batched hop
+ * of the mixed-precision batched solve (kernel per lgt_set_batch_hop_kernel)
+ * on FP32 copies of U and in, its result widened to FP64 (relative error
+ * ~1e-7).  in, out: n device pointers (host array) to canonical spinors;
+ * kappas: n host values.  INVALID_ARGUMENT: null pointers, n outside 1..16,
+ * other precisions, non-finite kappa. */
+LGT_API lgt_status lgt_dslash_batch(lgt_ctx* ctx, const void* U, int32_t n, const void* const* in, void* const* out,
+                                    const double* kappas, int32_t dagger, int32_t precision);
+
+/* Kernel of the FP32 batched hop in lgt_cg_solve_batch (mixed precision)
+ * and lgt_hop_benchmark_mrhs on this context: 1 = the VALU kernel (each
+ * lane one site, the link applied to each right-hand side in turn), 2 = the
+ * MFMA kernel (the link times the projected half spinors of a group of 4 or
+ * 8 right-hand sides as a real 6 x 6 by 6 x 2G product on
+ * v_mfma_f32_4x4x1_16b_f32, 16 sites per instruction), 0 (the default) =
+ * whichever of them and of their group sizes the first batched call on the
+ * context times fastest.  The kernels sum in different orders, so results
+ * may differ by rounding.  INVALID_ARGUMENT for other values. */
+LGT_API lgt_status lgt_set_batch_hop_kernel(lgt_ctx* ctx, int32_t kind);
 
 #ifdef __cplusplus
 }

@@ -9,7 +9,7 @@ from . import _lib
 
 _lib.load()
 
-from .api import (Lattice, LGTError, LGTNonFinite, LGTNotConverged, Params,  # noqa: E402
+from .api import (Batch, Lattice, LGTError, LGTNonFinite, LGTNotConverged, Params,  # noqa: E402
                   lgt_action, lgt_bilinear_force, lgt_cg_solve, lgt_cg_solve_batch, lgt_create, lgt_dslash,
                   lgt_dslash_noalloc,
                   lgt_fermion_force, lgt_gauge_force, lgt_hop_benchmark, lgt_hop_benchmark_mrhs, lgt_kinetic,
@@ -20,7 +20,7 @@ from .api import (Lattice, LGTError, LGTNonFinite, LGTNotConverged, Params,  # n
 from .autograd import LatticeAction, lattice_action  # noqa: E402
 
 __all__ = [
-    "Lattice", "Params", "LGTError", "LGTNotConverged", "LGTNonFinite", "lgt_cg_solve_batch",
+    "Batch", "Lattice", "Params", "LGTError", "LGTNotConverged", "LGTNonFinite", "lgt_cg_solve_batch",
     "lgt_create", "lgt_dslash", "lgt_dslash_noalloc", "lgt_cg_solve", "lgt_action", "lgt_fermion_force",
     "lgt_bilinear_force", "lgt_gauge_force", "lgt_link_update", "lgt_kinetic", "lgt_md_step",
     "lgt_hop_benchmark", "lgt_hop_benchmark_mrhs", "lgt_stout_smear", "lgt_stout_backprop", "lgt_smeared_force", "lgt_md_step_smeared", "lgt_md_step_sw",

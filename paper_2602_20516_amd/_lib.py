@@ -40,8 +40,8 @@ class SolverParams(ctypes.Structure):
 
 
 class BatchItem(ctypes.Structure):
-    _fields_ = [("phi", ctypes.c_void_p), ("X", ctypes.c_void_p), ("Y_or_null", ctypes.c_void_p),
-                ("kappa", ctypes.c_double)]
+    _fields_ = [("ctx", ctypes.c_void_p), ("U", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("X", ctypes.c_void_p),
+                ("Y_or_null", ctypes.c_void_p), ("kappa", ctypes.c_double)]
 
 
 class SolverStats(ctypes.Structure):
@@ -82,7 +82,11 @@ PROTOTYPES = {
                           ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
     "lgt_hop_benchmark": (_st, [_vp, _vp, _vp, _i, _i, ctypes.POINTER(_d)]),
     "lgt_hop_benchmark_mrhs": (_st, [_vp, _vp, _vp, _i, _i, _i, ctypes.POINTER(_d)]),
-    "lgt_cg_solve_batch": (_st, [_vp, _vp, _i, ctypes.POINTER(BatchItem), ctypes.POINTER(SolverParams),
+    "lgt_batch_create": (_st, [_vp, ctypes.POINTER(_vp)]),
+    "lgt_batch_destroy": (_st, [_vp]),
+    "lgt_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "lgt_batch_set_stream": (_st, [_vp, _vp]),
+    "lgt_cg_solve_batch": (_st, [_vp, _i, ctypes.POINTER(BatchItem), ctypes.POINTER(SolverParams),
                                  ctypes.POINTER(SolverStats)]),
     "lgt_stout_smear": (_st, [_vp, _vp, _vp, _d, _i]),
     "lgt_stout_backprop": (_st, [_vp, _vp, _vp, _d, _i, _vp]),
@@ -100,6 +104,8 @@ PROTOTYPES = {
     "lgt_set_stout_checkpoints": (_st, [_vp, _i]),
     "lgt_set_hop_block_sites": (_st, [_vp, _i]),
     "lgt_set_hop_block_order": (_st, [_vp, _i]),
+    "lgt_set_batch_hop_kernel": (_st, [_vp, _i]),
+    "lgt_dslash_batch": (_st, [_vp, _vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_d), _i, _i]),
     "lgt_stout_last_schedule": (_st, [_vp, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_int64)]),
     "lgt_stout_schedule": (_st, [_i, _i, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "lgt_rational_force_eo": (_st, [_vp, _vp, _vp, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d), _d,

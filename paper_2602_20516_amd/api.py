@@ -69,6 +69,60 @@ def _stream_ptr() -> int:
     return torch.cuda.current_stream().cuda_stream
 
 
+class Batch:
+    """A batch object (lgt_batch): batched solves whose items may sit on
+    several lattices (one Lattice each)."""
+
+    def __init__(self):
+        self.lib = _lib.load()
+        b = ctypes.c_void_p()
+        st = self.lib.lgt_batch_create(ctypes.c_void_p(_stream_ptr()), ctypes.byref(b))
+        if st != _lib.LGT_OK:
+            raise LGTError(st, "lgt_batch_create failed", None)
+        self.handle = b
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.lgt_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def cg_solve(self, items, params: Optional["Params"] = None, want_y: bool = True):
+        """lgt_cg_solve_batch over items [(lattice, U, phi, kappa), ...].
+        Returns (Xs, Ys, stats) in item order."""
+        params = params or Params()
+        n = len(items)
+        Xs = [lat.empty_spinor() for lat, _, _, _ in items]
+        Ys = [lat.empty_spinor() for lat, _, _, _ in items] if want_y else [None] * n
+        arr = (_lib.BatchItem * max(n, 1))()
+        for k, (lat, U, phi, kappa) in enumerate(items):
+            arr[k].ctx = lat.ctx
+            arr[k].U = lat._field(U, "gauge", f"U[{k}]")
+            arr[k].phi = lat._field(phi, "spinor", f"phi[{k}]")
+            arr[k].X = lat._field(Xs[k], "spinor", f"X[{k}]")
+            arr[k].Y_or_null = lat._field(Ys[k], "spinor", f"Y[{k}]") if want_y else None
+            arr[k].kappa = float(kappa)
+        stats = (SolverStats * max(n, 1))()
+        cp = params.to_c()
+        self.lib.lgt_batch_set_stream(self.handle, ctypes.c_void_p(_stream_ptr()))
+        st = self.lib.lgt_cg_solve_batch(self.handle, n, arr, ctypes.byref(cp), stats)
+        if st != _lib.LGT_OK:
+            msg = self.lib.lgt_batch_last_error(self.handle)
+            msg = msg.decode() if msg else ""
+            s0 = stats[0].as_dict() if n else None
+            if st == _lib.LGT_ERR_NOT_CONVERGED:
+                raise LGTNotConverged(st, msg, s0)
+            if st == _lib.LGT_ERR_NONFINITE:
+                raise LGTNonFinite(st, msg, s0)
+            raise LGTError(st, msg, s0)
+        return Xs, Ys, [stats[k].as_dict() for k in range(n)]
+
+
 class Lattice:
     """A library context (lgt_ctx) for one lattice geometry on the current device."""
 
@@ -143,29 +197,29 @@ class Lattice:
         _check(self.lib, self.ctx, st, stats)
         return X, Y, stats.as_dict()
 
-    def cg_solve_batch(self, U, phis, kappas, params: Optional[Params] = None, want_y: bool = True):
-        """lgt_cg_solve_batch: one solve per (phi_n, kappa_n) through shared launches.
-
-        Returns (Xs, Ys, stats) with one entry per right-hand side.
-        """
-        params = params or Params()
-        n = len(phis)
+    def dslash_batch(self, U, psis, kappas, dagger: bool = False, precision: str = "fp64"):
+        """lgt_dslash_batch: [D_k psi_k] (or D_k^dag) for up to 16 fields in one batched hop."""
+        n = len(psis)
         if len(kappas) != n:
-            raise ValueError("one kappa per right-hand side")
-        Xs = [self.empty_spinor() for _ in range(n)]
-        Ys = [self.empty_spinor() for _ in range(n)] if want_y else [None] * n
-        items = (_lib.BatchItem * n)()
-        for k in range(n):
-            items[k].phi = self._field(phis[k], "spinor", f"phi[{k}]")
-            items[k].X = self._field(Xs[k], "spinor", f"X[{k}]")
-            items[k].Y_or_null = self._field(Ys[k], "spinor", f"Y[{k}]") if want_y else None
-            items[k].kappa = float(kappas[k])
-        stats = (SolverStats * n)()
-        cp = params.to_c()
+            raise ValueError("one kappa per field")
+        outs = [self.empty_spinor() for _ in range(n)]
+        ins = (ctypes.c_void_p * n)(*[self._field(p, "spinor", f"psi[{k}]").value for k, p in enumerate(psis)])
+        outp = (ctypes.c_void_p * n)(*[self._field(o, "spinor", f"out[{k}]").value for k, o in enumerate(outs)])
+        ks = (ctypes.c_double * n)(*[float(k) for k in kappas])
         self._bind_stream()
-        st = self.lib.lgt_cg_solve_batch(self.ctx, self._field(U, "gauge", "U"), n, items, ctypes.byref(cp), stats)
-        _check(self.lib, self.ctx, st, stats[0] if n else None)
-        return Xs, Ys, [stats[k].as_dict() for k in range(n)]
+        st = self.lib.lgt_dslash_batch(self.ctx, self._field(U, "gauge", "U"), n, ins, outp, ks, int(bool(dagger)),
+                                       _PRECISIONS[precision])
+        _check(self.lib, self.ctx, st)
+        return outs
+
+    def cg_solve_batch(self, U, phis, kappas, params: Optional[Params] = None, want_y: bool = True):
+        """lgt_cg_solve_batch with every item on this lattice: one solve per
+        (phi_n, kappa_n) through shared launches.  Returns (Xs, Ys, stats)."""
+        if len(kappas) != len(phis):
+            raise ValueError("one kappa per right-hand side")
+        if getattr(self, "_batch", None) is None:
+            self._batch = Batch()
+        return self._batch.cg_solve([(self, U, phi, k) for phi, k in zip(phis, kappas)], params, want_y)
 
     def action(self, U, phi, beta: float, kappa: float, params: Optional[Params] = None,
                gauge: bool = True, fermion: bool = True):
@@ -410,6 +464,11 @@ class Lattice:
         """lgt_set_hop_block_order: 64-site block order, 1 site order, 2 t-fastest (0: by volume)."""
         _check(self.lib, self.ctx, self.lib.lgt_set_hop_block_order(self.ctx, int(order)))
 
+    def set_batch_hop_kernel(self, kind: str = "auto"):
+        """lgt_set_batch_hop_kernel: FP32 batched hop kernel, "auto" (timed), "valu" or "mfma"."""
+        code = {"auto": 0, "valu": 1, "mfma": 2}[kind]
+        _check(self.lib, self.ctx, self.lib.lgt_set_batch_hop_kernel(self.ctx, code))
+
     def stout_last_schedule(self) -> dict:
         """lgt_stout_last_schedule: levels kept and passes recomputed by the last reverse pass."""
         s, p = ctypes.c_int32(), ctypes.c_int64()
@@ -481,8 +540,8 @@ def lgt_cg_solve(lat: Lattice, U, phi, kappa, params=None, want_y=True):
     return lat.cg_solve(U, phi, kappa, params, want_y)
 
 
-def lgt_cg_solve_batch(lat: Lattice, U, phis, kappas, params=None, want_y=True):
-    return lat.cg_solve_batch(U, phis, kappas, params, want_y)
+def lgt_cg_solve_batch(batch: Batch, items, params=None, want_y=True):
+    return batch.cg_solve(items, params, want_y)
 
 
 def lgt_action(lat: Lattice, U, phi, beta, kappa, params=None, gauge=True, fermion=True):

@@ -9,11 +9,23 @@
 #include "lgt_ctx.h"
 #include "lgt_mrhs.h"
 
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <thread>
+
 using namespace lgt;
 
 namespace {
 
 std::string g_create_error;
+
+// the items of one lattice in a batched solve (indices into the caller's array)
+struct BatchGroup {
+  lgt_ctx* ctx;
+  const void* U;
+  std::vector<int> idx;
+};
 
 // packed gauge scratch used here (see smear.hip): thin links, smeared output, gradient
 enum { kThin = 6, kSmeared = 8, kGradIn = 9, kU0 = 10, kP0 = 11 };
@@ -650,6 +662,33 @@ lgt_status lgt_set_hop_block_order(lgt_ctx* c, int32_t order) {
   });
 }
 
+lgt_status lgt_dslash_batch(lgt_ctx* c, const void* U, int32_t n, const void* const* in, void* const* out,
+                            const double* kappas, int32_t dagger, int32_t precision) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(U && in && out && kappas, "null pointer");
+    require(n >= 1 && n <= 16, "a batch holds 1 to 16 fields");
+    require(precision == LGT_FP64 || precision == LGT_MIXED_FP32, "precision must be LGT_FP64 or LGT_MIXED_FP32");
+    require((size_t)12 * c->vh * n * sizeof(double2) < ((size_t)1 << 32),
+            "batch too large: the batched spinor field must stay below 4 GiB");
+    for (int k = 0; k < n; ++k) {
+      require(in[k] && out[k], "null field pointer");
+      require(std::isfinite(kappas[k]), "kappa must be finite");
+    }
+    const bool f32 = precision == LGT_MIXED_FP32;
+    pack_links(c, U, f32);
+    c->dslash_batch(n, kappas, in, out, dagger != 0, f32);
+  });
+}
+
+lgt_status lgt_set_batch_hop_kernel(lgt_ctx* c, int32_t kind) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(kind == 0 || kind == 1 || kind == 2, "batched hop kernel must be 0 (timed choice), 1 (VALU) or 2 (MFMA)");
+    c->batch_hop_kind = kind;
+  });
+}
+
 lgt_status lgt_stout_last_schedule(const lgt_ctx* c, int32_t* stored_levels, int64_t* recompute_passes) {
   if (!c || !stored_levels || !recompute_passes) return LGT_ERR_INVALID_ARGUMENT;
   *stored_levels = c->last_stout_slots;
@@ -674,44 +713,158 @@ lgt_status lgt_stout_schedule(int32_t nlevels, int32_t stored_levels, int64_t* r
   return LGT_OK;
 }
 
-lgt_status lgt_cg_solve_batch(lgt_ctx* c, const void* U, int32_t n, const lgt_batch_item* items,
-                              const lgt_solver_params* params, lgt_solver_stats* stats) {
-  if (!c) return LGT_ERR_INVALID_ARGUMENT;
-  bool nc = false;
-  lgt_status s = guarded(c, [&] {
-    require(U && items, "null pointer");
-    require(n >= 1 && n <= 16, "a batch holds 1 to 16 right-hand sides");
-    if (params && params->precision == LGT_MIXED_BF16)
-      throw Error(LGT_ERR_UNSUPPORTED, "the batched solve has no BF16-storage variant (use LGT_MIXED_FP32)");
-    require((size_t)12 * c->vh * n * sizeof(double2) < ((size_t)1 << 32),
-            "batch too large: the batched spinor field must stay below 4 GiB (use fewer right-hand sides)");
-    std::vector<double> kap(n);
-    std::vector<const void*> phis(n);
-    std::vector<void*> xs(n), ys(n);
-    for (int k = 0; k < n; ++k) {
-      require(items[k].phi && items[k].X, "null field pointer in a batch item");
-      require(std::isfinite(items[k].kappa), "kappa must be finite");
-      kap[k] = items[k].kappa;
-      phis[k] = items[k].phi;
-      xs[k] = items[k].X;
-      ys[k] = items[k].Y_or_null;
-    }
-    const SolverOpts o = parse(params);
-    Timer tm(c);
-    pack_links(c, U, o.precision != LGT_FP64);
-    check_nonfinite(c, "U");
-    std::vector<SolveStats> st = c->solve_batch(n, kap.data(), phis.data(), xs.data(), ys.data(), o);
-    const double ms = tm.stop();
-    for (int k = 0; k < n; ++k) {
-      fill_stats(stats ? stats + k : nullptr, st[k], ms);
-      nc = nc || !st[k].converged;
-    }
-  });
-  if (s == LGT_OK && nc) {
-    c->err = "solver did not reach the tolerance for every right-hand side";
-    return LGT_ERR_NOT_CONVERGED;
+lgt_status lgt_batch_create(void* hip_stream, lgt_batch** out) {
+  if (!out) return LGT_ERR_INVALID_ARGUMENT;
+  lgt_batch* b = new (std::nothrow) lgt_batch();
+  if (!b) return LGT_ERR_OUT_OF_MEMORY;
+  b->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return LGT_ERR_DEVICE;
   }
-  return s;
+  *out = b;
+  return LGT_OK;
+}
+
+lgt_status lgt_batch_destroy(lgt_batch* b) {
+  if (!b) return LGT_OK;
+  for (auto s : b->side) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  for (auto e : b->events) (void)hipEventDestroy(e);
+  delete b;
+  return LGT_OK;
+}
+
+const char* lgt_batch_last_error(const lgt_batch* b) { return b ? b->err.c_str() : ""; }
+
+lgt_status lgt_batch_set_stream(lgt_batch* b, void* hip_stream) {
+  if (!b) return LGT_ERR_INVALID_ARGUMENT;
+  b->stream = (hipStream_t)hip_stream;
+  return LGT_OK;
+}
+
+lgt_status lgt_cg_solve_batch(lgt_batch* b, int32_t n, const lgt_batch_item* items,
+                              const lgt_solver_params* params, lgt_solver_stats* stats) {
+  if (!b) return LGT_ERR_INVALID_ARGUMENT;
+  b->err.clear();
+  auto fail = [&](lgt_status s, const std::string& m) {
+    b->err = m;
+    return s;
+  };
+  if (!items || n < 1) return fail(LGT_ERR_INVALID_ARGUMENT, "null items or n < 1");
+  // group the items by lattice (context), in order of first appearance
+  std::vector<BatchGroup> groups;
+  for (int k = 0; k < n; ++k) {
+    const lgt_batch_item& it = items[k];
+    if (!it.ctx || !it.U || !it.phi || !it.X) return fail(LGT_ERR_INVALID_ARGUMENT, "null pointer in a batch item");
+    if (!std::isfinite(it.kappa)) return fail(LGT_ERR_INVALID_ARGUMENT, "kappa must be finite");
+    auto g = std::find_if(groups.begin(), groups.end(), [&](const BatchGroup& x) { return x.ctx == it.ctx; });
+    if (g == groups.end()) {
+      groups.push_back(BatchGroup{it.ctx, it.U, {}});
+      g = groups.end() - 1;
+    }
+    if (g->U != it.U) return fail(LGT_ERR_INVALID_ARGUMENT, "two gauge fields for one context in a batch");
+    g->idx.push_back(k);
+  }
+  if (groups.size() > 8) return fail(LGT_ERR_INVALID_ARGUMENT, "a batch spans at most 8 lattices (contexts)");
+  for (const auto& g : groups) {
+    if (g.idx.size() > 16) return fail(LGT_ERR_INVALID_ARGUMENT, "at most 16 right-hand sides per lattice");
+    if (g.ctx->device != b->device) return fail(LGT_ERR_INVALID_ARGUMENT, "a context on another device");
+  }
+  if (params && params->precision == LGT_MIXED_BF16)
+    return fail(LGT_ERR_UNSUPPORTED, "the batched solve has no BF16-storage variant (use LGT_MIXED_FP32)");
+  try {
+    (void)parse(params);
+  } catch (const Error& e) {
+    return fail(e.status, e.what());
+  }
+  const size_t ng = groups.size();
+  try {
+    while (b->side.size() < ng) {
+      hipStream_t s = nullptr;
+      LGT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      b->side.push_back(s);
+    }
+    while (b->events.size() < ng + 1) {
+      hipEvent_t e = nullptr;
+      LGT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b->events.push_back(e);
+    }
+    // the lattices' streams start after the work already on the caller's stream
+    LGT_HIP(hipEventRecord(b->events[ng], b->stream));
+    for (size_t g = 0; g < ng; ++g) LGT_HIP(hipStreamWaitEvent(b->side[g], b->events[ng], 0));
+  } catch (const Error& e) {
+    return fail(e.status, e.what());
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<lgt_status> st(ng, LGT_OK);
+  std::vector<std::string> msg(ng);
+  std::vector<std::vector<SolveStats>> res(ng);
+  auto run_group = [&](size_t g) {
+    lgt_ctx* c = groups[g].ctx;
+    const hipStream_t own = c->stream;
+    c->stream = b->side[g];
+    st[g] = guarded(c, [&] {
+      const int m = (int)groups[g].idx.size();
+      require((size_t)12 * c->vh * m * sizeof(double2) < ((size_t)1 << 32),
+              "batch too large: the batched spinor field must stay below 4 GiB (use fewer right-hand sides)");
+      std::vector<double> kap(m);
+      std::vector<const void*> phis(m);
+      std::vector<void*> xs(m), ys(m);
+      for (int k = 0; k < m; ++k) {
+        const lgt_batch_item& it = items[groups[g].idx[k]];
+        kap[k] = it.kappa;
+        phis[k] = it.phi;
+        xs[k] = it.X;
+        ys[k] = it.Y_or_null;
+      }
+      const SolverOpts o = parse(params);
+      pack_links(c, groups[g].U, o.precision != LGT_FP64);
+      check_nonfinite(c, "U");
+      res[g] = c->solve_batch(m, kap.data(), phis.data(), xs.data(), ys.data(), o);
+    });
+    if (st[g] != LGT_OK) msg[g] = c->err;
+    c->stream = own;
+  };
+  // one host thread per further lattice: each drives its lattice's solve
+  // (the CG control loops wait on the device), so the lattices' kernels
+  // overlap on the GPU
+  std::vector<std::thread> th;
+  for (size_t g = 1; g < ng; ++g) th.emplace_back(run_group, g);
+  run_group(0);
+  for (auto& t : th) t.join();
+  lgt_status out = LGT_OK;
+  try {
+    for (size_t g = 0; g < ng; ++g) {
+      LGT_HIP(hipEventRecord(b->events[g], b->side[g]));
+      LGT_HIP(hipStreamWaitEvent(b->stream, b->events[g], 0));
+    }
+    LGT_HIP(hipStreamSynchronize(b->stream));
+  } catch (const Error& e) {
+    return fail(e.status, e.what());
+  }
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  bool nc = false;
+  for (size_t g = 0; g < ng; ++g) {
+    if (st[g] != LGT_OK) {
+      if (out == LGT_OK) {
+        out = st[g];
+        char head[64];
+        std::snprintf(head, sizeof head, "lattice %d (%dx%dx%dx%d): ", (int)g, groups[g].ctx->g.L[0],
+                      groups[g].ctx->g.L[1], groups[g].ctx->g.L[2], groups[g].ctx->g.L[3]);
+        b->err = head + msg[g];
+      }
+      continue;
+    }
+    for (size_t k = 0; k < groups[g].idx.size(); ++k) {
+      fill_stats(stats ? stats + groups[g].idx[k] : nullptr, res[g][k], ms);
+      nc = nc || !res[g][k].converged;
+    }
+  }
+  if (out == LGT_OK && nc) return fail(LGT_ERR_NOT_CONVERGED, "solver did not reach the tolerance for every right-hand side");
+  return out;
 }
 
 lgt_status lgt_cg_solve_multishift(lgt_ctx* c, const void* U, const void* phi, double kappa, int32_t nshift,

@@ -34,7 +34,9 @@ struct BatchWork {
   int* dint = nullptr;      // device restart flags
   int* hint = nullptr;
   int G[2] = {0, 0};        // right-hand sides per hop block, tuned per precision (FP32, FP64) for tuned_nr
+                            // (FP32: negative = MFMA kernel with groups of -G)
   int tuned_nr = 0;
+  int tuned_kind = 0;
 };
 
 static void free_batch(BatchWork* w) {
@@ -87,27 +89,40 @@ static BatchWork* batch_work(lgt_ctx* c, int nr) {
   return w;
 }
 
-// Autotuner of the batched hop's group size G (right-hand sides per block):
-// large G loads the links fewer times, small G launches more blocks (more
-// waves to hide latency on small lattices).  Every G that gives a distinct
-// number of groups is timed once per context, right-hand-side count and
-// precision with HIP events on the context stream; the fastest is kept.
+// Autotuner of the batched hop: the kernel (VALU, or for FP32 the MFMA form)
+// and its group size G (right-hand sides per block): large G loads the
+// links fewer times, small G launches more blocks (more waves to hide
+// latency on small lattices).  Every VALU G that gives a distinct number of
+// groups, and the MFMA groups of 8 and 4 (encoded G = -8, -4), are timed
+// once per context, right-hand-side count, precision and kernel choice
+// (lgt_set_batch_hop_kernel) with HIP events on the context stream; the
+// fastest is kept.
 static void tune_group_size(lgt_ctx* c, BatchWork* w, int nr, bool f32) {
-  if (w->tuned_nr != nr) {
+  if (w->tuned_nr != nr || w->tuned_kind != c->batch_hop_kind) {
     w->G[0] = w->G[1] = 0;
     w->tuned_nr = nr;
+    w->tuned_kind = c->batch_hop_kind;
   }
   int& G = w->G[f32 ? 0 : 1];
-  if (G > 0) return;
+  if (G != 0) return;
   if (f32) c->ensure_u32();
   const Reduce red{w->partials, c->result, 0, w->npart, nullptr};
   const double* coef = w->dvec;  // any finite values: only the time is used
   double best = 1e30;
   int prev_groups = 0;
-  for (int gsz = nr; gsz >= 1; --gsz) {
-    const int ngroups = (nr + gsz - 1) / gsz;
-    if (ngroups == prev_groups) continue;
-    prev_groups = ngroups;
+  std::vector<int> cand;
+  if (!f32 || c->batch_hop_kind != 2)
+    for (int gsz = nr; gsz >= 1; --gsz) {
+      const int ngroups = (nr + gsz - 1) / gsz;
+      if (ngroups == prev_groups) continue;
+      prev_groups = ngroups;
+      cand.push_back(gsz);
+    }
+  if (f32 && c->batch_hop_kind != 1) {
+    cand.push_back(-8);
+    cand.push_back(-4);
+  }
+  for (int gsz : cand) {
     auto once = [&] {
       if (f32) {
         HopIn<float> hin{c->U32, w->h[0], w->h[0]};
@@ -439,6 +454,51 @@ std::vector<SolveStats> lgt_ctx::solve_batch(int nr, const double* kappas, const
     if (Ys && Ys[k]) LGT_HIP(launch_munpack(g, nr, k, w->f[bY], (double2*)Ys[k], stream));
   }
   return b.st;
+}
+
+// out_n = D_n in_n (or D_n^dag in_n), D_n = 1 - kappa_n H, for nr fields in
+// one batched hop launch over both parities: FP64, or (f32) the FP32
+// batched hop on FP32 copies of the links and inputs, its output widened
+// back to FP64.
+void lgt_ctx::dslash_batch(int nr, const double* kappas, const void* const* ins, void* const* outs, bool dag,
+                           bool f32) {
+  BatchWork* w = batch_work(this, nr);
+  tune_group_size(this, w, nr, f32);
+  const int G = w->G[f32 ? 0 : 1];
+  for (int k = 0; k < kMaxRhs; ++k) {
+    w->hvec[vOne * kMaxRhs + k] = 1.0;
+    w->hvec[vMKap * kMaxRhs + k] = k < nr ? -kappas[k] : 0.0;
+  }
+  LGT_HIP(hipMemcpyAsync(w->dvec, w->hvec, 8 * kMaxRhs * sizeof(double), hipMemcpyHostToDevice, stream));
+  const double* one = w->dvec + vOne * kMaxRhs;
+  const double* mkap = w->dvec + vMKap * kMaxRhs;
+  for (int k = 0; k < nr; ++k) LGT_HIP(launch_mpack(g, nr, k, (const double2*)ins[k], w->f[bPhi], stream));
+  const size_t h = (size_t)12 * vh * nr;
+  const Reduce red{w->partials, result, 0, w->npart, nullptr};
+  if (f32) {
+    // the half fields h[0], h[1] hold the even and odd FP32 input, h[2], h[3] the output
+    LGT_HIP(launch_convert_64_32((int)h, w->f[bPhi], w->h[0], stream));
+    LGT_HIP(launch_convert_64_32((int)h, w->f[bPhi] + h, w->h[1], stream));
+    HopIn<float> hin{U32, w->h[0], w->h[1]};
+    if (dag)
+      LGT_HIP((launch_mhop_axpy<float, true>(g, nr, G, -1, hin, w->h[2], w->h[3], w->h[0], w->h[1], mkap, stream,
+                                              nullptr, nullptr, red)));
+    else
+      LGT_HIP((launch_mhop_axpy<float, false>(g, nr, G, -1, hin, w->h[2], w->h[3], w->h[0], w->h[1], mkap, stream,
+                                               nullptr, nullptr, red)));
+    LGT_HIP(launch_zero64((int)(2 * h), w->f[bX], stream));
+    LGT_HIP(launch_mmixed_update(vh, nr, w->h[2], w->f[bX], one, stream));
+    LGT_HIP(launch_mmixed_update(vh, nr, w->h[3], w->f[bX] + h, one, stream));
+  } else {
+    HopIn<double> hin{U64, w->f[bPhi], w->f[bPhi] + h};
+    if (dag)
+      LGT_HIP((launch_mhop_axpy<double, true>(g, nr, G, -1, hin, w->f[bX], w->f[bX] + h, w->f[bPhi],
+                                               w->f[bPhi] + h, mkap, stream, nullptr, nullptr, red)));
+    else
+      LGT_HIP((launch_mhop_axpy<double, false>(g, nr, G, -1, hin, w->f[bX], w->f[bX] + h, w->f[bPhi],
+                                                w->f[bPhi] + h, mkap, stream, nullptr, nullptr, red)));
+  }
+  for (int k = 0; k < nr; ++k) LGT_HIP(launch_munpack(g, nr, k, w->f[bX], (double2*)outs[k], stream));
 }
 
 double lgt_ctx::bench_mhop(int nr, bool f32, const void* psi, int nrep) {

@@ -17,6 +17,8 @@
 // it by timing (see batch.hip).  Per-RHS reductions are deterministic: a
 // fixed-order wave reduction, then the four waves in order, one partial per
 // (site block, right-hand side), summed by a one-block finalize launch.
+#include <type_traits>
+
 #include "lgt_internal.h"
 #include "lgt_hop.h"
 #include "lgt_mrhs.h"
@@ -253,22 +255,267 @@ __global__ __launch_bounds__(256) void k_hop_mrhs(Geom g, int nr, int G, int nbp
   epi.tail(nr);
 }
 
-static inline int mrhs_nbp(const Geom& g) { return (g.vh + 63) / 64; }
+// ---------------------------------------------------------------------------
+// MFMA form of the FP32 batched hop.  Per site x, direction mu and sign, the
+// hop applies one link to the projected half spinors of every right-hand
+// side of the group: W = U H, a complex 3 x (2 G) product, i.e. the real
+// product [[Ur, -Ui], [Ui, Ur]] (6 x 6) times [Hr; Hi] (6 x 2G).  Every
+// site has its own U, so the product runs on v_mfma_f32_4x4x1_16b_f32,
+// whose 16 independent 4x4 blocks take 16 sites per instruction: block b
+// (lanes 4b..4b+3) is site b of the wave's 16; its output rows are the
+// real-form rows (Re W_0, Re W_1, Re W_2, Im W_0 | Im W_1, Im W_2, -, -)
+// in two row tiles, its columns (spin, right-hand side) in 2G/4 column
+// tiles, and the six real input components are six rank-1 steps.  Lane j
+// of a block feeds row j of the link operand and column j of the spinor
+// operand, and receives column j of every output tile: the whole W of
+// right-hand sides j (and j + 4 for G = 8), both spins.  So the lane that
+// projects a right-hand side's neighbour spinor is also the lane that
+// reconstructs its W, and the link is loaded once per site (each lane one
+// or two of its rows).  A 256-thread block takes 16 sites of one parity
+// and a group of G right-hand sides; wave w takes direction mu = w (both
+// hops); the four directions meet in LDS as in k_hop_mrhs and the same
+// epilogues run.  Reductions: per right-hand side, a fixed-order sum over
+// the threads that own it, then one partial per (block, right-hand side).
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Rows of the real-form link operand fed by lane j (0..3): tile 0 row j,
+// tile 1 row j, as six values over the input components (Re h_c, Im h_c).
+// Forward: the link U; backward: U^dag (rows of U^dag = conjugated columns).
+template <bool ADJ>
+__device__ __forceinline__ void link_rows(const BufRsrc& ru, unsigned o, unsigned gs, int j, float* a0,
+                                          float* a1) {
+  // element (i, c) of the operator and its real and imaginary parts
+  auto el = [&](int i, int c) -> C<float> {
+    const C<float> u = ADJ ? ld_buf<float>(ru, o, (3 * c + i) * gs) : ld_buf<float>(ru, o, (3 * i + c) * gs);
+    return ADJ ? conj(u) : u;
+  };
+  if (j < 3) {  // tile 0: Re W_j = sum_c Re u_jc Re h_c - Im u_jc Im h_c
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const C<float> u = el(j, c);
+      a0[c] = u.re;
+      a0[3 + c] = -u.im;
+    }
+  } else {      // tile 0 row 3: Im W_0 = sum_c Im u_0c Re h_c + Re u_0c Im h_c
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const C<float> u = el(0, c);
+      a0[c] = u.im;
+      a0[3 + c] = u.re;
+    }
+  }
+  if (j < 2) {  // tile 1 rows 0, 1: Im W_1, Im W_2
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const C<float> u = el(j + 1, c);
+      a1[c] = u.im;
+      a1[3 + c] = u.re;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a1[c] = 0.f;
+  }
+}
+
+// W (2 spins x 3 colours) of the right-hand side in column tiles (c0, c1)
+// (spin 0, spin 1) from the accumulators
+__device__ __forceinline__ void tile_w(const v4f (*acc)[4], int c0, int c1, C<float>* w) {
+  const int cs[2] = {c0, c1};
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int c = cs[a];
+    w[3 * a + 0] = cmk<float>(acc[0][c][0], acc[0][c][3]);
+    w[3 * a + 1] = cmk<float>(acc[0][c][1], acc[1][c][0]);
+    w[3 * a + 2] = cmk<float>(acc[0][c][2], acc[1][c][1]);
+  }
+}
+
+// One hop (forward: U_mu(x) psi(x + mu) with projector 1 + S gamma_mu;
+// backward: U_mu(x - mu)^dag psi(x - mu) with 1 + S gamma_mu) of the lane's
+// right-hand sides, added to out[0..NL-1][12].
+template <int MU, int S, bool ADJ, int G>
+__device__ __forceinline__ void mfma_hop(const MrhsIn<float>& in, unsigned osite, const BufRsrc& ru, unsigned olink,
+                                         unsigned gs, int j, int n0, unsigned live, bool bc, float bcs,
+                                         C<float> (*out)[12]) {
+  constexpr int NL = G / 4;       // right-hand sides per lane
+  constexpr int NCT = 2 * G / 4;  // column tiles
+  float a0[6], a1[6];
+  link_rows<ADJ>(ru, olink, gs, j, a0, a1);
+  C<float> h[NL][6];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int nl = j + 4 * q;
+    if ((live >> nl) & 1u) {
+      C<float> psi[12];
+      const unsigned o = in.off(0, n0 + nl) + osite;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) psi[k] = in.ld(o, k);
+      project<float, MU, S>(psi, h[q]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) h[q][k] = czero<float>();
+    }
+  }
+  v4f acc[2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = v4f{0.f, 0.f, 0.f, 0.f};
+  // column tile c: spin c / NL, right-hand side (lane's) c % NL
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const C<float> hv = h[c % NL][3 * (c / NL) + (k % 3)];
+      const float b = k < 3 ? hv.re : hv.im;
+      acc[0][c] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0[k], b, acc[0][c], 0, 0, 0);
+      acc[1][c] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1[k], b, acc[1][c], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    C<float> w[6];
+    tile_w(acc, q, NL + q, w);
+    if (bc) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) w[k] = bcs * w[k];
+    }
+    reconstruct<float, MU, S>(w, out[q]);
+  }
+}
+
+template <int MU, bool DAG, int G>
+__device__ __forceinline__ void mfma_dir(const Geom& g, const MrhsIn<float>& in, const float2* gauge, int p, int cb,
+                                         const int c[4], int j, int n0, unsigned live, C<float> (*out)[12]) {
+  constexpr int SF = DAG ? +1 : -1;
+  constexpr unsigned E = sizeof(float2);
+  const unsigned gs = (unsigned)g.vh * E;
+  const int nf = cb_shift(g, c, MU, +1), nb = cb_shift(g, c, MU, -1);
+  const BufRsrc ruf = make_rsrc(gptr<float>(gauge, g, p, MU), (size_t)9 * gs);
+  const BufRsrc rub = make_rsrc(gptr<float>(gauge, g, 1 - p, MU), (size_t)9 * gs);
+  const float bcs = (float)g.bc;
+  mfma_hop<MU, SF, false, G>(in, (unsigned)nf * E, ruf, (unsigned)cb * E, gs, j, n0, live,
+                             MU == 3 && c[3] == g.L[3] - 1, bcs, out);
+  mfma_hop<MU, -SF, true, G>(in, (unsigned)nb * E, rub, (unsigned)nb * E, gs, j, n0, live, MU == 3 && c[3] == 0,
+                             bcs, out);
+}
+
+template <bool DAG, typename Epi, int G>
+__global__ __launch_bounds__(256) void k_hop_mrhs_mfma(Geom g, int nr, int nbp, int ngrp, int p_fixed,
+                                                       HopIn<float> hin, Epi epi, double* partials) {
+  if (epi.skip()) return;
+  constexpr int NL = G / 4;
+  __shared__ float2 lds[4][G][12][16];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int per_par = nbp * ngrp;
+  const int p = p_fixed >= 0 ? p_fixed : lb / per_par;
+  const int rem = p_fixed >= 0 ? lb : lb % per_par;
+  const int blk = rem / ngrp, grp = rem - blk * ngrp;
+  const int n0 = grp * G, ng = min(G, nr - n0);
+  const int lane = threadIdx.x & 63;
+  const int mu = threadIdx.x >> 6;
+  const int j = lane & 3, sb = lane >> 2;
+  const int cb = blk * 16 + sb;
+  const bool active = cb < g.vh;
+  __shared__ unsigned s_act;
+  if (threadIdx.x == 0) {
+    unsigned m = 0;
+    for (int n = 0; n < ng; ++n) m |= (epi.rhs_active(n0 + n) ? 1u : 0u) << n;
+    s_act = m;
+  }
+  __syncthreads();
+  const unsigned act = s_act;
+  constexpr unsigned E = sizeof(float2);
+  const unsigned ns = (unsigned)g.vh * E;
+  const MrhsIn<float> in{make_rsrc(p ? hin.in_even : hin.in_odd, (size_t)12 * nr * ns), (unsigned)nr * ns, ns};
+  C<float> out[NL][12];
+#pragma unroll
+  for (int q = 0; q < NL; ++q)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) out[q][k] = czero<float>();
+  // every lane of the wave runs the MFMA (inactive sites read site 0 and
+  // are not stored); a block whose group has no running right-hand side
+  // skips the work
+  if (act) {
+    int c[4] = {0, 0, 0, 0};
+    cb_coords(g, p, active ? cb : 0, c);
+    switch (mu) {
+      case 0: mfma_dir<0, DAG, G>(g, in, hin.gauge, p, active ? cb : 0, c, j, n0, act, out); break;
+      case 1: mfma_dir<1, DAG, G>(g, in, hin.gauge, p, active ? cb : 0, c, j, n0, act, out); break;
+      case 2: mfma_dir<2, DAG, G>(g, in, hin.gauge, p, active ? cb : 0, c, j, n0, act, out); break;
+      default: mfma_dir<3, DAG, G>(g, in, hin.gauge, p, active ? cb : 0, c, j, n0, act, out); break;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NL; ++q)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) lds[mu][j + 4 * q][k][sb] = make_float2(out[q][k].re, out[q][k].im);
+  __syncthreads();
+  // epilogue: thread t owns right-hand side nl = t / (256 / G) of the group
+  // and components k = kq, kq + KS, ... of site t % 16
+  constexpr int TPR = 256 / G;   // threads per right-hand side (32 or 64)
+  constexpr int KS = TPR / 16;   // component stride (2 or 4)
+  const int nl = threadIdx.x / TPR, q = threadIdx.x % TPR;
+  const int site = q & 15, kq = q >> 4;
+  const int ocb = blk * 16 + site;
+  const bool run = nl < ng && ((act >> nl) & 1u) && ocb < g.vh;
+  double red = 0.0;
+  if (run) {
+    const int n = n0 + nl;
+#pragma unroll
+    for (int k = kq; k < 12; k += KS) {
+      const float2 a = lds[0][nl][k][site], b = lds[1][nl][k][site], cc = lds[2][nl][k][site],
+                   d = lds[3][nl][k][site];
+      epi.apply(p, ((size_t)k * nr + n) * g.vh + ocb, n, cmk<float>(((a.x + b.x) + cc.x) + d.x,
+                                                                     ((a.y + b.y) + cc.y) + d.y), red);
+    }
+  }
+  if constexpr (Epi::kReduce) {
+#pragma unroll
+    for (int o = TPR / 2; o > 0; o >>= 1) red += __shfl_xor(red, o, 64);
+    if (q == 0 && nl < ng) {
+      const int row = p_fixed >= 0 ? blk : p * nbp + blk;
+      partials[(size_t)row * kMaxRhs + n0 + nl] = red;
+    }
+  }
+  epi.tail(nr);
+}
+
+// site blocks per parity of the batched hop: 64 sites (VALU kernel, G > 0)
+// or 16 sites (MFMA kernel, G = -4 or -8)
+static inline int mrhs_nbp(const Geom& g, int G = 1) { return G < 0 ? (g.vh + 15) / 16 : (g.vh + 63) / 64; }
 
 template <typename R, bool DAG, typename Epi>
 static hipError_t mlaunch(const Geom& g, int nr, int G, int p_out, const HopIn<R>& hin, const Epi& epi, Reduce red,
                           hipStream_t s) {
-  if (G < 1 || G > kMaxRhs || nr < 1 || nr > kMaxRhs) return hipErrorInvalidValue;
-  const int nbp = mrhs_nbp(g);
-  const int ngrp = (nr + G - 1) / G;
+  if (nr < 1 || nr > kMaxRhs) return hipErrorInvalidValue;
+  const int gs = G < 0 ? -G : G;
+  if (gs < 1 || gs > kMaxRhs || (G < 0 && gs != 4 && gs != 8)) return hipErrorInvalidValue;
+  const int nbp = mrhs_nbp(g, G);
+  const int ngrp = (nr + gs - 1) / gs;
   const int rows = p_out >= 0 ? nbp : 2 * nbp;
   if (Epi::kReduce && (size_t)rows * kMaxRhs > red.ndoubles) return hipErrorInvalidValue;
+  if (G < 0) {
+    if constexpr (std::is_same<R, float>::value) {
+      if (gs == 8)
+        hipLaunchKernelGGL((k_hop_mrhs_mfma<DAG, Epi, 8>), dim3(rows * ngrp), dim3(256), 0, s, g, nr, nbp, ngrp,
+                           p_out, hin, epi, red.partials);
+      else
+        hipLaunchKernelGGL((k_hop_mrhs_mfma<DAG, Epi, 4>), dim3(rows * ngrp), dim3(256), 0, s, g, nr, nbp, ngrp,
+                           p_out, hin, epi, red.partials);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;  // the MFMA form is FP32 only
+    }
+  }
   hipLaunchKernelGGL((k_hop_mrhs<R, DAG, Epi>), dim3(rows * ngrp), dim3(256), 0, s, g, nr, G, nbp, ngrp, p_out, hin,
                      epi, red.partials);
   return hipGetLastError();
 }
 
-int mrhs_hop_blocks(const Geom& g, int p_out) { return p_out >= 0 ? mrhs_nbp(g) : 2 * mrhs_nbp(g); }
+// largest number of partial rows a reducing batched hop writes (the 16-site MFMA blocks)
+int mrhs_hop_blocks(const Geom& g, int p_out) { return p_out >= 0 ? mrhs_nbp(g, -8) : 2 * mrhs_nbp(g, -8); }
 
 template <typename R, bool DAG>
 hipError_t launch_mhop_axpy(const Geom& g, int nr, int G, int p_out, HopIn<R> hin, R2<R>* out_e, R2<R>* out_o,
@@ -282,7 +529,7 @@ hipError_t launch_mhop_axpy(const Geom& g, int nr, int G, int p_out, HopIn<R> hi
   e.coef = coef;
   e.guard = guard;
   e.pap_partials = pap_partials;
-  e.pap_nblk = mrhs_nbp(g);
+  e.pap_nblk = mrhs_nbp(g, G);
   e.state = guard;
   return mlaunch<R, DAG>(g, nr, G, p_out, hin, e, red, s);
 }
@@ -300,7 +547,7 @@ hipError_t launch_mhop_schur_cg(const Geom& g, int nr, int G, HopIn<R> hin, cons
   MEpiSchurCG<R> e{w, x, r, p, coef, st};
   hipError_t err = mlaunch<R, DAG>(g, nr, G, 1, hin, e, red, s);
   if (err != hipSuccess) return err;
-  return launch_mfinalize(kFinCgStep, mrhs_nbp(g), nr, red, st, 0.0, 0, s);
+  return launch_mfinalize(kFinCgStep, mrhs_nbp(g, G), nr, red, st, 0.0, 0, s);
 }
 
 template <bool DAG>
@@ -318,7 +565,7 @@ hipError_t launch_mhop_residual(const Geom& g, int nr, int G, HopIn<double> hin,
   e.coef = coef;
   hipError_t err = mlaunch<double, DAG>(g, nr, G, -1, hin, e, red, s);
   if (err != hipSuccess) return err;
-  return launch_mfinalize(kFinResult1, 2 * mrhs_nbp(g), nr, red, nullptr, 0.0, 0, s);
+  return launch_mfinalize(kFinResult1, 2 * mrhs_nbp(g, G), nr, red, nullptr, 0.0, 0, s);
 }
 
 #define LGT_INST_MHOP(R, DAG)                                                                                   \

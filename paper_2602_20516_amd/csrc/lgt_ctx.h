@@ -73,6 +73,15 @@ struct BatchWork;       // batched-solver workspace (batch.hip)
 struct MultiShiftWork;  // multi-shift solver workspace (multishift.hip)
 struct lgt_ctx;
 void lgt_ctx_free_batch(lgt_ctx* c);
+// batch object of lgt_cg_solve_batch: the caller's stream, one stream per
+// lattice of a call (created on demand, default priority) and their events
+struct lgt_batch {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> events;
+  std::string err;
+};
 // message lgt_last_error(NULL) returns (calls without a context)
 void lgt_set_global_error(const std::string& msg);
 void lgt_ctx_free_multishift(lgt_ctx* c);
@@ -186,6 +195,8 @@ struct lgt_ctx {
   // levels as device memory holds), the schedule for n levels, the forward
   // sweep that keeps its checkpoints, and the reverse pass over it
   int stout_slot_cap = -1;
+  // kernel of the FP32 batched hop: 0 timed choice, 1 VALU, 2 MFMA (batch.hip)
+  int batch_hop_kind = 0;
   int last_stout_slots = 0;
   int64_t last_stout_passes = 0;
   std::unique_ptr<lgt::StoutSchedule> sched;
@@ -201,6 +212,7 @@ struct lgt_ctx {
   // batched solves (batch.hip): nr right-hand sides with their own kappa
   BatchWork* batch = nullptr;
   double bench_mhop(int nr, bool f32, const void* psi, int nrep);  // ms per multi-RHS hop launch
+  void dslash_batch(int nr, const double* kappas, const void* const* ins, void* const* outs, bool dag, bool f32);
   std::vector<lgt::SolveStats> solve_batch(int nr, const double* kappas, const void* const* phis, void* const* Xs,
                                            void* const* Ys, const lgt::SolverOpts& o);
 

@@ -27,7 +27,9 @@ hipError_t launch_mfinalize(int mode, int nblk, int nr, Reduce red, BatchState* 
 int mrhs_hop_blocks(const Geom& g, int p_out);
 
 // Batched hops over nr fields in the [12][nr][vh] layout; G = right-hand
-// sides per block (1..nr; the links are loaded once per group of G).
+// sides per block (1..nr; the links are loaded once per group of G) for the
+// VALU kernel, or G = -4 / -8 for the MFMA kernel (FP32 only) with groups
+// of 4 or 8 right-hand sides.
 // out = self + coef_n H in  (coef: device array [nr]); guard/pap_partials as launch_hop_axpy
 template <typename R, bool DAG>
 hipError_t launch_mhop_axpy(const Geom& g, int nr, int G, int p_out, HopIn<R> hin, R2<R>* out_e, R2<R>* out_o,
