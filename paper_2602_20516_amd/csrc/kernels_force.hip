@@ -10,6 +10,7 @@
 // 9 KB span.
 #include "lgt_internal.h"
 #include "lgt_su3.h"
+#include "lgt_hop.h"
 
 namespace lgt {
 
@@ -121,15 +122,156 @@ __global__ __launch_bounds__(256) void k_bilinear(Geom g, const double2* __restr
 
 static inline int link_blocks(const Geom& g) { return (2 * g.vh * 4 + 255) / 256; }
 
+// ---------------------------------------------------------------------------
+// Per-link kernels in site-block form: a 256-thread block owns 64
+// consecutive checkerboard sites of one parity and all four directions,
+// wave w taking direction mu = w, so every wave's loads of a field
+// component (own site, neighbour, link) are 64 consecutive elements, and
+// the site's own spinors are shared by its four waves through L1.  Blocks
+// alternate parity (logical block 2i + p is site block i of parity p), so
+// the neighbour spinors a block reads are the own spinors the block next to
+// it reads at about the same time, on the same XCD.  Output: the packed
+// layout is written directly (coalesced); the canonical [V][4][3][3] layout
+// is staged in LDS and written as each site's 576-byte record (all four
+// links), by consecutive threads.
+// ---------------------------------------------------------------------------
+constexpr int kSB = 64;  // sites per block
+
+__device__ __forceinline__ int lex_of(const Geom& g, const int c[4]) {
+  return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+}
+
+// Stage M (the link's output matrix) and write the block's sites: packed
+// layout directly, canonical through LDS.  mode 2 subtracts dt M from the
+// momenta in place.
+template <int LAYOUT>
+__device__ __forceinline__ void emit_block(const Geom& g, double2* out, int p, int blk, int lane, int mu, int mode,
+                                           double dt, const M3<double>& M, bool active, int s_lex,
+                                           double2 (*sh)[36], int* sh_site) {
+  if (LAYOUT == kPacked) {
+    if (active) {
+      const int cb = blk * kSB + lane;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        double2* q = out + ((size_t)(p * 4 + mu) * 9 + k) * g.vh + cb;
+        if (mode == 2) st<double>(q, ld<double>(q) - dt * M.m[k]);
+        else st<double>(q, M.m[k]);
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) sh[lane][mu * 9 + k] = make_double2(M.m[k].re, M.m[k].im);
+  if (mu == 0) sh_site[lane] = active ? s_lex : -1;
+  __syncthreads();
+  for (int e = threadIdx.x; e < kSB * 36; e += 256) {
+    const int site = e / 36, r = e - site * 36;
+    const int sl = sh_site[site];
+    if (sl < 0) continue;
+    double2* q = out + (size_t)sl * 36 + r;
+    const double2 v = sh[site][r];
+    if (mode == 2) {
+      const double2 o = *q;
+      *q = make_double2(o.x - dt * v.x, o.y - dt * v.y);
+    } else {
+      *q = v;
+    }
+  }
+}
+
+// Z of the bilinear adjoint for direction MU at (p, cb): sum of the outer
+// products of the projected half spinors, one pair of spinors at a time
+template <int MU>
+__device__ __forceinline__ M3<double> bilinear_z(const SpinorIn<double, double2>& a_own,
+                                                 const SpinorIn<double, double2>& b_own,
+                                                 const SpinorIn<double, double2>& a_nb,
+                                                 const SpinorIn<double, double2>& b_nb, int cb, int nf) {
+  M3<double> Z;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Z.m[k] = czero<double>();
+  C<double> psi[12], hx[6], hy[6];
+  {  // h-[b(x+mu)] h-[a(x)]^dag
+    const unsigned ob = b_nb.off(nf, 0), oa = a_own.off(cb, 0);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = b_nb.ld(ob, k);
+    project<double, MU, -1>(psi, hx);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = a_own.ld(oa, k);
+    project<double, MU, -1>(psi, hy);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Z.m[3 * i + j] += mulcj(hx[i], hy[j]) + mulcj(hx[3 + i], hy[3 + j]);
+  }
+  {  // h+[a(x+mu)] h+[b(x)]^dag
+    const unsigned oa = a_nb.off(nf, 0), ob = b_own.off(cb, 0);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = a_nb.ld(oa, k);
+    project<double, MU, +1>(psi, hx);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = b_own.ld(ob, k);
+    project<double, MU, +1>(psi, hy);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Z.m[3 * i + j] += mulcj(hx[i], hy[j]) + mulcj(hx[3 + i], hy[3 + j]);
+  }
+  return Z;
+}
+
+// The bilinear adjoint (see k_bilinear) in site-block form.
+template <int LAYOUT>
+__global__ __launch_bounds__(256) void k_bilinear_sb(Geom g, const double2* __restrict__ U,
+                                                     const double2* __restrict__ a, const double2* __restrict__ b,
+                                                     double kappa, double coeff, int mode, double dt,
+                                                     double2* out) {
+  __shared__ double2 sh[LAYOUT == kCanonical ? kSB : 1][36];
+  __shared__ int sh_site[kSB];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int p = lb & 1, blk = lb >> 1;
+  const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
+  const int cb = blk * kSB + lane;
+  const bool active = cb < g.vh;
+  const int vh = g.vh;
+  int c[4];
+  cb_coords(g, p, active ? cb : 0, c);
+  const int cbx = active ? cb : 0;
+  const int nf = cb_shift(g, c, mu, +1);
+  const unsigned ks = (unsigned)vh * (unsigned)sizeof(double2);
+  const size_t half = (size_t)12 * vh;
+  const SpinorIn<double, double2> a_own{make_rsrc(a + p * half, (size_t)12 * ks), ks, 1u};
+  const SpinorIn<double, double2> b_own{make_rsrc(b + p * half, (size_t)12 * ks), ks, 1u};
+  const SpinorIn<double, double2> a_nb{make_rsrc(a + (1 - p) * half, (size_t)12 * ks), ks, 1u};
+  const SpinorIn<double, double2> b_nb{make_rsrc(b + (1 - p) * half, (size_t)12 * ks), ks, 1u};
+  M3<double> Z;
+  switch (mu) {
+    case 0: Z = bilinear_z<0>(a_own, b_own, a_nb, b_nb, cbx, nf); break;
+    case 1: Z = bilinear_z<1>(a_own, b_own, a_nb, b_nb, cbx, nf); break;
+    case 2: Z = bilinear_z<2>(a_own, b_own, a_nb, b_nb, cbx, nf); break;
+    default: Z = bilinear_z<3>(a_own, b_own, a_nb, b_nb, cbx, nf); break;
+  }
+  const double sbc = (mu == 3 && c[3] == g.L[3] - 1) ? double(g.bc) : 1.0;
+  M3<double> M;
+  if (mode == 1) {
+    M = mscale(-coeff * kappa * sbc, mdag(Z));
+  } else {
+    const M3<double> Ux = load_m3<double>(gptr<double>(U, g, p, mu), vh, cbx);
+    M = mscale(0.5 * coeff * kappa * sbc, proj_ta(mmul(Ux, Z)));
+  }
+  emit_block<LAYOUT>(g, out, p, blk, lane, mu, mode, dt, M, active, lex_of(g, c), sh, sh_site);
+}
+
+static inline int sb_blocks(const Geom& g) { return 2 * ((g.vh + kSB - 1) / kSB); }
+
 hipError_t launch_bilinear_force(const Geom& g, const double2* U, const double2* a_full, const double2* b_full,
                                  double kappa, double coeff, int mode, double dt, void* out, int layout,
                                  hipStream_t s) {
-  const int nb = link_blocks(g);
+  const int nb = sb_blocks(g);
   if (layout == kCanonical)
-    hipLaunchKernelGGL((k_bilinear<kCanonical>), dim3(nb), dim3(256), 0, s, g, U, a_full, b_full, kappa, coeff,
+    hipLaunchKernelGGL((k_bilinear_sb<kCanonical>), dim3(nb), dim3(256), 0, s, g, U, a_full, b_full, kappa, coeff,
                        mode, dt, (double2*)out);
   else
-    hipLaunchKernelGGL((k_bilinear<kPacked>), dim3(nb), dim3(256), 0, s, g, U, a_full, b_full, kappa, coeff,
+    hipLaunchKernelGGL((k_bilinear_sb<kPacked>), dim3(nb), dim3(256), 0, s, g, U, a_full, b_full, kappa, coeff,
                        mode, dt, (double2*)out);
   return hipGetLastError();
 }
@@ -162,14 +304,58 @@ __global__ __launch_bounds__(256) void k_gauge_force(Geom g, const double2* __re
   emit<LAYOUT>(g, out, s, p, cb, mu, mode, dt, F, G);
 }
 
+// The staple force in site-block form (see k_bilinear_sb): each thread sums
+// the six staples of its link one at a time, each as two 3x3 products, so
+// at most the running sum, one partial product and two links are live.
+template <int LAYOUT>
+__global__ __launch_bounds__(256) void k_gauge_force_sb(Geom g, const double2* __restrict__ U, double beta,
+                                                        int mode, double dt, double2* out) {
+  __shared__ double2 sh[LAYOUT == kCanonical ? kSB : 1][36];
+  __shared__ int sh_site[kSB];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int p = lb & 1, blk = lb >> 1;
+  const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
+  const int cb = blk * kSB + lane;
+  const bool active = cb < g.vh;
+  int c[4];
+  cb_coords(g, p, active ? cb : 0, c);
+  int xpm[4];
+  shifted(g, c, mu, +1, xpm);
+  M3<double> A;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) A.m[k] = czero<double>();
+#pragma unroll 1
+  for (int k = 1; k < 4; ++k) {
+    const int nu = (mu + k) & 3;
+    int xpn[4], xmn[4], xpmmn[4];
+    shifted(g, c, nu, +1, xpn);
+    shifted(g, c, nu, -1, xmn);
+    shifted(g, xpm, nu, -1, xpmmn);
+    // U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+    M3<double> t = mmul_nd(link_at(U, g, xpm, nu), link_at(U, g, xpn, mu));
+    A = madd(A, mmul_nd(t, link_at(U, g, c, nu)));
+    // U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu) = (U_mu(x-nu) U_nu(x+mu-nu))^dag U_nu(x-nu)
+    t = mmul(link_at(U, g, xmn, mu), link_at(U, g, xpmmn, nu));
+    A = madd(A, mmul_dn(t, link_at(U, g, xmn, nu)));
+  }
+  M3<double> M;
+  if (mode == 1) {
+    M = mscale(-beta / 3.0, mdag(A));
+  } else {
+    const M3<double> Ux = load_m3<double>(gptr<double>(U, g, p, mu), g.vh, active ? cb : 0);
+    M = mscale(beta / 6.0, proj_ta(mmul(Ux, A)));
+  }
+  emit_block<LAYOUT>(g, out, p, blk, lane, mu, mode, dt, M, active, lex_of(g, c), sh, sh_site);
+}
+
 hipError_t launch_gauge_force(const Geom& g, const double2* U, double beta, int mode, double dt, void* out,
                               int layout, hipStream_t s) {
-  const int nb = link_blocks(g);
+  const int nb = sb_blocks(g);
   if (layout == kCanonical)
-    hipLaunchKernelGGL((k_gauge_force<kCanonical>), dim3(nb), dim3(256), 0, s, g, U, beta, mode, dt,
+    hipLaunchKernelGGL((k_gauge_force_sb<kCanonical>), dim3(nb), dim3(256), 0, s, g, U, beta, mode, dt,
                        (double2*)out);
   else
-    hipLaunchKernelGGL((k_gauge_force<kPacked>), dim3(nb), dim3(256), 0, s, g, U, beta, mode, dt,
+    hipLaunchKernelGGL((k_gauge_force_sb<kPacked>), dim3(nb), dim3(256), 0, s, g, U, beta, mode, dt,
                        (double2*)out);
   return hipGetLastError();
 }
