@@ -130,8 +130,9 @@ def main():
     ap.add_argument("--hop-shapes", action="store_true",
                     help="time the two work shapes of the hop kernel (hop alone and inside the force)")
     ap.add_argument("--study", default=None, choices=("dh-vs-dt", "reliable-delta"))
-    ap.add_argument("--hop-probe", nargs=6, default=None, metavar=("LX", "LY", "LZ", "LT", "PREC", "NRHS"),
-                    help="launch the hop kernel and a calibration copy for rocprofv3 (no JSON line)")
+    ap.add_argument("--hop-probe", nargs="+", default=None, metavar="ARG",
+                    help="LX LY LZ LT PREC NRHS [valu|mfma]: launch the hop kernel and a calibration copy for "
+                         "rocprofv3 (no JSON line)")
     ap.add_argument("--therm", type=int, default=100, help="thermalisation trajectories of the study")
     ap.add_argument("--meas", type=int, default=40, help="measured trajectories per step size in the study")
     args = ap.parse_args()
@@ -461,8 +462,11 @@ def hop_probe(argv):
 
     import lgt_inputs as li
     import paper_2602_20516_amd as lgt
+    if len(argv) not in (6, 7):
+        raise SystemExit("--hop-probe takes LX LY LZ LT PREC NRHS [valu|mfma]")
     dims = tuple(int(v) for v in argv[:4])
     prec, nrhs = argv[4], int(argv[5])
+    kind = argv[6] if len(argv) == 7 else "auto"
     small = int(np.prod(dims)) <= 65536  # larger lattices: fields tiled from 8^4 (see _tiled_links)
     u = li.random_links(dims, 0.3, 201) if small else _tiled_links(dims)
     eta = (li.gaussian_spinor(dims, 202) if small
@@ -470,6 +474,7 @@ def hop_probe(argv):
     U = torch.from_numpy(u).to("cuda")
     E = torch.from_numpy(eta).to("cuda")
     lat = lgt.Lattice(dims)
+    lat.set_batch_hop_kernel(kind)
     ms = lat.hop_benchmark_mrhs(U, E, nrhs, prec, 20) if nrhs > 1 else lat.hop_benchmark(U, E, prec, 20)
     a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
@@ -477,7 +482,7 @@ def hop_probe(argv):
         b.copy_(a)
     torch.cuda.synchronize()
     src = MHOP_SOURCES if nrhs > 1 else HOP_SOURCES
-    print(f"hop {dims} {prec} nrhs {nrhs}: {ms * 1e3:.2f} us per launch; copy of {a.numel() * 8 >> 20} MiB x5 done; "
+    print(f"hop {dims} {prec} nrhs {nrhs} kernel {kind}: {ms * 1e3:.2f} us per launch; copy of {a.numel() * 8 >> 20} MiB x5 done; "
           f"kernel_sources_sha {kernel_sources_sha(src)}", flush=True)
 
 

@@ -7,12 +7,12 @@
  * by reverse-mode AD of the action code:
  *
  *   - the Wilson-Dirac operator D(U) (used in S_f of eq. S3.1),
- *   - the solve of A chi = phi, A = D^dag D (eq. S3.5; "e.g. via conjugate
- *     gradient", not differentiated),
+ *   - the solve of A chi = phi, A = D^dag D (eq. S3.6; solved by an iterative
+ *     method and not differentiated, Supp. S3 remarks on the linear solver),
  *   - the actions S_G (Wilson plaquette) and S_f = phi^dag (D^dag D)^-1 phi,
  *   - the MD forces: the pseudofermion force from
- *     delta S_f = -2 Re[eta^dag (delta D) chi] (eq. S3.11) and the plaquette
- *     (staple) force, projected to su(3) (eq. 6 / S2.11),
+ *     delta S_f = -2 Re[eta^dag (delta D) chi] (eq. S3.12) and the plaquette
+ *     (staple) force, projected to su(3) (eq. 7 / S2.9),
  *   - the leapfrog step U -> exp(dt Pi) U, Pi -> Pi - dt F (eqs. S2.1-S2.2).
  *
  * Here the forces are explicit adjoint kernels, not AD output.
@@ -43,9 +43,9 @@
  *   the last time slice, where U~ = fermion_t_bc * U.
  *
  * Gradients and forces (Sec. S2): the gradient of a real action S is
- *   G = dS/dRe U + i dS/dIm U (eq. S2.7), so delta S = Re tr(G^dag delta U);
+ *   G = dS/dRe U + i dS/dIm U (eq. S2.12), so delta S = Re tr(G^dag delta U);
  *   the force is F = -1/2 P_su3[U G^dag] with
- *   P_su3[A] = (A - A^dag)/2 - tr(A - A^dag)/6 (eq. 6).  The momentum update
+ *   P_su3[A] = (A - A^dag)/2 - tr(A - A^dag)/6 (eq. 7).  The momentum update
  *   Pi <- Pi - dt F equals the paper's Pi <- Pi + (dt/2) P_su3[U G^dag].
  *   Momenta are traceless anti-Hermitian, K = -sum tr Pi^2.
  *
@@ -193,7 +193,7 @@ LGT_API lgt_status lgt_dslash(lgt_ctx* ctx, const void* U, const void* in, void*
 LGT_API lgt_status lgt_dslash_noalloc(const lgt_geom* geom, void* hip_stream, const void* U, const void* in,
                                       void* out, double kappa, int32_t dagger);
 
-/* Solve (D^dag D) X = phi (eq. S3.5) and return Y = D X (the paper's
+/* Solve (D^dag D) X = phi (eq. S3.6) and return Y = D X (the paper's
  * eta = D chi below eq. S3.10).  The solve is not differentiated (S3,
  * "Remarks on the role of the linear solver").  Method: two even/odd Schur
  * complement solves, D^dag Y = phi then D X = Y, each by CG on the normal
@@ -215,7 +215,7 @@ LGT_API lgt_status lgt_action(lgt_ctx* ctx, const void* U, const void* phi, doub
                       lgt_solver_stats* stats);
 
 /* Pseudofermion force: solve as in lgt_cg_solve, then the adjoint kernel of
- * delta S_f = -2 Re[Y^dag (delta D) X] (eq. S3.11) for every link, projected
+ * delta S_f = -2 Re[Y^dag (delta D) X] (eq. S3.12) for every link, projected
  * by F = -1/2 P_su3[U G^dag].  mode/dt/out as in lgt_out_mode; out is a
  * gauge-type buffer.  The force itself is accumulated in FP64 for every
  * precision. */
@@ -235,10 +235,16 @@ LGT_API lgt_status lgt_bilinear_force(lgt_ctx* ctx, const void* U, const void* a
 LGT_API lgt_status lgt_gauge_force(lgt_ctx* ctx, const void* U, double beta, int32_t mode, double dt,
                            void* out);
 
-/* U <- reunitarize(exp(dt Pi) U) on every link, in place (eq. 4 / S2.1 in
+/* U <- reunitarize(exp(dt Pi) U) on every link, in place (eq. 5 / S2.1 in
  * the anti-Hermitian form).  exp by the Cayley-Hamilton closed form;
  * reunitarization by row Gram-Schmidt with row3 = conj(row1 x row2).  FP64. */
 LGT_API lgt_status lgt_link_update(lgt_ctx* ctx, void* U, const void* P, double dt);
+
+/* HMC momentum refresh (Sec. III B): P_mu(x) = i sum_a c_a T_a with
+ * T_a = lambda_a / 2 (Gell-Mann), from normals: device FP64 [V][4][8],
+ * c_a at [s][mu][a-1] (the caller draws them, N(0,1) for the heat bath).
+ * P: gauge-type output (canonical).  FP64. */
+LGT_API lgt_status lgt_momenta_from_normals(lgt_ctx* ctx, const void* normals, void* P);
 
 /* K = -sum_{x,mu} tr Pi_mu(x)^2 for traceless anti-Hermitian momenta.  FP64. */
 LGT_API lgt_status lgt_kinetic(lgt_ctx* ctx, const void* P, double* K);
@@ -264,7 +270,7 @@ LGT_API lgt_status lgt_md_step(lgt_ctx* ctx, void* U, void* P, const void* phi, 
  * nlevels 0..256; U_in and U_out may not overlap. */
 LGT_API lgt_status lgt_stout_smear(lgt_ctx* ctx, const void* U_in, void* U_out, double rho, int32_t nlevels);
 
-/* Reverse mode through the smearing (the adjoint update of eq. 3, written
+/* Reverse mode through the smearing (the adjoint update of eq. 4, written
  * by hand): G_out = gradient at U_in of Re tr(G_top^dag stout^n(U_in)), in the
  * G convention.  The intermediate levels each level's adjoint needs follow
  * the context's checkpoint schedule (lgt_set_stout_checkpoints): the sweep
@@ -385,7 +391,7 @@ typedef struct lgt_batch_item {
   double kappa;    /* hopping parameter of this item */
 } lgt_batch_item;
 
-/* Batched solve of n pseudofermion fields (the solve of eq. S3.5 for each,
+/* Batched solve of n pseudofermion fields (the solve of eq. S3.6 for each,
  * as lgt_cg_solve: same method and stopping rule) spread over up to 8
  * lattices of any sizes, each item with its own lattice and kappa: the
  * workload of many pseudofermions, kappa values and lattice sizes in one

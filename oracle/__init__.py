@@ -13,18 +13,18 @@ of the action.  It shares no code with the HIP path; the only common module is
 
 Modules and the parts of the paper they follow:
 
-* ``su3``     su(N) projection (eq. 6 / S2.11), the left update exp (eq. 4, S2.1)
+* ``su3``     su(N) projection (eq. 7 / S2.9), the left update exp (eq. 5, S2.1)
 * ``lattice`` periodic shifts of site fields
 * ``dirac``   Wilson-Dirac operator D(U) and D^dagger (the operator of S3.1;
               the paper names it but does not write it out)
-* ``solver``  CG for A chi = phi with A = D^dagger D (S3.5, "Remarks on the
+* ``solver``  CG for A chi = phi with A = D^dagger D (S3.6, "Remarks on the
               role of the linear solver")
 * ``action``  Wilson plaquette action, pseudofermion action S_f (S3.1), kinetic
               energy
-* ``force``   matrix gradient G = dS/dU_R + i dS/dU_I (S2.7), force
-              F = -1/2 P_su(3)[U G^dagger] (S2.11, S2.15 and the S4 listings),
+* ``force``   matrix gradient G = dS/dU_R + i dS/dU_I (S2.12), force
+              F = -1/2 P_su(3)[U G^dagger] (S2.9, S2.15 and the S4 listings),
               fermion force via delta S_f = -2 Re[eta^dagger (delta D) chi]
-              (S3.11) and the building block I(U) = a^dagger D(U) b (S3.13)
+              (S3.12) and the building block I(U) = a^dagger D(U) b (S3.13)
 * ``md``      leapfrog molecular dynamics (eqs. S2.1-S2.2; Sec. III B), Delta H
 * ``stout``   stout smearing (Morningstar-Peardon) and its gradient through
               torch CPU autograd

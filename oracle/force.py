@@ -3,14 +3,14 @@
 Conventions (Sec. S2):
 
 * The gradient of a real action is the complex matrix
-  G = dS/dU_R + i dS/dU_I (eq. S2.7), so that a first-order variation reads
+  G = dS/dU_R + i dS/dU_I (eq. S2.12), so that a first-order variation reads
   delta S = Re tr(G^dag delta U).  (The paper's matrix derivative is
   dS/dU = G^dag / 2, eq. S2.15.)
 * Reading of the force: with the left update U -> exp(dt Pi) U, Pi = i sum_a p_a T_a
   and H = 1/2 sum p_a^2 + S, energy conservation needs dp_a/dtau = -d_a S with
   d_a S = d/ds S(exp(i s T_a) U)|_0 = Re tr(G^dag i T_a U).  Writing
   Pi' = -F gives F = i sum_a (d_a S) T_a = -1/2 P_su(3)[U G^dag], i.e. the
-  projection of eq. (6) applied to U G^dag (S2 "Why the implementation
+  projection of eq. (7) applied to U G^dag (S2 "Why the implementation
   constructs U G^dag"), with the overall factor -1/2.  A momentum update
   P <- P - dt F is then P <- P + (dt/2) P_su(3)[U G^dag], the gauge-force
   listing's step with factor eps*dtau/2.
@@ -19,7 +19,7 @@ Gauge gradient: reverse-mode differentiation, written by hand, of the
 plaquette sum of ``action.gauge_action``: every plaquette term
 -beta/3 Re tr(A B C^dag D^dag) sends one adjoint to each of its four links.
 
-Fermion gradient (Sec. S3): delta S_f = -2 Re[eta^dag (delta D) chi] (S3.11)
+Fermion gradient (Sec. S3): delta S_f = -2 Re[eta^dag (delta D) chi] (S3.12)
 with chi = (D^dag D)^-1 phi and eta = D chi, i.e. S_f's gradient is -2 times
 the gradient of Re I(U), I(U) = a^dag D(U) b (S3.13) at a = eta, b = chi, with
 the solve itself not differentiated.
@@ -99,7 +99,7 @@ def bilinear_grad(u: np.ndarray, a: np.ndarray, b: np.ndarray, kappa: float,
 
 
 def fermion_grad_from_solution(u, chi, eta, kappa, bc=-1):
-    """G_f = -2 * grad Re[eta^dag D(U) chi] (eq. S3.11)."""
+    """G_f = -2 * grad Re[eta^dag D(U) chi] (eq. S3.12)."""
     return -2.0 * bilinear_grad(u, eta, chi, kappa, bc)
 
 

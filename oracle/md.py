@@ -49,7 +49,7 @@ def hamiltonian(u, p, phi, beta, kappa, bc=-1, tol=1e-12, with_fermion=True):
 
 
 def link_update(u, p, dt):
-    """U <- reunitarize(exp(dt Pi) U)  (eq. 4 / S2.1 with the reunitarization reading)."""
+    """U <- reunitarize(exp(dt Pi) U)  (eq. 5 / S2.1 with the reunitarization reading)."""
     return reunitarize(expm_antihermitian(dt * p) @ u)
 
 

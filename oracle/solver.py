@@ -1,7 +1,7 @@
 """Conjugate gradient for the oracle (test infrastructure only).
 
 The pseudofermion action and force need chi = A^-1 phi with A = D^dag D
-(eq. S3.5); the paper solves it "e.g. via conjugate gradient" and does not
+(eq. S3.6); the paper names conjugate gradient as one way to solve it and does not
 differentiate the solve.  This is the textbook CG (Hestenes-Stiefel) on the
 Hermitian positive definite A, from a zero initial guess, stopping when the
 recursively updated residual satisfies ||r|| <= tol * ||b||.  The true
@@ -53,7 +53,7 @@ def cg(apply_a, b: np.ndarray, tol: float, max_iter: int = 20000):
 
 def solve_ddag_d(u: np.ndarray, phi: np.ndarray, kappa: float, bc: int = -1,
                  tol: float = 1e-12, max_iter: int = 20000):
-    """chi = (D^dag D)^-1 phi and eta = D chi (eq. S3.5 and the definition below S3.10).
+    """chi = (D^dag D)^-1 phi and eta = D chi (eq. S3.6 and the definition below S3.10).
 
     Returns (chi, eta, iterations, true relative residual).  The oracle calls
     the paper's eta "Y" to keep it apart from the Gaussian heat-bath field.

@@ -1,9 +1,9 @@
 """SU(3) group and algebra helpers for the oracle (test infrastructure only).
 
 * ``project_su`` is the su(N) projection P[A] = (A - A^dag)/2 - tr(A - A^dag)/(2N) * 1
-  of eq. (6) / eq. (S2.11).
+  of eq. (7) / eq. (S2.9).
 * ``expm_antihermitian`` is the matrix exponential of an anti-Hermitian matrix,
-  as used by the left-multiplication update U -> exp(i eps H) U (eq. 4, S2.1).
+  as used by the left-multiplication update U -> exp(i eps H) U (eq. 5, S2.1).
   It is computed exactly through the Hermitian eigendecomposition.
 * ``reunitarize`` re-projects a near-unitary 3x3 matrix onto SU(3) by row
   Gram-Schmidt with the third row conj(r1 x r2).
@@ -62,7 +62,7 @@ def identity_like(m: np.ndarray) -> np.ndarray:
 
 
 def project_su(a: np.ndarray) -> np.ndarray:
-    """Traceless anti-Hermitian part, eq. (6): (A-A^dag)/2 - tr(A-A^dag)/(2N)."""
+    """Traceless anti-Hermitian part, eq. (7): (A-A^dag)/2 - tr(A-A^dag)/(2N)."""
     d = a - dag(a)
     n = a.shape[-1]
     return 0.5 * d - (trace(d) / (2 * n))[..., None, None] * identity_like(a)

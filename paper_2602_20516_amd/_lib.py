@@ -78,6 +78,7 @@ PROTOTYPES = {
     "lgt_gauge_force": (_st, [_vp, _vp, _d, _i, _d, _vp]),
     "lgt_link_update": (_st, [_vp, _vp, _vp, _d]),
     "lgt_kinetic": (_st, [_vp, _vp, ctypes.POINTER(_d)]),
+    "lgt_momenta_from_normals": (_st, [_vp, _vp, _vp]),
     "lgt_md_step": (_st, [_vp, _vp, _vp, _vp, _d, _d, _d, _i, ctypes.POINTER(SolverParams),
                           ctypes.POINTER(_d), ctypes.POINTER(SolverStats)]),
     "lgt_hop_benchmark": (_st, [_vp, _vp, _vp, _i, _i, ctypes.POINTER(_d)]),

@@ -285,6 +285,19 @@ class Lattice:
         _check(self.lib, self.ctx, st)
         return U
 
+    def momenta_from_normals(self, normals, out=None):
+        """lgt_momenta_from_normals: P = i sum_a c_a T_a from float64 normals [...,4,8]."""
+        shape = self.site_shape + (4, 8)
+        if not isinstance(normals, torch.Tensor) or normals.dtype != torch.float64 or tuple(normals.shape) != shape \
+                or not normals.is_cuda or not normals.is_contiguous():
+            raise ValueError(f"normals: expected a contiguous float64 device tensor of shape {shape}")
+        out = self.empty_gauge() if out is None else out
+        self._bind_stream()
+        st = self.lib.lgt_momenta_from_normals(self.ctx, ctypes.c_void_p(normals.data_ptr()),
+                                               self._field(out, "gauge", "P"))
+        _check(self.lib, self.ctx, st)
+        return out
+
     def kinetic(self, P) -> float:
         """lgt_kinetic."""
         k = ctypes.c_double()

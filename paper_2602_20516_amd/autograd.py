@@ -4,7 +4,7 @@
 returns S = S_G(U) + phi^dag (D^dag D)^-1 phi with D built on stout^n(U).
 U is taken as a float64 real view ``[..., 4, 3, 3, 2]`` of the complex links, so
 the backward returns exactly (dS/dRe U, dS/dIm U), the real components the
-paper's AD differentiates (S2.7).  The backward is the library's explicit
+paper's AD differentiates (S2.12).  The backward is the library's explicit
 adjoint (lgt_smeared_force in gradient mode): the fermion adjoint on the
 smeared links, then the stout adjoint chain, recomputing the smeared levels
 instead of saving them; only U and phi are kept between forward and backward.

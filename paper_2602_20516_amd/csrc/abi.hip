@@ -367,6 +367,14 @@ lgt_status lgt_link_update(lgt_ctx* c, void* U, const void* P, double dt) {
   });
 }
 
+lgt_status lgt_momenta_from_normals(lgt_ctx* c, const void* normals, void* P) {
+  if (!c) return LGT_ERR_INVALID_ARGUMENT;
+  return guarded(c, [&] {
+    require(normals && P, "null pointer");
+    LGT_HIP(launch_momenta(c->g, (const double*)normals, (double2*)P, c->stream));
+  });
+}
+
 lgt_status lgt_kinetic(lgt_ctx* c, const void* P, double* K) {
   if (!c) return LGT_ERR_INVALID_ARGUMENT;
   return guarded(c, [&] {

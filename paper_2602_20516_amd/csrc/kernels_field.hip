@@ -98,6 +98,32 @@ hipError_t launch_pack(const Geom& g, int nc, const double2* canon, double2* out
   return hipGetLastError();
 }
 
+// HMC momentum refresh (Sec. III B): Pi = i sum_a c_a T_a, T_a = lambda_a / 2
+// (Gell-Mann), from eight normals c_a per link, canonical [V][4][3][3].
+// Written out per element (traceless anti-Hermitian by construction).
+__global__ __launch_bounds__(256) void k_momenta(size_t nlinks, const double* __restrict__ c,
+                                                 double2* __restrict__ P) {
+  const size_t l = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (l >= nlinks) return;
+  const double* a = c + 8 * l;
+  const double h = 0.5, r3 = 0.57735026918962576451;  // 1/sqrt(3)
+  double2* q = P + 9 * l;
+  q[0] = make_double2(0.0, h * (a[2] + r3 * a[7]));
+  q[1] = make_double2(h * a[1], h * a[0]);
+  q[2] = make_double2(h * a[4], h * a[3]);
+  q[3] = make_double2(-h * a[1], h * a[0]);
+  q[4] = make_double2(0.0, h * (-a[2] + r3 * a[7]));
+  q[5] = make_double2(h * a[6], h * a[5]);
+  q[6] = make_double2(-h * a[4], h * a[3]);
+  q[7] = make_double2(-h * a[6], h * a[5]);
+  q[8] = make_double2(0.0, -2.0 * h * r3 * a[7]);
+}
+hipError_t launch_momenta(const Geom& g, const double* normals, double2* P, hipStream_t s) {
+  const size_t n = (size_t)2 * g.vh * 4;
+  hipLaunchKernelGGL(k_momenta, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, normals, P);
+  return hipGetLastError();
+}
+
 hipError_t launch_unpack(const Geom& g, int nc, const double2* packed, double2* canon, hipStream_t s) {
   const int V = 2 * g.vh;
   const int nb = (V + kPackSites - 1) / kPackSites;

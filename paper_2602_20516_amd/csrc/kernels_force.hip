@@ -2,7 +2,7 @@
 //
 // Conventions (Sec. S2): G = dS/dRe U + i dS/dIm U, delta S = Re tr(G^dag dU),
 // F = -1/2 P_su3[U G^dag] with P_su3 the traceless anti-Hermitian projection
-// of eq. (6); the momentum update is P <- P - dt F.
+// of eq. (7); the momentum update is P <- P - dt F.
 //
 // Thread mapping of the per-link kernels: thread t handles link (s, mu) with
 // s = t/4 the lexicographic site and mu = t%4, so a wavefront covers 16
@@ -74,7 +74,7 @@ __device__ __forceinline__ void emit(const Geom& g, double2* out, int s, int p, 
 // where h-/h+ are the projections of (1 - gamma_mu)/(1 + gamma_mu).  For the
 // functional coeff * Re I:  G = -coeff kappa s_bc Z^dag and
 // F = -1/2 P[U G^dag] = (coeff kappa s_bc / 2) P[U Z].  The pseudofermion
-// force of eq. S3.11 is coeff = -2, a = Y = D X, b = X.
+// force of eq. S3.12 is coeff = -2, a = Y = D X, b = X.
 // ---------------------------------------------------------------------------
 template <int LAYOUT>
 __global__ __launch_bounds__(256) void k_bilinear(Geom g, const double2* __restrict__ U,
@@ -136,6 +136,22 @@ static inline int link_blocks(const Geom& g) { return (2 * g.vh * 4 + 255) / 256
 // links), by consecutive threads.
 // ---------------------------------------------------------------------------
 constexpr int kSB = 64;  // sites per block
+
+// Site block of logical block lb: parity lb & 1, block lb >> 1, taken in
+// the t-fastest order of the hop kernel (groups of tgrp t-slices of bps
+// blocks each; tgrp = 0: site order), so that a block's t-neighbour links
+// and spinors were read a few blocks earlier on the same XCD and are still
+// in its L2 (on large lattices a t-slice of links does not fit in it).
+__device__ __forceinline__ int site_block(int lb, int bps, int tgrp) {
+  int blk = lb >> 1;
+  if (tgrp > 0) {
+    const int span = tgrp * bps;
+    const int grp = blk / span, rem = blk - grp * span;
+    const int chunk = rem / tgrp, tl = rem - chunk * tgrp;
+    blk = (grp * tgrp + tl) * bps + chunk;
+  }
+  return blk;
+}
 
 __device__ __forceinline__ int lex_of(const Geom& g, const int c[4]) {
   return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
@@ -224,11 +240,11 @@ template <int LAYOUT>
 __global__ __launch_bounds__(256) void k_bilinear_sb(Geom g, const double2* __restrict__ U,
                                                      const double2* __restrict__ a, const double2* __restrict__ b,
                                                      double kappa, double coeff, int mode, double dt,
-                                                     double2* out) {
+                                                     double2* out, int bps, int tgrp) {
   __shared__ double2 sh[LAYOUT == kCanonical ? kSB : 1][36];
   __shared__ int sh_site[kSB];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int p = lb & 1, blk = lb >> 1;
+  const int p = lb & 1, blk = site_block(lb, bps, tgrp);
   const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
   const int cb = blk * kSB + lane;
   const bool active = cb < g.vh;
@@ -263,16 +279,28 @@ __global__ __launch_bounds__(256) void k_bilinear_sb(Geom g, const double2* __re
 
 static inline int sb_blocks(const Geom& g) { return 2 * ((g.vh + kSB - 1) / kSB); }
 
+// t-fastest groups for the site-block kernels (as the hop's): above 131072
+// sites per parity, when a t-slice holds a whole number of blocks
+static inline void sb_order(const Geom& g, int& bps, int& tgrp) {
+  const int vslice = g.vh / g.L[3];
+  bps = vslice / kSB;
+  tgrp = 0;
+  if (vslice % kSB != 0 || bps == 0 || g.vh <= 131072) return;
+  tgrp = g.L[3] % 8 == 0 ? 8 : (g.L[3] % 4 == 0 ? 4 : 2);
+}
+
 hipError_t launch_bilinear_force(const Geom& g, const double2* U, const double2* a_full, const double2* b_full,
                                  double kappa, double coeff, int mode, double dt, void* out, int layout,
                                  hipStream_t s) {
   const int nb = sb_blocks(g);
+  int bps, tgrp;
+  sb_order(g, bps, tgrp);
   if (layout == kCanonical)
     hipLaunchKernelGGL((k_bilinear_sb<kCanonical>), dim3(nb), dim3(256), 0, s, g, U, a_full, b_full, kappa, coeff,
-                       mode, dt, (double2*)out);
+                       mode, dt, (double2*)out, bps, tgrp);
   else
     hipLaunchKernelGGL((k_bilinear_sb<kPacked>), dim3(nb), dim3(256), 0, s, g, U, a_full, b_full, kappa, coeff,
-                       mode, dt, (double2*)out);
+                       mode, dt, (double2*)out, bps, tgrp);
   return hipGetLastError();
 }
 
@@ -309,11 +337,11 @@ __global__ __launch_bounds__(256) void k_gauge_force(Geom g, const double2* __re
 // at most the running sum, one partial product and two links are live.
 template <int LAYOUT>
 __global__ __launch_bounds__(256) void k_gauge_force_sb(Geom g, const double2* __restrict__ U, double beta,
-                                                        int mode, double dt, double2* out) {
+                                                        int mode, double dt, double2* out, int bps, int tgrp) {
   __shared__ double2 sh[LAYOUT == kCanonical ? kSB : 1][36];
   __shared__ int sh_site[kSB];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int p = lb & 1, blk = lb >> 1;
+  const int p = lb & 1, blk = site_block(lb, bps, tgrp);
   const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
   const int cb = blk * kSB + lane;
   const bool active = cb < g.vh;
@@ -351,12 +379,14 @@ __global__ __launch_bounds__(256) void k_gauge_force_sb(Geom g, const double2* _
 hipError_t launch_gauge_force(const Geom& g, const double2* U, double beta, int mode, double dt, void* out,
                               int layout, hipStream_t s) {
   const int nb = sb_blocks(g);
+  int bps, tgrp;
+  sb_order(g, bps, tgrp);
   if (layout == kCanonical)
     hipLaunchKernelGGL((k_gauge_force_sb<kCanonical>), dim3(nb), dim3(256), 0, s, g, U, beta, mode, dt,
-                       (double2*)out);
+                       (double2*)out, bps, tgrp);
   else
     hipLaunchKernelGGL((k_gauge_force_sb<kPacked>), dim3(nb), dim3(256), 0, s, g, U, beta, mode, dt,
-                       (double2*)out);
+                       (double2*)out, bps, tgrp);
   return hipGetLastError();
 }
 

@@ -129,6 +129,8 @@ inline int reduce_capacity(int vh) {
 hipError_t launch_pack(const Geom& g, int nc, const double2* canon, double2* out64, float2* out32,
                        int* nonfinite, hipStream_t s);
 hipError_t launch_unpack(const Geom& g, int nc, const double2* packed, double2* canon, hipStream_t s);
+// Pi = i sum_a c_a T_a per link from normals [V][4][8] (canonical output)
+hipError_t launch_momenta(const Geom& g, const double* normals, double2* P, hipStream_t s);
 
 // Hop variants (kernels_hop.hip).  p_out in {0,1}: one parity; -1: both.
 // out = self + coef * H in   (self may be null); T: spinor storage type

@@ -1,6 +1,6 @@
-// Solver driver: A X = phi with A = D^dag D (eq. S3.5), X = chi, Y = D X.
+// Solver driver: A X = phi with A = D^dag D (eq. S3.6), X = chi, Y = D X.
 //
-// Method (the paper only says "e.g. via conjugate gradient"; the solve is
+// Method (the paper names conjugate gradient only as an example; the solve is
 // not differentiated): two even/odd Schur-complement solves,
 //     D^dag Y = phi,   D X = Y,
 // each written as M z = b with M = D or D^dag = 1 - kappa H^(dag):

@@ -7,8 +7,10 @@ stout^n of them), run one molecular-dynamics trajectory with
 lgt_md_step_sw (leapfrog for n_inner = 1, Sexton-Weingarten otherwise), and
 accept the new links with probability min(1, exp(-Delta H)).
 
-Random numbers come from a seeded torch generator on the GPU; every step of
-the trajectory runs in liblgt.so.  This module only orchestrates.
+Random numbers come from a seeded torch generator on the GPU (normals for
+the momenta, whose algebra element lgt_momenta_from_normals assembles, and
+for eta); every step of the trajectory runs in liblgt.so.  This module only
+orchestrates (the Metropolis test is a host decision on Delta H).
 """
 from __future__ import annotations
 
@@ -19,21 +21,6 @@ from typing import List, Optional
 import torch
 
 from .api import Lattice, Params
-
-
-def _generators(device) -> torch.Tensor:
-    """T_a = lambda_a / 2 (Gell-Mann), shape (8, 3, 3) complex128."""
-    lam = torch.zeros((8, 3, 3), dtype=torch.complex128)
-    lam[0, 0, 1] = lam[0, 1, 0] = 1
-    lam[1, 0, 1], lam[1, 1, 0] = -1j, 1j
-    lam[2, 0, 0], lam[2, 1, 1] = 1, -1
-    lam[3, 0, 2] = lam[3, 2, 0] = 1
-    lam[4, 0, 2], lam[4, 2, 0] = -1j, 1j
-    lam[5, 1, 2] = lam[5, 2, 1] = 1
-    lam[6, 1, 2], lam[6, 2, 1] = -1j, 1j
-    lam[7, 0, 0] = lam[7, 1, 1] = 1 / math.sqrt(3)
-    lam[7, 2, 2] = -2 / math.sqrt(3)
-    return (lam / 2).to(device)
 
 
 def _site_shape(dims):
@@ -77,12 +64,11 @@ class HMC:
         self.dev = torch.device("cuda")
         self.gen = torch.Generator(device=self.dev)
         self.gen.manual_seed(seed)
-        self.T = _generators(self.dev)
         self.shape = _site_shape(lat.dims)
 
     def momenta(self) -> torch.Tensor:
         c = torch.randn(self.shape + (4, 8), generator=self.gen, dtype=torch.float64, device=self.dev)
-        return (1j * torch.einsum("...a,aij->...ij", c.to(torch.complex128), self.T)).contiguous()
+        return self.lat.momenta_from_normals(c)
 
     def gaussian_spinor(self) -> torch.Tensor:
         re = torch.randn(self.shape + (4, 3), generator=self.gen, dtype=torch.float64, device=self.dev)

@@ -26,7 +26,7 @@ def max_rel_err(got, ref) -> float:
 
 
 def link_errors(got, ref):
-    """Per-link relative Frobenius error of eq. (9): (median, 99th percentile, max)."""
+    """Per-link relative Frobenius error of eq. (8): (median, 99th percentile, max)."""
     num = np.sqrt(np.sum(np.abs(got - ref) ** 2, axis=(-2, -1))).ravel()
     den = np.sqrt(np.sum(np.abs(ref) ** 2, axis=(-2, -1))).ravel()
     e = num / np.where(den > 0, den, 1.0)

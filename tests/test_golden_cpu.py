@@ -46,3 +46,24 @@ def test_stored_gauge_action_recomputes(g):
     # terms raise the plaquette a little (0.785 at eps = 0.3)
     e2 = g["eps"] ** 2
     assert 1 - 3 * e2 < g["mean_plaquette"] < 1 - 2 * e2
+
+
+def test_stored_smeared_trajectory_is_consistent():
+    """The stored 8^3x16 smeared trajectory: the end links are SU(3), the end
+    momenta traceless anti-Hermitian, and the trajectory's H at the start
+    agrees with the heat-bath identity S_f(D(V)^dag eta) = |eta|^2 (the rest
+    of H0 is K + S_G of the stored seeds)."""
+    with open(os.path.join(HERE, "c5_8x8x8x16_smeared_trajectory.json")) as f:
+        g = json.load(f)
+    dims = tuple(g["dims"])
+    u = np.array([[complex(*v) for v in m] for m in g["U"]]).reshape(-1, 3, 3)
+    p = np.array([[complex(*v) for v in m] for m in g["P"]]).reshape(-1, 3, 3)
+    assert su3.unitarity_defect(u) < 1e-13
+    assert np.allclose(np.linalg.det(u), 1.0, atol=1e-13)
+    assert np.allclose(p, -su3.dag(p), atol=1e-14)
+    assert np.allclose(su3.trace(p), 0, atol=1e-14)
+    u0 = li.random_links(dims, g["eps"], g["seeds"]["links"])
+    p0 = li.random_momenta(dims, g["seeds"]["mom"])
+    eta = li.gaussian_spinor(dims, g["seeds"]["eta"])
+    h0 = action.kinetic(p0) + action.gauge_action(u0, g["beta"]) + float(np.vdot(eta.ravel(), eta.ravel()).real)
+    assert abs(g["H0"] - h0) / abs(h0) < 1e-12

@@ -9,7 +9,7 @@ staple force, the bilinear adjoint) are compared on the whole 16^4 lattice
 against the oracle run here.
 
 Force gates (relative Frobenius error over the sampled links, and of the
-full-field norm; the link-level measure of Sec. III A, eq. 9):
+full-field norm; the link-level measure of Sec. III A, eq. 8):
 * FP64 path, and mixed precision driven to the same FP64 true residual
   (1e-14): 1e-12;
 * mixed precision at an outer tolerance of 1e-11: 1e-9.  At the workloads'

@@ -281,3 +281,18 @@ def test_error_paths(lgt):
     # the context still works after errors
     X, _, st = lat.cg_solve(U, to_dev(eta), 0.12, lgt.Params(tol=1e-10))
     assert st["true_rel_residual"] <= 1e-10
+
+
+def test_momenta_from_normals(lgt, margin):
+    """HMC momentum refresh in the library: P = i sum_a c_a T_a from the same
+    normals the input generator draws, against its complex128 construction."""
+    import torch
+    dims = (4, 4, 6, 8)
+    c = np.random.Generator(np.random.PCG64(77)).standard_normal(li.lattice_shape(dims) + (4, 8))
+    ref = su3.from_coeffs(c)
+    lat = lgt.Lattice(dims)
+    got = to_host(lat.momenta_from_normals(torch.from_numpy(c).to("cuda")))
+    margin("momenta from normals vs i sum_a c_a T_a", max_rel_err(got, ref), 1e-15)
+    margin("momenta anti-Hermitian", float(np.abs(got + np.conj(np.swapaxes(got, -1, -2))).max()), 1e-15)
+    margin("momenta traceless", float(np.abs(np.trace(got, axis1=-2, axis2=-1)).max()), 1e-15)
+
