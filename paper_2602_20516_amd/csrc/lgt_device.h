@@ -70,6 +70,18 @@ template <> __device__ __forceinline__ C<double> ld_buf<double>(BufRsrc r, unsig
   const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
   return {v.x, v.y};
 }
+// The same with the non-temporal cache policy (cache-policy bit 1, nt): for
+// data a kernel reads once (the links of a hop), so that they do not push
+// the re-read spinors out of L2.
+template <typename R> __device__ __forceinline__ C<R> ld_buf_nt(BufRsrc r, unsigned voff, unsigned soff);
+template <> __device__ __forceinline__ C<float> ld_buf_nt<float>(BufRsrc r, unsigned voff, unsigned soff) {
+  const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 2));
+  return {v.x, v.y};
+}
+template <> __device__ __forceinline__ C<double> ld_buf_nt<double>(BufRsrc r, unsigned voff, unsigned soff) {
+  const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 2));
+  return {v.x, v.y};
+}
 
 // ---------------------------------------------------------------------------
 // Storage types.  A spinor element lives in HBM as R2<R> (the arithmetic
