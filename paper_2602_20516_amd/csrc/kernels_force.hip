@@ -137,6 +137,13 @@ static inline int link_blocks(const Geom& g) { return (2 * g.vh * 4 + 255) / 256
 // ---------------------------------------------------------------------------
 constexpr int kSB = 64;  // sites per block
 
+// non-temporal store of one complex double
+typedef double v2d __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_nt2(double2* q, double x, double y) {
+  const v2d v = {x, y};
+  __builtin_nontemporal_store(v, reinterpret_cast<v2d*>(q));
+}
+
 // Site block of logical block lb: parity lb & 1, block lb >> 1, taken in
 // the t-fastest order of the hop kernel (groups of tgrp t-slices of bps
 // blocks each; tgrp = 0: site order), so that a block's t-neighbour links
@@ -171,7 +178,7 @@ __device__ __forceinline__ void emit_block(const Geom& g, double2* out, int p, i
       for (int k = 0; k < 9; ++k) {
         double2* q = out + ((size_t)(p * 4 + mu) * 9 + k) * g.vh + cb;
         if (mode == 2) st<double>(q, ld<double>(q) - dt * M.m[k]);
-        else st<double>(q, M.m[k]);
+        else st_nt2(q, M.m[k].re, M.m[k].im);
       }
     }
     return;
@@ -190,7 +197,7 @@ __device__ __forceinline__ void emit_block(const Geom& g, double2* out, int p, i
       const double2 o = *q;
       *q = make_double2(o.x - dt * v.x, o.y - dt * v.y);
     } else {
-      *q = v;
+      st_nt2(q, v.x, v.y);  // written once: kept out of the caches the inputs use
     }
   }
 }
@@ -271,7 +278,13 @@ __global__ __launch_bounds__(256) void k_bilinear_sb(Geom g, const double2* __re
   if (mode == 1) {
     M = mscale(-coeff * kappa * sbc, mdag(Z));
   } else {
-    const M3<double> Ux = load_m3<double>(gptr<double>(U, g, p, mu), vh, cbx);
+    // each link is read once here: streamed past the caches (non-temporal)
+    // so that the neighbour spinors stay in them
+    M3<double> Ux;
+    const BufRsrc ru = make_rsrc(gptr<double>(U, g, p, mu), (size_t)9 * vh * sizeof(double2));
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      Ux.m[k] = ld_buf_nt<double>(ru, (unsigned)cbx * (unsigned)sizeof(double2), (unsigned)(k * vh * sizeof(double2)));
     M = mscale(0.5 * coeff * kappa * sbc, proj_ta(mmul(Ux, Z)));
   }
   emit_block<LAYOUT>(g, out, p, blk, lane, mu, mode, dt, M, active, lex_of(g, c), sh, sh_site);
