@@ -899,8 +899,10 @@ def bench_c5(args):
     t_eq = float(np.median(times))
     return {
         "metric": "smeared HMC trajectory ms at 32^3x64 (10 leapfrog steps, 2 stout levels)",
-        "value": round(t_eq * 1e3, 1), "unit": "ms/trajectory", "n_gpus": 1, "steps": len(times), "warmup": 0,
-        "ms_per_step": round(t_eq * 1e3, 1), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "value": round(t * 1e3, 1), "unit": "ms/trajectory", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(t * 1e3, 1), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "value_note": "the trajectory from the seeded inputs; trajectories on a thermalised background are in "
+                      "thermalised_background (the smeared operator is supercritical there)",
         "dtype": "f32+f64 (FP32 inner CG, FP64 forces, smearing, integrator)",
         "data": "synthetic (seeded SU(3) links eps=0.2, Gaussian eta and momenta)",
         "config": {"workload": "32^3x64, beta 6.0, kappa 0.135, stout rho 0.1 x 2, tau 1, 10 steps, FP64 true "
@@ -912,9 +914,10 @@ def bench_c5(args):
                                                   "summary": rq.summary(), "plaquette": plaq_th,
                                                   "smeared_plaquette": plaq_sm,
                                                   "mean_field_kappa_c_smeared": kappa_c},
-                                   "note": "value = median over these trajectories (dt 0.1, 10 steps, Metropolis), "
-                                           "run on a gauge background thermalised at beta 6 by quenched molecular "
-                                           "dynamics from the seeded links"},
+                                   "note": "trajectories at dt 0.1, 10 steps, Metropolis, on a gauge background "
+                                           "thermalised at beta 6 by quenched molecular dynamics from the seeded "
+                                           "links; the mean-field kappa_c of the smeared operator there is below "
+                                           "the workload's kappa"},
         "seeded_start": {"ms": round(t * 1e3, 1), "dH": dh, "dH_reversed": dh_back, "reversibility_rel_U": rev_u,
                          "reversibility_rel_P": rev_p, "iters": st["iters"],
                          "reliable_updates": st["reliable_updates"],

@@ -71,6 +71,84 @@ struct EpiAxpy {  // out = self + coef * acc
   }
 };
 
+// First hop of a CG iteration with the previous iteration's step folded in
+// (FP64 and FP32-stored recursions).  Every block first sums the |r|^2
+// partials the previous iteration's last hop wrote (same partials, same
+// order: every block takes the same decision) into rr, beta = rr / rr_prev
+// and the stop test; block 0 records the state and posts to the mailbox.
+// If the recursion goes on, the hop runs on r instead of p, using
+// H p_new = H (r + beta p) = H r + beta H p, with H p the t of the previous
+// iteration (kept in t, which the iteration's second use of the even half
+// does not overwrite), and each thread updates p = r + beta p at the odd
+// sites of its own (site, spin): the hop reads only r, so the update races
+// with no reader.  One launch and one pass over r and p fewer per iteration
+// than a separate step kernel.  A launch finding the solve stopped returns
+// (block 0 turns kDoneUpdate into kDoneUpdateHeld and repeats the action).
+template <typename R>
+struct EpiStep {
+  static constexpr bool kReduce = false;
+  R2<R>* t;         // even half: H p, updated in place
+  R2<R>* p;         // odd half: search direction
+  const R2<R>* r;   // odd half: residual (the hop's input)
+  int vh;
+  SolverState* state;
+  const double* partials;
+  int nblk;
+  Mailbox* mb;
+  __device__ static double& beta_sh() {
+    __shared__ double b;
+    return b;
+  }
+  __device__ bool skip() const {  // block-collective: every thread of the block calls it
+    __shared__ int s_run;
+    SolverState* st = state;
+    const int done0 = st->done;
+    if (done0 != kDoneRunning) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (done0 == kDoneUpdate) st->done = kDoneUpdateHeld;
+        post_progress(mb, st->iter, action_word(st->epoch, done0 == kDoneUpdateHeld ? kDoneUpdate : done0));
+      }
+      return true;
+    }
+    double tot[1];
+    sum_partials<256, 1>(partials, nblk, tot);
+    if (threadIdx.x == 0) {
+      const double rr = tot[0];
+      const double beta = rr / st->rr_prev;
+      const int iter = st->iter_prev + 1;
+      const double rr_max = fmax(st->rr_max, rr);
+      int code = kDoneRunning;
+      if (!isfinite(rr)) code = kDoneBreakdown;
+      else if (rr <= st->rr_stop) code = st->delta2 > 0.0 ? kDoneUpdate : kDoneConverged;
+      else if (rr <= st->delta2 * rr_max) code = kDoneUpdate;
+      else if (iter >= st->max_iter) code = kDoneMaxIter;
+      beta_sh() = beta;
+      s_run = code == kDoneRunning;
+      if (blockIdx.x == 0) {
+        st->beta = beta;
+        st->rr = rr;
+        st->iter = iter;
+        st->rr_max = rr_max;
+        if (code != kDoneRunning) st->done = code;
+        post_progress(mb, iter, code != kDoneRunning ? action_word(st->epoch, code) : 0u);
+      }
+    }
+    __syncthreads();
+    return !s_run;
+  }
+  __device__ void apply(int, int cb, int spin, const C<R>* acc, double&) const {
+    const R b = R(beta_sh());
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const size_t o = (size_t)(3 * spin + i) * vh + cb;
+      lgt::st<R>(t + o, acc[i] + b * ld<R>(t + o));
+      lgt::st<R>(p + o, ld<R>(r + o) + b * ld<R>(p + o));
+    }
+  }
+  template <int NT>
+  __device__ void tail() const {}
+};
+
 template <typename R, typename T>
 struct EpiSchurNorm {  // w = x + coef * acc (odd sites), block partials of |w|^2 (of w as stored)
   static constexpr bool kReduce = true;
@@ -346,6 +424,31 @@ hipError_t launch_hop_residual(const Geom& g, HopIn<double> hin, const double2* 
   if (err != hipSuccess) return err;
   return launch_finalize(kFinResult1, 2 * nblk_parity(g), red, nullptr, slot, 0.0, 0, s);
 }
+
+template <typename R, bool DAG>
+hipError_t launch_hop_step(const Geom& g, const R2<R>* gauge, int nk, R2<R>* t, R2<R>* p, const R2<R>* r,
+                           SolverState* st, Reduce red, hipStream_t s) {
+  EpiStep<R> e;
+  e.t = t;
+  e.p = p;
+  e.r = r;
+  e.vh = g.vh;
+  e.state = st;
+  e.partials = red.partials;
+  e.nblk = nblk_parity(g);
+  e.mb = red.mbox;
+  if (e.nblk > red.capacity) return hipErrorInvalidValue;
+  const HopIn<R> hin{gauge, r, r, nk};
+  return launch<R, DAG>(g, 0, hin, e, nullptr, s);
+}
+template hipError_t launch_hop_step<double, false>(const Geom&, const double2*, int, double2*, double2*,
+                                                   const double2*, SolverState*, Reduce, hipStream_t);
+template hipError_t launch_hop_step<double, true>(const Geom&, const double2*, int, double2*, double2*,
+                                                  const double2*, SolverState*, Reduce, hipStream_t);
+template hipError_t launch_hop_step<float, false>(const Geom&, const float2*, int, float2*, float2*,
+                                                  const float2*, SolverState*, Reduce, hipStream_t);
+template hipError_t launch_hop_step<float, true>(const Geom&, const float2*, int, float2*, float2*, const float2*,
+                                                 SolverState*, Reduce, hipStream_t);
 
 #define LGT_INST_AXPY(R, DAG, T)                                                                          \
   template hipError_t launch_hop_axpy<R, DAG, T>(const Geom&, int, HopIn<R, T>, T*, T*, const T*, const T*, \

@@ -142,6 +142,13 @@ hipError_t launch_hop_axpy(const Geom& g, int p_out, HopIn<R, T> hin, T* out_eve
                            const typename NoDeduce<T>::type* self_even, const typename NoDeduce<T>::type* self_odd,
                            double coef, hipStream_t s, SolverState* guard = nullptr,
                            const double* pap_partials = nullptr);
+// t = H (r + beta p) = H r + beta t and p = r + beta p, after the CG step of
+// the previous iteration (every block: beta and the stop test from its |r|^2
+// partials; block 0 records the state); a no-op once the solve has stopped.
+// For R2<R> storage (FP64, FP32).
+template <typename R, bool DAG>
+hipError_t launch_hop_step(const Geom& g, const R2<R>* gauge, int nk, R2<R>* t, R2<R>* p, const R2<R>* r,
+                           SolverState* st, Reduce red, hipStream_t s);
 // One CG iteration on Mhat^dag Mhat (Mhat = 1 - kappa^2 H_oe H_eo, odd sites)
 // is four hop launches and the step kernel:
 //  (1) t = H p                                      launch_hop_axpy (guard)

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "lgt_ctx.h"
 
@@ -104,33 +105,55 @@ void lgt_ctx::apply_mhat_dag_mhat64(bool dag, const double2* x, double2* out) {
   }
 }
 
-// One CG iteration on Mhat^dag Mhat: four hop launches and the step kernel
-// (scalars, stop test, direction update).  t, w, p stored as T; x, r as R2<R>.
+// Largest half volume on which the CG step is folded into the first hop:
+// there the iteration is bound by its launches (16^4: 5.96 -> 5.35 ms per
+// mixed force call, FP64 8.48 -> 7.95 ms); on larger lattices every block of
+// the first hop re-reading all the |r|^2 partials and the extra t, p traffic
+// cost more than the launch saved (24^3x48: 71 -> 81 ms).
+constexpr int kFuseStepMaxVh = 65536;
+
+// One CG iteration on Mhat^dag Mhat.  t, w, p stored as T; x, r as R2<R>.
+// FP64 and FP32 storage on small lattices: four hop launches, the first of
+// which also does the previous iteration's step (scalars, stop test,
+// p = r + beta p; see EpiStep), except in a fresh iteration (the first of a
+// solve and the first after a reliable update, where p has just been set):
+// there the first hop is a plain t = H p.  t keeps H p for the next
+// iteration's step, so the third hop writes t2.  Otherwise: the four hops
+// and a separate step kernel.
 template <typename R, typename T, bool DAG>
-static void cg_iteration(const Geom& g, const R2<R>* gauge, double kappa, T* t, T* w, R2<R>* x, R2<R>* r, T* p,
-                         SolverState* st, Reduce red, hipStream_t s, int n, int nk = 9) {
+static void cg_iteration(const Geom& g, const R2<R>* gauge, double kappa, T* t, T* t2, T* w, R2<R>* x, R2<R>* r,
+                         T* p, SolverState* st, Reduce red, hipStream_t s, int n, bool fresh, int nk = 9) {
   const double k2 = -kappa * kappa;
-  LGT_HIP((launch_hop_axpy<R, DAG, T>(g, 0, HopIn<R, T>{gauge, p, p, nk}, t, t, nullptr, nullptr, 1.0, s, st)));
+  constexpr bool kFused = std::is_same<T, R2<R>>::value;
+  const bool fuse = kFused && g.vh <= kFuseStepMaxVh;
+  if (fuse && !fresh) {
+    if constexpr (kFused) LGT_HIP((launch_hop_step<R, DAG>(g, gauge, nk, t, p, r, st, red, s)));
+  } else {
+    LGT_HIP((launch_hop_axpy<R, DAG, T>(g, 0, HopIn<R, T>{gauge, p, p, nk}, t, t, nullptr, nullptr, 1.0, s, st)));
+  }
   LGT_HIP((launch_hop_schur_norm<R, T, DAG>(g, HopIn<R, T>{gauge, t, t, nk}, w, p, k2, st, red, s)));
   // block 0 also forms alpha from the |w|^2 partials
-  LGT_HIP((launch_hop_axpy<R, !DAG, T>(g, 0, HopIn<R, T>{gauge, w, w, nk}, t, t, nullptr, nullptr, 1.0, s, st,
+  LGT_HIP((launch_hop_axpy<R, !DAG, T>(g, 0, HopIn<R, T>{gauge, w, w, nk}, t2, t2, nullptr, nullptr, 1.0, s, st,
                                          red.partials)));
-  LGT_HIP((launch_hop_schur_cg<R, T, !DAG>(g, HopIn<R, T>{gauge, t, t, nk}, w, x, r, p, k2, st, red, s)));
-  LGT_HIP((launch_cg_step<R, T>(n, r, p, st, red, hop_blocks(g, 1), s)));
+  LGT_HIP((launch_hop_schur_cg<R, T, !DAG>(g, HopIn<R, T>{gauge, t2, t2, nk}, w, x, r, p, k2, st, red, s)));
+  if (!fuse) LGT_HIP((launch_cg_step<R, T>(n, r, p, st, red, hop_blocks(g, 1), s)));
 }
 
 // CG on Mhat^dag Mhat z = rhs (odd half fields), FP64.  Returns the state's done code.
 int lgt_ctx::cg_normal64(bool dag, double2* z, const double2* rhs, double tol, int max_iter, SolveStats& stt) {
   const int n = (int)half_elems();
   double2* t = f64(kW0);
+  double2* t2 = f64(kW1);  // even half (the odd half holds rhs)
   double2* r = f64(kW2) + half_elems();
   double2* p = f64(kW3) + half_elems();
   double2* w = f64(kW4) + half_elems();
   LGT_HIP(launch_cg_init<double>(n, rhs, r, p, z, state, red(), tol, max_iter, stream));
+  bool fresh = true;
   for (int iter0 = 0;;) {
     drive(iter0, [&] {
-      if (dag) cg_iteration<double, double2, true>(g, U64, kappa, t, w, z, r, p, state, red(), stream, n);
-      else cg_iteration<double, double2, false>(g, U64, kappa, t, w, z, r, p, state, red(), stream, n);
+      if (dag) cg_iteration<double, double2, true>(g, U64, kappa, t, t2, w, z, r, p, state, red(), stream, n, fresh);
+      else cg_iteration<double, double2, false>(g, U64, kappa, t, t2, w, z, r, p, state, red(), stream, n, fresh);
+      fresh = false;
     });
     LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
     sync();
@@ -173,6 +196,7 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
   float2* xs = h32(2);
   float2* rs = h32(3);
   T* ps = reinterpret_cast<T*>(h32(4));
+  T* ts2 = std::is_same<T, float2>::value ? reinterpret_cast<T*>(h32(5)) : ts;
   double2* r64 = f64(kW2) + half_elems();
   LGT_HIP(launch_zero64(n, z, stream));
   compress_links();
@@ -209,10 +233,12 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
   // resumes the recursion or ends the solve.
   unsigned min_epoch = 0;
   int iter0 = 0;
+  bool fresh = true;  // p has just been set: the next iteration's first hop is a plain t = H p
   for (;;) {
     const unsigned long long v = drive(iter0, [&] {
-      if (dag) cg_iteration<float, T, true>(g, links, kappa, ts, ws, xs, rs, ps, state, red(), stream, n, nk);
-      else cg_iteration<float, T, false>(g, links, kappa, ts, ws, xs, rs, ps, state, red(), stream, n, nk);
+      if (dag) cg_iteration<float, T, true>(g, links, kappa, ts, ts2, ws, xs, rs, ps, state, red(), stream, n, fresh, nk);
+      else cg_iteration<float, T, false>(g, links, kappa, ts, ts2, ws, xs, rs, ps, state, red(), stream, n, fresh, nk);
+      fresh = false;
     }, min_epoch, false);
     unsigned act = (unsigned)(v >> 32);
     int dev_iter = (int)(unsigned)v;
@@ -236,6 +262,7 @@ int lgt_ctx::cg_normal_mixed(bool dag, double2* z, const double2* rhs, double to
       LGT_HIP(launch_rescale_residual_dev<T>(n, r64, rs, ps, state, stream));
       min_epoch = (act >> 8) + 1;
       iter0 = dev_iter;
+      fresh = true;
       continue;
     }
     if (code == kDoneMaxIter) LGT_HIP(launch_mixed_fold(n, xs, z, state, stream));
