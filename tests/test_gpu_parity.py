@@ -133,6 +133,32 @@ def test_gauge_force(lgt, dims, mode, margin):
     margin("rel_err(got, ref)", rel_err(got, ref), 1e-13)
 
 
+@pytest.mark.parametrize("mode", ["force", "momentum"])
+def test_gauge_force_tiled_16x16x32x64(lgt, mode, margin):
+    """Staple force on 16x16x32x64 (the block order of large lattices) with
+    the links of a seeded 8^4 field repeated periodically: the force at every
+    site is the oracle's 8^4 force at the site modulo 8 (no boundary sign)."""
+    say("gauge tiled 16x16x32x64", mode)
+    small = (8, 8, 8, 8)
+    u8, _ = fields(small, eps=0.3, seed=41)
+    beta, dt = 6.0, 0.05
+    reps = (64 // 8, 32 // 8, 16 // 8, 16 // 8, 1, 1, 1)
+    ref8 = force.gauge_force(u8, beta)
+    lat = lgt.Lattice((16, 16, 32, 64))
+    U = to_dev(np.tile(u8, reps))
+    if mode == "force":
+        got = to_host(lat.gauge_force(U, beta, "force"))
+        ref = np.tile(ref8, reps)
+    else:
+        p = li.random_momenta((16, 16, 32, 64), 43)
+        P = to_dev(p)
+        lat.gauge_force(U, beta, "momentum", dt, out=P)
+        got = to_host(P)
+        ref = p - dt * np.tile(ref8, reps)
+    margin("rel_err(got, ref)", rel_err(got, ref), 1e-13)
+    margin("max_rel_err(got, ref)", max_rel_err(got, ref), 1e-13)
+
+
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 6, 6, 6)])
 def test_gauge_action_and_kinetic(lgt, dims, margin):
     u, _ = fields(dims)
