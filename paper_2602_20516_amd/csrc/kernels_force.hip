@@ -160,25 +160,6 @@ __device__ __forceinline__ int site_block(int lb, int bps, int tgrp) {
   return blk;
 }
 
-// Site block of logical block lb in the staple force's order on large
-// lattices whose (x, y) plane holds a whole number nyc of blocks: t fastest
-// within groups of 4 t-slices, then z within groups of 4 planes, then the
-// nyc blocks of a plane, then the z groups, then the t groups.  A block's t
-// and z neighbours were then read at most a few dozen blocks earlier on the
-// same XCD.
-__device__ __forceinline__ int site_block_tz(int lb, int nyc, int lz) {
-  int r = lb >> 1;
-  const int t_in = r & 3;
-  r >>= 2;
-  const int z_in = r & 3;
-  r >>= 2;
-  const int yc = r % nyc;
-  r /= nyc;
-  const int nzg = lz >> 2;
-  const int zo = r % nzg, to = r / nzg;
-  return ((to * 4 + t_in) * lz + zo * 4 + z_in) * nyc + yc;
-}
-
 __device__ __forceinline__ int lex_of(const Geom& g, const int c[4]) {
   return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
 }
@@ -367,15 +348,13 @@ __global__ __launch_bounds__(256) void k_gauge_force(Geom g, const double2* __re
 // The staple force in site-block form (see k_bilinear_sb): each thread sums
 // the six staples of its link one at a time, each as two 3x3 products, so
 // at most the running sum, one partial product and two links are live.
-// nyc > 0: blocks in site_block_tz order, else in site_block order.
 template <int LAYOUT>
 __global__ __launch_bounds__(256) void k_gauge_force_sb(Geom g, const double2* __restrict__ U, double beta,
-                                                        int mode, double dt, double2* out, int bps, int tgrp,
-                                                        int nyc) {
+                                                        int mode, double dt, double2* out, BlockOrder order) {
   __shared__ double2 sh[LAYOUT == kCanonical ? kSB : 1][36];
   __shared__ int sh_site[kSB];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int p = lb & 1, blk = nyc > 0 ? site_block_tz(lb, nyc, g.L[2]) : site_block(lb, bps, tgrp);
+  const int p = lb & 1, blk = gauge_site_block(lb, order, g.L[2]);
   const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
   const int cb = blk * kSB + lane;
   const bool active = cb < g.vh;
@@ -413,17 +392,13 @@ __global__ __launch_bounds__(256) void k_gauge_force_sb(Geom g, const double2* _
 hipError_t launch_gauge_force(const Geom& g, const double2* U, double beta, int mode, double dt, void* out,
                               int layout, hipStream_t s) {
   const int nb = sb_blocks(g);
-  int bps, tgrp;
-  sb_order(g, bps, tgrp);
-  // 32^3x64: 1501 -> 1374 us in this order (unrolled staple loop: 1322 us)
-  const int plane = g.hx * g.L[1];
-  const int nyc = (tgrp > 0 && plane % kSB == 0 && g.L[2] % 4 == 0 && g.L[3] % 4 == 0) ? plane / kSB : 0;
+  const BlockOrder order = gauge_block_order(g);
   if (layout == kCanonical)
     hipLaunchKernelGGL((k_gauge_force_sb<kCanonical>), dim3(nb), dim3(256), 0, s, g, U, beta, mode, dt,
-                       (double2*)out, bps, tgrp, nyc);
+                       (double2*)out, order);
   else
     hipLaunchKernelGGL((k_gauge_force_sb<kPacked>), dim3(nb), dim3(256), 0, s, g, U, beta, mode, dt,
-                       (double2*)out, bps, tgrp, nyc);
+                       (double2*)out, order);
   return hipGetLastError();
 }
 

@@ -19,43 +19,117 @@
 
 namespace lgt {
 
-// exp(A) and L(A, E) = d/dt exp(A + t E)|_0 for a 3x3 complex A: Taylor
-// series of order 16 on A/2^s, E/2^s (||A/2^s||_F <= 1/2, remainder below
-// 1e-19), then s doubling steps exp(2A) = exp(A)^2,
-// L(2A, 2E) = exp(A) L(A,E) + L(A,E) exp(A).
-__device__ __forceinline__ void exp_frechet(const M3<double>& A, const M3<double>& E, M3<double>& F,
-                                            M3<double>& L) {
-  double n2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) n2 += norm2(A.m[k]);
-  double nrm = sqrt(n2);
+// exp(X) = f0 + f1 X + f2 X^2 for a traceless 3x3 X, by Cayley-Hamilton
+// (X^3 = c1 X + c0 with c1 = tr(X^2)/2, c0 = det X = tr(X^3)/3), with the
+// derivatives df_j/dc0 and df_j/dc1: the Taylor polynomial of order 16 of
+// exp(X/2^s), ||X/2^s||_F <= 1/2 (remainder below 1e-19), carried in the
+// basis {1, X, X^2} as scalar recurrences -- X^(k+1) = c0 z + (x + c1 z) X
+// + y X^2 for X^k = x + y X + z X^2 -- differentiated forward in c0 and c1,
+// then squared s times in the same basis.  The truncation is that of the
+// matrix series; no 3x3 products are needed.
+struct ChCoef {
+  C<double> f[3], d0[3], d1[3];
+};
+__device__ __forceinline__ ChCoef exp_ch(C<double> c0, C<double> c1, double nrm) {
   int s = 0;
   while (nrm > 0.5 && s < 40) {
     nrm *= 0.5;
     ++s;
   }
   const double sc = ldexp(1.0, -s);
-  const M3<double> As = mscale(sc, A), Es = mscale(sc, E);
-  M3<double> T = mident<double>(), N, Fs = mident<double>(), Ls;
+  C<double> p[3] = {cmk(1.0, 0.0), czero<double>(), czero<double>()};
+  C<double> q0[3] = {czero<double>(), czero<double>(), czero<double>()};
+  C<double> q1[3] = {czero<double>(), czero<double>(), czero<double>()};
+  ChCoef r;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    r.f[j] = p[j];
+    r.d0[j] = czero<double>();
+    r.d1[j] = czero<double>();
+  }
+#pragma unroll
+  for (int k = 1; k <= 16; ++k) {
+    const double h = sc / double(k);
+    const C<double> x = p[0], y = p[1], z = p[2];
+    p[0] = h * (c0 * z);
+    p[1] = h * (x + c1 * z);
+    p[2] = h * y;
+    const C<double> x0 = q0[0], y0 = q0[1], z0 = q0[2];
+    q0[0] = h * (z + c0 * z0);
+    q0[1] = h * (x0 + c1 * z0);
+    q0[2] = h * y0;
+    const C<double> x1 = q1[0], y1 = q1[1], z1 = q1[2];
+    q1[0] = h * (c0 * z1);
+    q1[1] = h * (x1 + z + c1 * z1);
+    q1[2] = h * y1;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      r.f[j] += p[j];
+      r.d0[j] += q0[j];
+      r.d1[j] += q1[j];
+    }
+  }
+  // (a0 + a1 X + a2 X^2)^2 = b0 + b1 X + b2 X^2 with X^3 = c1 X + c0, X^4 = c1 X^2 + c0 X
+  for (int j = 0; j < s; ++j) {
+    const C<double> a0 = r.f[0], a1 = r.f[1], a2 = r.f[2];
+    const C<double> a12 = a1 * a2, a22 = a2 * a2;
+    const C<double> e0 = r.d0[0], e1 = r.d0[1], e2 = r.d0[2];
+    const C<double> g0 = r.d1[0], g1 = r.d1[1], g2 = r.d1[2];
+    const C<double> de12 = e1 * a2 + a1 * e2, dg12 = g1 * a2 + a1 * g2;
+    const C<double> de22 = 2.0 * (a2 * e2), dg22 = 2.0 * (a2 * g2);
+    r.f[0] = a0 * a0 + 2.0 * (a12 * c0);
+    r.f[1] = 2.0 * (a0 * a1) + 2.0 * (a12 * c1) + a22 * c0;
+    r.f[2] = a1 * a1 + 2.0 * (a0 * a2) + a22 * c1;
+    r.d0[0] = 2.0 * (a0 * e0) + 2.0 * (de12 * c0) + 2.0 * a12;
+    r.d0[1] = 2.0 * (e0 * a1 + a0 * e1) + 2.0 * (de12 * c1) + de22 * c0 + a22;
+    r.d0[2] = 2.0 * (a1 * e1) + 2.0 * (e0 * a2 + a0 * e2) + de22 * c1;
+    r.d1[0] = 2.0 * (a0 * g0) + 2.0 * (dg12 * c0);
+    r.d1[1] = 2.0 * (g0 * a1 + a0 * g1) + 2.0 * (dg12 * c1) + 2.0 * a12 + dg22 * c0;
+    r.d1[2] = 2.0 * (a1 * g1) + 2.0 * (g0 * a2 + a0 * g2) + dg22 * c1 + a22;
+  }
+  return r;
+}
+
+// For anti-Hermitian traceless X and the cotangent GE of E = exp(X):
+// Einv = E^dag = exp(-X), and GX, whose traceless anti-Hermitian part is
+// that of the adjoint Frechet derivative L(X^dag, GE).  With
+// d exp(X)[dX] = sum_j (df_j/dc0 dc0 + df_j/dc1 dc1) X^j + f1 dX + f2 (dX X + X dX)
+// and, for traceless dX, dc0 = tr(X^2 dX), dc1 = tr(X dX):
+//   GX = conj(k0) X^2 - conj(k1) X + conj(f1) GE - conj(f2) (GE X + X GE),
+//   k_i = sum_j tr(GE^dag X^j) df_j/dc_i.
+__device__ __forceinline__ void exp_adjoint_ah(const M3<double>& X, const M3<double>& GE, M3<double>& Einv,
+                                               M3<double>& GX) {
+  const M3<double> X2 = mmul(X, X);
+  C<double> c1 = czero<double>(), c0 = czero<double>(), g0 = czero<double>(), g1 = czero<double>(),
+            g2 = czero<double>();
+  double n2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    c1 += X2.m[4 * i];
+    g0 += conj(GE.m[4 * i]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      c0 += X2.m[3 * i + j] * X.m[3 * j + i];
+      g1 += cjmul(GE.m[3 * i + j], X.m[3 * i + j]);
+      g2 += cjmul(GE.m[3 * i + j], X2.m[3 * i + j]);
+      n2 += norm2(X.m[3 * i + j]);
+    }
+  }
+  c1 = 0.5 * c1;
+  c0 = (1.0 / 3.0) * c0;
+  const ChCoef ch = exp_ch(c0, c1, sqrt(n2));
+  const C<double> k0 = g0 * ch.d0[0] + g1 * ch.d0[1] + g2 * ch.d0[2];
+  const C<double> k1 = g0 * ch.d1[0] + g1 * ch.d1[1] + g2 * ch.d1[2];
+  const C<double> a = conj(k0), b = -conj(k1), f1 = conj(ch.f[1]), f2 = -conj(ch.f[2]);
+  const M3<double> GX1 = mmul(GE, X), GX2 = mmul(X, GE);
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    N.m[k] = czero<double>();
-    Ls.m[k] = czero<double>();
+    GX.m[k] = a * X2.m[k] + b * X.m[k] + f1 * GE.m[k] + f2 * (GX1.m[k] + GX2.m[k]);
+    Einv.m[k] = conj(ch.f[2]) * X2.m[k] - conj(ch.f[1]) * X.m[k];
   }
-  for (int k = 0; k < 16; ++k) {
-    const double inv = 1.0 / double(k + 1);
-    const M3<double> Nn = mscale(inv, madd(mmul(As, N), mmul(Es, T)));
-    T = mscale(inv, mmul(As, T));
-    N = Nn;
-    Fs = madd(Fs, T);
-    Ls = madd(Ls, N);
-  }
-  for (int j = 0; j < s; ++j) {
-    Ls = madd(mmul(Fs, Ls), mmul(Ls, Fs));
-    Fs = mmul(Fs, Fs);
-  }
-  F = Fs;
-  L = Ls;
+  const C<double> f0 = conj(ch.f[0]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Einv.m[4 * i] += f0;
 }
 
 struct LinkIdx {
@@ -63,21 +137,18 @@ struct LinkIdx {
   int c[4];
 };
 
-// Thread -> link: a block owns 64 consecutive sites of one parity, wave w
-// the links of direction w there (the four links of a site share most of
-// their staple links), and blocks are numbered XCD-contiguously, so that
+// Thread -> link: a block owns 64 sites of one parity (a site block, in the
+// order of gauge_site_block, parity alternating between blocks), wave w the
+// links of direction w there (the four links of a site share most of their
+// staple links), and blocks are numbered XCD-contiguously, so that
 // neighbouring site blocks -- whose staples read each other's links -- run
-// under the same L2.  (Against one direction per launch segment and
-// round-robin XCDs, this raised the L2 hit rate of the forward kernel from
-// 11 % to 46 % and cut its time 1.6x at 24^3x48; walking each XCD's slab
-// with t fastest gained nothing more.)
+// under the same L2.
 __device__ __forceinline__ bool link_of_thread(const Geom& g, LinkIdx& li) {
-  const int nbp = (g.vh + 63) / 64;
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  li.p = lb / nbp;
-  li.cb = (lb - li.p * nbp) * 64 + (threadIdx.x & 63);
+  li.p = lb & 1;
+  li.cb = gauge_site_block(lb, gauge_block_order(g), g.L[2]) * 64 + (threadIdx.x & 63);
   li.mu = threadIdx.x >> 6;
-  if (li.p > 1 || li.cb >= g.vh) return false;
+  if (li.cb >= g.vh) return false;
   cb_coords(g, li.p, li.cb, li.c);
   return true;
 }
@@ -104,7 +175,7 @@ __global__ __launch_bounds__(256) void k_stout_adj_a(Geom g, const double2* __re
   const M3<double> G1 = load_m3<double>(gptr<double>(Gp, g, li.p, li.mu), vh, li.cb);
   const M3<double> GE = mmul_nd(G1, Ux);  // G' U^dag
   M3<double> Einv, GX;
-  exp_frechet(mscale(-1.0, X), GE, Einv, GX);  // exp(X^dag) = E^dag, L(X^dag, G_E)
+  exp_adjoint_ah(X, GE, Einv, GX);  // E^dag, and L(X^dag, G_E) up to its non-su(3) part
   const M3<double> GOm = proj_ta(GX);
   const M3<double> C = mscale(rho, mdag(A));
   store_m3<double>((double2*)gptr<double>(Lam, g, li.p, li.mu), vh, li.cb, mmul(GOm, Ux));
@@ -140,21 +211,21 @@ __global__ __launch_bounds__(256) void k_stout_adj_b(Geom g, const double2* __re
     shifted(g, y, a, +1, ypa);
     shifted(g, y, m, -1, ymm);
     shifted(g, ymm, a, +1, ymmpa);
+    // the first and third terms of each side share their last factor:
+    // five 3x3 products per side instead of six
     {  // forward side: sites y, y+m, y+a
       const M3<double> Ua_ypm = link_at(U, g, ypm, a);
-      const M3<double> Um_ypa = link_at(U, g, ypa, m);
       const M3<double> Um_y = link_at(U, g, y, m);
-      S = madd(S, mmul(link_at(Lam, g, y, m), mmul_nd(Ua_ypm, Um_ypa)));
+      const M3<double> W = madd(mmul(link_at(Lam, g, y, m), Ua_ypm), mmul(Um_y, link_at(Lam, g, ypm, a)));
+      S = madd(S, mmul_nd(W, link_at(U, g, ypa, m)));
       S = madd(S, mmul_nd(mmul(Um_y, Ua_ypm), link_at(Lam, g, ypa, m)));
-      S = madd(S, mmul_nd(mmul(Um_y, link_at(Lam, g, ypm, a)), Um_ypa));
     }
     {  // backward side: sites y-m, y-m+a
       const M3<double> Ua_ymm = link_at(U, g, ymm, a);
-      const M3<double> Um_ymmpa = link_at(U, g, ymmpa, m);
       const M3<double> Um_ymm = link_at(U, g, ymm, m);
-      S = madd(S, mmul_dn(link_at(Lam, g, ymm, m), mmul(Ua_ymm, Um_ymmpa)));
+      const M3<double> W = madd(mmul_dn(link_at(Lam, g, ymm, m), Ua_ymm), mmul_dn(Um_ymm, link_at(Lam, g, ymm, a)));
+      S = madd(S, mmul(W, link_at(U, g, ymmpa, m)));
       S = madd(S, mmul(mmul_dn(Um_ymm, Ua_ymm), link_at(Lam, g, ymmpa, m)));
-      S = madd(S, mmul(mmul_dn(Um_ymm, link_at(Lam, g, ymm, a)), Um_ymmpa));
     }
   }
   const M3<double> Gx = load_m3<double>(gptr<double>(Gpart, g, li.p, a), g.vh, li.cb);

@@ -6,6 +6,51 @@
 
 namespace lgt {
 
+// Order of the 64-site blocks of the gauge-link kernels (staple force,
+// stout levels; logical block lb, parity lb & 1, so the two parities of a
+// site block run side by side).  On lattices above 131072 sites per parity
+// whose t-slice holds whole blocks: where the (x, y) plane holds nyc whole
+// blocks and Lz, Lt are multiples of 4, t fastest within groups of 4
+// t-slices, then z within groups of 4 planes, then the nyc blocks of a
+// plane, then the z groups, then the t groups; otherwise t fastest within
+// groups of tgrp t-slices of bps blocks.  A block's neighbours in t and z
+// were then read a few dozen blocks earlier on the same XCD (32^3x64, staple
+// force: 1501 -> 1374 us; stout levels 9.3 -> 8.0 ms).
+struct BlockOrder {
+  int bps, tgrp, nyc;
+};
+__host__ __device__ inline BlockOrder gauge_block_order(const Geom& g) {
+  BlockOrder o{0, 0, 0};
+  const int vslice = g.vh / g.L[3];
+  o.bps = vslice / 64;
+  if (vslice % 64 != 0 || o.bps == 0 || g.vh <= 131072) return o;
+  o.tgrp = g.L[3] % 8 == 0 ? 8 : (g.L[3] % 4 == 0 ? 4 : 2);
+  const int plane = g.hx * g.L[1];
+  if (plane % 64 == 0 && g.L[2] % 4 == 0 && g.L[3] % 4 == 0) o.nyc = plane / 64;
+  return o;
+}
+__device__ __forceinline__ int gauge_site_block(int lb, const BlockOrder& o, int lz) {
+  int r = lb >> 1;
+  if (o.nyc > 0) {
+    const int t_in = r & 3;
+    r >>= 2;
+    const int z_in = r & 3;
+    r >>= 2;
+    const int yc = r % o.nyc;
+    r /= o.nyc;
+    const int nzg = lz >> 2;
+    const int zo = r % nzg, to = r / nzg;
+    return ((to * 4 + t_in) * lz + zo * 4 + z_in) * o.nyc + yc;
+  }
+  if (o.tgrp > 0) {
+    const int span = o.tgrp * o.bps;
+    const int grp = r / span, rem = r - grp * span;
+    const int chunk = rem / o.tgrp, tl = rem - chunk * o.tgrp;
+    return (grp * o.tgrp + tl) * o.bps + chunk;
+  }
+  return r;
+}
+
 __device__ __forceinline__ M3<double> link_at(const double2* U, const Geom& g, const int c[4], int mu) {
   return load_m3<double>(gptr<double>(U, g, parity_of(c), mu), g.vh, cb_of(g, c));
 }
