@@ -378,9 +378,9 @@ def kernel_sources_sha(files):
     return h.hexdigest()[:16]
 
 
-def _traffic(name, sources=HOP_SOURCES):
-    """HBM bytes per launch from the committed counter passes of a kernel,
-    or None when the kernel's sources changed since the counters were taken."""
+def _traffic_record(name, sources=HOP_SOURCES):
+    """The committed counter record of a kernel (profiles/<name>), or None when
+    the kernel's sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
@@ -389,10 +389,32 @@ def _traffic(name, sources=HOP_SOURCES):
         return None
     if rec.get("kernel_sources_sha") != kernel_sources_sha(sources):
         return None
-    return rec.get("bytes_per_launch")
+    return rec
 
 
-def _hop_line(lat, U, E, V, prec, nrep=200):
+def _traffic(name, sources=HOP_SOURCES):
+    """HBM bytes per launch from the committed counter passes of a kernel, or None."""
+    rec = _traffic_record(name, sources)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def _with_profile(line, name):
+    """Add the committed record's HBM bytes and its rocprofv3 launch time (and the
+    fraction of the HBM peak that time gives) to a hop roofline line."""
+    rec = _traffic_record(name)
+    line["traffic"] = rec.get("bytes_per_launch") if rec else None
+    if rec and rec.get("avg_duration_us"):
+        t = rec["avg_duration_us"] * 1e-6
+        line["profile"] = f"profiles/{name}"
+        line["profiled_avg_launch_us"] = rec["avg_duration_us"]
+        line["frac_profiled"] = round(line["algorithmic_bytes_per_launch"] / t / 1e9 / HBM_PEAK_GBS, 4)
+    return line
+
+
+HOP_REPS, HOP_REPS_LARGE = 200, 100  # timed hop launches at 16^4 and on the out-of-cache lattices
+
+
+def _hop_line(lat, U, E, V, prec, nrep=HOP_REPS):
     """Roofline figures of the single-field hop: algorithmic bytes are 96 reals
     per lattice site (all 4V links as full 3x3 matrices, input and output half
     spinors); the FP32 kernel reads SU(3) links as two rows (72 reals per
@@ -415,9 +437,8 @@ def _hop_roofline(lat, U, E, V):
             "bytes_model": "96 reals per lattice site (4V links, input and output half spinors)"}
     line.update(_hop_line(lat, U, E, V, "mixed_fp32"))
     name = "x".join(str(d) for d in lat.dims)
-    line["traffic"] = _traffic(f"hop_fp32_{name}_traffic.json")
-    line["fp64"] = _hop_line(lat, U, E, V, "fp64")
-    line["fp64"]["traffic"] = _traffic(f"hop_fp64_{name}_traffic.json")
+    _with_profile(line, f"hop_fp32_{name}_traffic.json")
+    line["fp64"] = _with_profile(_hop_line(lat, U, E, V, "fp64"), f"hop_fp64_{name}_traffic.json")
     line["note"] = ("at 16^4 the hop's 19-50 MB sit in the 256 MB last-level cache; the HBM figures are the "
                     "out_of_cache lines")
     return line
@@ -449,8 +470,8 @@ def _hop_out_of_cache():
                                      tuple(d // 8 for d in dims[::-1]) + (1, 1))).to("cuda")
         lat = lgt.Lattice(dims)
         name = "x".join(str(d) for d in dims)
-        line = _hop_line(lat, U, E, V, prec, 100)
-        line["traffic"] = _traffic(f"hop_{'fp64' if prec == 'fp64' else 'fp32'}_{name}_traffic.json")
+        line = _with_profile(_hop_line(lat, U, E, V, prec, HOP_REPS_LARGE),
+                             f"hop_{'fp64' if prec == 'fp64' else 'fp32'}_{name}_traffic.json")
         out[f"{prec}_{name}"] = line
         del U, E, lat
         torch.cuda.empty_cache()
@@ -458,7 +479,8 @@ def _hop_out_of_cache():
 
 
 def hop_probe(argv):
-    """Launch the hop kernel (20 times) and a 512 MiB device copy, for
+    """Launch the hop kernel (as often as the bench line times it; 20 times for
+    the batched hop) and a 512 MiB device copy, for
     rocprofv3 kernel traces and counter passes: bytes per hop launch =
     counter(hop) / counter(copy) x 512 MiB."""
     import numpy as np
@@ -479,7 +501,9 @@ def hop_probe(argv):
     E = torch.from_numpy(eta).to("cuda")
     lat = lgt.Lattice(dims)
     lat.set_batch_hop_kernel(kind)
-    ms = lat.hop_benchmark_mrhs(U, E, nrhs, prec, 20) if nrhs > 1 else lat.hop_benchmark(U, E, prec, 20)
+    # as many launches as the bench line times, so that the profiled mean matches its HIP-event mean
+    reps = 20 if nrhs > 1 else (HOP_REPS if small else HOP_REPS_LARGE)
+    ms = lat.hop_benchmark_mrhs(U, E, nrhs, prec, reps) if nrhs > 1 else lat.hop_benchmark(U, E, prec, reps)
     a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     for _ in range(5):
