@@ -144,22 +144,6 @@ __device__ __forceinline__ void st_nt2(double2* q, double x, double y) {
   __builtin_nontemporal_store(v, reinterpret_cast<v2d*>(q));
 }
 
-// Site block of logical block lb: parity lb & 1, block lb >> 1, taken in
-// the t-fastest order of the hop kernel (groups of tgrp t-slices of bps
-// blocks each; tgrp = 0: site order), so that a block's t-neighbour links
-// and spinors were read a few blocks earlier on the same XCD and are still
-// in its L2 (on large lattices a t-slice of links does not fit in it).
-__device__ __forceinline__ int site_block(int lb, int bps, int tgrp) {
-  int blk = lb >> 1;
-  if (tgrp > 0) {
-    const int span = tgrp * bps;
-    const int grp = blk / span, rem = blk - grp * span;
-    const int chunk = rem / tgrp, tl = rem - chunk * tgrp;
-    blk = (grp * tgrp + tl) * bps + chunk;
-  }
-  return blk;
-}
-
 __device__ __forceinline__ int lex_of(const Geom& g, const int c[4]) {
   return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
 }
@@ -243,15 +227,17 @@ __device__ __forceinline__ M3<double> bilinear_z(const SpinorIn<double, double2>
 }
 
 // The bilinear adjoint (see k_bilinear) in site-block form.
+// Blocks in the t-fastest groups of gauge_site_block (its 4x4 t/z groups
+// are not used: a bilinear reads only its +mu neighbours).
 template <int LAYOUT>
 __global__ __launch_bounds__(256) void k_bilinear_sb(Geom g, const double2* __restrict__ U,
                                                      const double2* __restrict__ a, const double2* __restrict__ b,
                                                      double kappa, double coeff, int mode, double dt,
-                                                     double2* out, int bps, int tgrp) {
+                                                     double2* out, BlockOrder order) {
   __shared__ double2 sh[LAYOUT == kCanonical ? kSB : 1][36];
   __shared__ int sh_site[kSB];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int p = lb & 1, blk = site_block(lb, bps, tgrp);
+  const int p = lb & 1, blk = gauge_site_block(lb, order, g.L[2]);
   const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
   const int cb = blk * kSB + lane;
   const bool active = cb < g.vh;
@@ -292,28 +278,18 @@ __global__ __launch_bounds__(256) void k_bilinear_sb(Geom g, const double2* __re
 
 static inline int sb_blocks(const Geom& g) { return 2 * ((g.vh + kSB - 1) / kSB); }
 
-// t-fastest groups for the site-block kernels (as the hop's): above 131072
-// sites per parity, when a t-slice holds a whole number of blocks
-static inline void sb_order(const Geom& g, int& bps, int& tgrp) {
-  const int vslice = g.vh / g.L[3];
-  bps = vslice / kSB;
-  tgrp = 0;
-  if (vslice % kSB != 0 || bps == 0 || g.vh <= 131072) return;
-  tgrp = g.L[3] % 8 == 0 ? 8 : (g.L[3] % 4 == 0 ? 4 : 2);
-}
-
 hipError_t launch_bilinear_force(const Geom& g, const double2* U, const double2* a_full, const double2* b_full,
                                  double kappa, double coeff, int mode, double dt, void* out, int layout,
                                  hipStream_t s) {
   const int nb = sb_blocks(g);
-  int bps, tgrp;
-  sb_order(g, bps, tgrp);
+  BlockOrder order = gauge_block_order(g);
+  order.nyc = 0;
   if (layout == kCanonical)
     hipLaunchKernelGGL((k_bilinear_sb<kCanonical>), dim3(nb), dim3(256), 0, s, g, U, a_full, b_full, kappa, coeff,
-                       mode, dt, (double2*)out, bps, tgrp);
+                       mode, dt, (double2*)out, order);
   else
     hipLaunchKernelGGL((k_bilinear_sb<kPacked>), dim3(nb), dim3(256), 0, s, g, U, a_full, b_full, kappa, coeff,
-                       mode, dt, (double2*)out, bps, tgrp);
+                       mode, dt, (double2*)out, order);
   return hipGetLastError();
 }
 

@@ -48,6 +48,25 @@ def test_stout_backprop_vs_autograd(lgt, dims, nlev, margin):
     margin("rel_err(got, ref)", rel_err(got, ref), 1e-12)
 
 
+def test_stout_tiled_16x16x32x64(lgt, margin):
+    """Forward (2 levels) and backprop (1 level) on 16x16x32x64, the block
+    order of large lattices, with links and cotangent of seeded 8^4 fields
+    repeated periodically: every site equals the oracle's 8^4 result at the
+    site modulo 8 (smearing has no boundary sign)."""
+    small = (8, 8, 8, 8)
+    u8 = li.random_links(small, 0.3, 61)
+    g8 = li.random_links(small, 1.0, 62) + 0.3 * li.random_links(small, 1.0, 63)
+    reps = (64 // 8, 32 // 8, 16 // 8, 16 // 8, 1, 1, 1)
+    lat = lgt.Lattice((16, 16, 32, 64))
+    U = to_dev(np.tile(u8, reps))
+    got = to_host(lat.stout_smear(U, RHO, 2))
+    ref = np.tile(stout.stout(u8, RHO, 2), reps)
+    margin("forward rel_err(got, ref)", rel_err(got, ref), 1e-13)
+    got = to_host(lat.stout_backprop(U, to_dev(np.tile(g8, reps)), RHO, 1))
+    ref = np.tile(stout.stout_vjp(u8, g8, RHO, 1), reps)
+    margin("backprop rel_err(got, ref)", rel_err(got, ref), 1e-12)
+
+
 def test_stout_backprop_large_rho(lgt, margin):
     """rho = 0.3 (the paper's value in its smeared test) exercises the scaling of the exp adjoint."""
     dims = (4, 4, 4, 4)
