@@ -67,6 +67,29 @@ def test_stout_tiled_16x16x32x64(lgt, margin):
     margin("backprop rel_err(got, ref)", rel_err(got, ref), 1e-12)
 
 
+@pytest.mark.parametrize("case", ["unit_links", "rho_zero", "tiny_exponent"])
+def test_stout_degenerate_cases(lgt, case, margin):
+    """Unit links (every staple sum is 6, so the exponent X vanishes and exp,
+    its Cayley-Hamilton coefficients and their derivatives sit at X = 0),
+    rho = 0 (the identity map, whose adjoint is the identity), and links
+    within 1e-6 of the identity (exponent of order 1e-7)."""
+    dims = (4, 4, 4, 4)
+    if case == "unit_links":
+        u = np.zeros(li.random_links(dims, 0.1, 1).shape, dtype=np.complex128)
+        u[..., 0, 0] = u[..., 1, 1] = u[..., 2, 2] = 1.0
+    else:
+        u = li.random_links(dims, 1e-6 if case == "tiny_exponent" else 0.5, 71)
+    rho = 0.0 if case == "rho_zero" else RHO
+    gt = li.random_links(dims, 1.0, 72) + 0.3 * li.random_links(dims, 1.0, 73)
+    lat = lgt.Lattice(dims)
+    got = to_host(lat.stout_smear(to_dev(u), rho, 2))
+    ref = u if case != "tiny_exponent" else stout.stout(u, rho, 2)
+    margin("forward rel_err(got, ref)", rel_err(got, ref), 1e-13)
+    got = to_host(lat.stout_backprop(to_dev(u), to_dev(gt), rho, 2))
+    ref = gt if case == "rho_zero" else stout.stout_vjp(u, gt, rho, 2)
+    margin("backprop rel_err(got, ref)", rel_err(got, ref), 1e-12)
+
+
 def test_stout_backprop_large_rho(lgt, margin):
     """rho = 0.3 (the paper's value in its smeared test) exercises the scaling of the exp adjoint."""
     dims = (4, 4, 4, 4)
