@@ -31,6 +31,7 @@ namespace lgt {
 template <typename R, typename T>
 struct EpiAxpy {  // out = self + coef * acc
   static constexpr bool kReduce = false;
+  static constexpr bool kPrefetch = !std::is_same<T, Bf16c>::value;
   T* out[2];
   const T* self[2];
   R coef;
@@ -42,13 +43,21 @@ struct EpiAxpy {  // out = self + coef * acc
   const double* pap_partials;
   int pap_nblk;
   __device__ bool skip() const { return guard && guard->done != kDoneRunning; }
-  __device__ void apply(int p, int cb, int spin, const C<R>* acc, double&) const {
+  struct Pre {
+    C<R> s[3];
+  };
+  __device__ Pre pre(int p, int cb, int spin) const {
+    Pre q;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      q.s[i] = self[p] ? Store<R, T>::ld(self[p] + (size_t)(3 * spin + i) * vh + cb) : czero<R>();
+    return q;
+  }
+  __device__ void apply(int p, int cb, int spin, const C<R>* acc, double&, const Pre& q) const {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const size_t o = (size_t)(3 * spin + i) * vh + cb;
-      C<R> v = coef * acc[i];
-      if (self[p]) v += Store<R, T>::ld(self[p] + o);
-      Store<R, T>::st(out[p] + o, v);
+      Store<R, T>::st(out[p] + o, q.s[i] + coef * acc[i]);
     }
   }
   template <int NT>
@@ -87,6 +96,7 @@ struct EpiAxpy {  // out = self + coef * acc
 template <typename R>
 struct EpiStep {
   static constexpr bool kReduce = false;
+  static constexpr bool kPrefetch = true;
   R2<R>* t;         // even half: H p, updated in place
   R2<R>* p;         // odd half: search direction
   const R2<R>* r;   // odd half: residual (the hop's input)
@@ -136,13 +146,27 @@ struct EpiStep {
     __syncthreads();
     return !s_run;
   }
-  __device__ void apply(int, int cb, int spin, const C<R>* acc, double&) const {
+  struct Pre {
+    C<R> t[3], r[3], p[3];
+  };
+  __device__ Pre pre(int, int cb, int spin) const {
+    Pre q;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const size_t o = (size_t)(3 * spin + i) * vh + cb;
+      q.t[i] = ld<R>(t + o);
+      q.r[i] = ld<R>(r + o);
+      q.p[i] = ld<R>(p + o);
+    }
+    return q;
+  }
+  __device__ void apply(int, int cb, int spin, const C<R>* acc, double&, const Pre& q) const {
     const R b = R(beta_sh());
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const size_t o = (size_t)(3 * spin + i) * vh + cb;
-      lgt::st<R>(t + o, acc[i] + b * ld<R>(t + o));
-      lgt::st<R>(p + o, ld<R>(r + o) + b * ld<R>(p + o));
+      lgt::st<R>(t + o, acc[i] + b * q.t[i]);
+      lgt::st<R>(p + o, q.r[i] + b * q.p[i]);
     }
   }
   template <int NT>
@@ -152,17 +176,27 @@ struct EpiStep {
 template <typename R, typename T>
 struct EpiSchurNorm {  // w = x + coef * acc (odd sites), block partials of |w|^2 (of w as stored)
   static constexpr bool kReduce = true;
+  static constexpr bool kPrefetch = !std::is_same<T, Bf16c>::value;
   T* w;
   const T* x;
   R coef;
   int vh;
   SolverState* state;
   __device__ bool skip() const { return state->done != kDoneRunning; }
-  __device__ void apply(int, int cb, int spin, const C<R>* acc, double& red) const {
+  struct Pre {
+    C<R> x[3];
+  };
+  __device__ Pre pre(int, int cb, int spin) const {
+    Pre q;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) q.x[i] = Store<R, T>::ld(x + (size_t)(3 * spin + i) * vh + cb);
+    return q;
+  }
+  __device__ void apply(int, int cb, int spin, const C<R>* acc, double& red, const Pre& q) const {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const size_t o = (size_t)(3 * spin + i) * vh + cb;
-      const C<R> v = Store<R, T>::round(Store<R, T>::ld(x + o) + coef * acc[i]);
+      const C<R> v = Store<R, T>::round(q.x[i] + coef * acc[i]);
       Store<R, T>::st(w + o, v);
       red += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
     }
@@ -174,6 +208,7 @@ struct EpiSchurNorm {  // w = x + coef * acc (odd sites), block partials of |w|^
 template <typename R, typename T>
 struct EpiSchurCG {  // q = w + coef * acc; x += alpha p (if x); r -= alpha q; block partials of |r|^2
   static constexpr bool kReduce = true;
+  static constexpr bool kPrefetch = !std::is_same<T, Bf16c>::value;
   const T* w;
   R2<R>* x;
   R2<R>* r;
@@ -182,14 +217,31 @@ struct EpiSchurCG {  // q = w + coef * acc; x += alpha p (if x); r -= alpha q; b
   int vh;
   SolverState* state;
   __device__ bool skip() const { return state->done != kDoneRunning; }
-  __device__ void apply(int, int cb, int spin, const C<R>* acc, double& red) const {
+  struct Pre {
+    C<R> w[3], x[3], r[3], p[3];
+  };
+  __device__ Pre pre(int, int cb, int spin) const {
+    Pre q;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const size_t o = (size_t)(3 * spin + i) * vh + cb;
+      q.w[i] = Store<R, T>::ld(w + o);
+      q.r[i] = ld<R>(r + o);
+      if (x) {
+        q.x[i] = ld<R>(x + o);
+        q.p[i] = Store<R, T>::ld(p + o);
+      }
+    }
+    return q;
+  }
+  __device__ void apply(int, int cb, int spin, const C<R>* acc, double& red, const Pre& pq) const {
     const R alpha = R(state->alpha);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const size_t o = (size_t)(3 * spin + i) * vh + cb;
-      const C<R> q = Store<R, T>::ld(w + o) + coef * acc[i];
-      if (x) st<R>(x + o, ld<R>(x + o) + alpha * Store<R, T>::ld(p + o));
-      C<R> rv = ld<R>(r + o) - alpha * q;
+      const C<R> q = pq.w[i] + coef * acc[i];
+      if (x) st<R>(x + o, pq.x[i] + alpha * pq.p[i]);
+      C<R> rv = pq.r[i] - alpha * q;
       st<R>(r + o, rv);
       red += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
     }
@@ -200,17 +252,31 @@ struct EpiSchurCG {  // q = w + coef * acc; x += alpha p (if x); r -= alpha q; b
 
 struct EpiResidual {  // r = phi - (self + coef * acc) over both parities, block partials of |r|^2
   static constexpr bool kReduce = true;
+  static constexpr bool kPrefetch = true;
   const double2* self[2];
   const double2* phi[2];
   double2* r[2];
   double coef;
   int vh;
   __device__ bool skip() const { return false; }
-  __device__ void apply(int p, int cb, int spin, const C<double>* acc, double& red) const {
+  struct Pre {
+    C<double> f[3], s[3];
+  };
+  __device__ Pre pre(int p, int cb, int spin) const {
+    Pre q;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const size_t o = (size_t)(3 * spin + i) * vh + cb;
-      C<double> v = ld<double>(phi[p] + o) - (ld<double>(self[p] + o) + coef * acc[i]);
+      q.f[i] = ld<double>(phi[p] + o);
+      q.s[i] = ld<double>(self[p] + o);
+    }
+    return q;
+  }
+  __device__ void apply(int p, int cb, int spin, const C<double>* acc, double& red, const Pre& q) const {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const size_t o = (size_t)(3 * spin + i) * vh + cb;
+      C<double> v = q.f[i] - (q.s[i] + coef * acc[i]);
       st<double>(r[p] + o, v);
       red += norm2(v);
     }
@@ -258,6 +324,16 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, In hi
   const bool bwd = NS == 32 && lane >= 32;
   const int cb = blk * NS + (NS == 64 ? lane : lane & 31);
   const bool active = cb < g.vh;
+  // 64-site blocks: the lane's epilogue operands at its own (site, spin =
+  // wave) are independent of the hop, so they are loaded before it and
+  // arrive while the neighbour loads are in flight (16^4 mixed force call
+  // 5.40 -> 5.15 ms, FP64 at 24^3x48 187 -> 183 ms).  Not for BF16-stored
+  // vectors, where holding them across the hop cost more than it saved
+  // (24^3x48: 65.0 -> 67.5 ms).
+  typename Epi::Pre pre{};
+  if constexpr (NS == 64 && Epi::kPrefetch) {
+    if (active) pre = epi.pre(p, cb, mu);
+  }
 
   C<R> acc[12];
 #pragma unroll
@@ -301,7 +377,10 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, In hi
       R2<R> a = lds[0][k][lane], b = lds[1][k][lane], cc = lds[2][k][lane], d = lds[3][k][lane];
       out[i] = cmk<R>(((a.x + b.x) + cc.x) + d.x, ((a.y + b.y) + cc.y) + d.y);
     }
-    if (active) epi.apply(p, cb, spin, out, red);
+    if constexpr (!Epi::kPrefetch) {
+      if (active) pre = epi.pre(p, cb, spin);
+    }
+    if (active) epi.apply(p, cb, spin, out, red, pre);
   } else if (mu < 2) {
     // lane -> site lane & 31, spin 2 mu + lane / 32; eight partial hops
     const int site = lane & 31;
@@ -320,7 +399,7 @@ __global__ __launch_bounds__(256) void k_hop(Geom g, int nbp, int p_fixed, In hi
       }
       out[i] = cmk<R>(sx, sy);
     }
-    if (cbo < g.vh) epi.apply(p, cbo, spin, out, red);
+    if (cbo < g.vh) epi.apply(p, cbo, spin, out, red, epi.pre(p, cbo, spin));
   }
   if constexpr (Epi::kReduce) {
     double v[1] = {red};
