@@ -13,8 +13,9 @@ full-field norm; the link-level measure of Sec. III A, eq. 8):
 * FP64 path, and mixed precision driven to the same FP64 true residual
   (1e-14): 1e-12;
 * mixed precision at an outer tolerance of 1e-11: 1e-9.  At the workloads'
-  own tolerance of 1e-10 the solver error alone is about 1e-9 (FP64 and
-  mixed alike), so that case is recorded against 1e-8.
+  own tolerance of 1e-10 the solver error alone is about 1e-9 at 16^4 and
+  2e-8 at 24^3x48 (FP64 and mixed alike), so that case is recorded against
+  1e-8 and 5e-8.
 """
 import json
 import os
@@ -153,7 +154,14 @@ def test_c3_actions_and_gauge_force(c3, margin):
     margin("24^3x48 sampled gauge force vs oracle", rel_err(sample(got, c3["links"]), c3["fg"]), 1e-13)
 
 
-@pytest.mark.parametrize("precision,tol,gate", FORCE_CASES)
+# At the workload's tolerance the force carries the solver error of a 1e-10
+# residual, which grows with the conditioning of D: 1.1e-9 at 16^4 (kappa
+# 0.125), 2.0e-8 at 24^3x48 (kappa 0.13, where the unpreconditioned CG needs
+# 775 iterations to 1e-14), FP64 and mixed alike; recorded against 5e-8 there.
+C3_FORCE_CASES = [c if c[1] != 1e-10 else (c[0], c[1], 5e-8) for c in FORCE_CASES]
+
+
+@pytest.mark.parametrize("precision,tol,gate", C3_FORCE_CASES)
 def test_c3_fermion_force_vs_stored_oracle(c3, precision, tol, gate, margin):
     g = c3["gold"]
     check_force(c3["lat"], c3["U"], c3["phi"], g["kappa"], g, c3["links"], c3["ff"], c3["lgt"], precision, tol, gate,
