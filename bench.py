@@ -321,27 +321,35 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-def _force_vs_oracle(lat, U, phi, kappa, params):
-    """Relative error of the fermion force against the stored oracle values of
-    the 16^4 workload (tests/golden, written from the oracle alone): over the
-    sampled links, and of the full-field Frobenius norm."""
-    import numpy as np
-
-    path = os.path.join(ROOT, "tests", "golden", "c2_16x16x16x16.json")
+def _golden(name):
+    """Stored oracle values of a workload (tests/golden, written from the oracle alone), or None."""
     try:
-        with open(path) as f:
-            gold = json.load(f)
+        with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+            return json.load(f)
     except OSError:
         return None
+
+
+def _vs_golden(F, gold):
+    """Relative error of a fermion force (host array) against stored oracle
+    values: over the sampled links, and of the full-field Frobenius norm."""
+    import numpy as np
+
     links = [tuple(l) for l in gold["links"]]
     ref = np.array([[complex(*v) for v in m] for m in gold["F_fermion"]]).reshape(-1, 3, 3)
-    out = {"oracle_tol": gold["oracle_tol"], "sampled_links": len(links)}
+    got = np.stack([F[l] for l in links])
+    return {"sampled_rel_err": float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel())),
+            "norm_rel_diff": float(abs(np.linalg.norm(F.ravel()) - gold["F_fermion_fro"]) / gold["F_fermion_fro"])}
+
+
+def _force_vs_oracle(lat, U, phi, kappa, params, golden="c2_16x16x16x16.json"):
+    """The fermion force of each parameter set against the stored oracle values."""
+    gold = _golden(golden)
+    if gold is None:
+        return None
+    out = {"oracle_tol": gold["oracle_tol"], "sampled_links": len(gold["links"])}
     for name, prm in params.items():
-        F = lat.fermion_force(U, phi, kappa, prm)[0].cpu().numpy()
-        got = np.stack([F[l] for l in links])
-        out[name] = {"sampled_rel_err": float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel())),
-                     "norm_rel_diff": float(abs(np.linalg.norm(F.ravel()) - gold["F_fermion_fro"])
-                                            / gold["F_fermion_fro"])}
+        out[name] = _vs_golden(lat.fermion_force(U, phi, kappa, prm)[0].cpu().numpy(), gold)
     return out
 
 
@@ -561,6 +569,27 @@ def bench_c3(args):
     for prec in ("mixed_fp32", "mixed_bf16"):
         if prec in forces:
             res[prec]["force_rel_diff_vs_fp64"] = _rel(forces[prec], forces["fp64"])
+    gold = _golden("c3_24x24x24x48.json")
+    at_bar = None
+    if gold is not None:
+        for prec in forces:
+            res[prec]["force_vs_oracle"] = _vs_golden(forces[prec].cpu().numpy(), gold)
+        # the outer tolerance at which the mixed force meets its bar of 1e-9
+        at_bar = {"tol": 1e-11, "force_bar": 1e-9, "oracle_tol": gold["oracle_tol"]}
+        for prec in ("mixed_fp32", "fp64", "mixed_bf16"):
+            prm = lgt.Params(precision=prec, tol=1e-11)
+            out = lat.empty_gauge()
+            lat.fermion_force(U, phi, kappa, prm, out=out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = lat.fermion_force(U, phi, kappa, prm, out=out)
+            torch.cuda.synchronize()
+            e = _vs_golden(out.cpu().numpy(), gold)
+            at_bar[prec] = {"ms_per_call": round((time.perf_counter() - t0) * 1e3, 3), "iters": st["iters"],
+                            "corrections": st["corrections"], "true_rel_residual": st["true_rel_residual"], **e,
+                            "meets_bar": e["sampled_rel_err"] <= 1e-9}
+            log(f"bench c3: at the force bar {prec} {at_bar[prec]}")
+        at_bar["speedup_mixed_vs_fp64"] = round(at_bar["fp64"]["ms_per_call"] / at_bar["mixed_fp32"]["ms_per_call"], 3)
     hop_ms = lat.hop_benchmark(U, E, "mixed_fp32", 100)
     hop_bytes = 72 * 4 * V  # two-row FP32 links + half spinors
     gbs = hop_bytes / (hop_ms * 1e-3) / 1e9
@@ -576,6 +605,7 @@ def bench_c3(args):
                    "dims": list(dims), "kappa": kappa, "tol": tol},
         "results": res,
         "speedup_mixed_vs_fp64": round(res["fp64"]["ms_per_call"] / t_mixed, 3),
+        "at_force_bar": at_bar,
         "roofline": {"kernel": "even/odd hop H_eo, FP32, two-row SU(3) links", "bound": "hbm",
                      "achieved": round(gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
