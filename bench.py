@@ -272,7 +272,14 @@ def main():
     hop = _hop_roofline(lat, U, E, V)
     hop["measured_copy_GBs"] = round(copy_gbs, 1)
     hop["frac_of_copy"] = round(hop["achieved"] / copy_gbs, 4)
+    hop["hbm_ceilings"] = _hbm_ceilings(copy_gbs)
     hop["out_of_cache"] = _hop_out_of_cache()
+    for line in hop["out_of_cache"].values():
+        if line.get("traffic"):
+            # the bytes the kernel moved through HBM per second, against the read-only rate
+            moved = line["traffic"] / (line["avg_launch_us"] * 1e-6) / 1e9
+            line["measured_traffic_GBs"] = round(moved, 1)
+            line["frac_of_read_ceiling"] = round(moved / hop["hbm_ceilings"]["read_GBs"], 4)
     log(f"bench: hop roofline {hop}")
 
     # effective GB/s of the whole call: compulsory bytes of the CG iterations
@@ -370,6 +377,31 @@ def _copy_ceiling():
         best = min(best, e0.elapsed_time(e1))
     del a, b
     return 2 * 1024 ** 3 / (best * 1e-3) / 1e9
+
+
+def _hbm_ceilings(copy_gbs):
+    """What plain streaming reaches on this GPU, best of 10 over 2 GiB: a
+    read-only pass (sums of rows of 1024 floats, which writes 1/1024 of the
+    bytes; a full sum reaches only 4 TB/s), a write-only pass (fill) and the
+    1 GiB copy of _copy_ceiling.  A kernel that mostly reads (the hop reads
+    7/8 of its bytes) can exceed the copy rate."""
+    import torch
+
+    a = torch.ones(512 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    for name, fn in (("read", lambda: a.view(-1, 1024).sum(1)), ("write", lambda: a.fill_(1.0))):
+        best = 1e30
+        for _ in range(10):
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        out[f"{name}_GBs"] = round(2 * 1024 ** 3 / (best * 1e-3) / 1e9, 1)
+    del a
+    out["copy_GBs"] = round(copy_gbs, 1)
+    return out
 
 
 HOP_SOURCES = ("kernels_hop.hip", "lgt_hop.h", "lgt_device.h", "lgt_internal.h")
