@@ -15,58 +15,6 @@
 namespace lgt {
 
 // ---------------------------------------------------------------------------
-// Spin projection with a per-lane direction: B_mu of gamma_mu = [[0,B],[B^dag,0]]
-// in the chiral basis, B_0 = -i sigma_1, B_1 = -i sigma_2, B_2 = -i sigma_3, B_3 = 1.
-// h = psi_up + s * B_mu psi_dn (per colour).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void b_matrix(int mu, C<double> B[4]) {
-  const C<double> z = {0.0, 0.0}, one = {1.0, 0.0}, mone = {-1.0, 0.0}, mi = {0.0, -1.0}, pi = {0.0, 1.0};
-  B[0] = mu == 2 ? mi : (mu == 3 ? one : z);
-  B[1] = mu == 0 ? mi : (mu == 1 ? mone : z);
-  B[2] = mu == 0 ? mi : (mu == 1 ? one : z);
-  B[3] = mu == 2 ? pi : (mu == 3 ? one : z);
-}
-
-// load a spinor (12 complex) at (parity half pointer, cb) and return its
-// projection h (6 complex: [spin a][colour]) for sign s
-__device__ __forceinline__ void load_project(const double2* __restrict__ half, int vh, int cb,
-                                             const C<double> B[4], double s, C<double> h[6]) {
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const C<double> u0 = ld<double>(half + (size_t)i * vh + cb);
-    const C<double> u1 = ld<double>(half + (size_t)(3 + i) * vh + cb);
-    const C<double> d0 = ld<double>(half + (size_t)(6 + i) * vh + cb);
-    const C<double> d1 = ld<double>(half + (size_t)(9 + i) * vh + cb);
-    h[i] = u0 + s * (B[0] * d0 + B[1] * d1);
-    h[3 + i] = u1 + s * (B[2] * d0 + B[3] * d1);
-  }
-}
-
-template <int LAYOUT>
-__device__ __forceinline__ size_t link_elem(const Geom& g, int s, int p, int cb, int mu, int k) {
-  if (LAYOUT == kCanonical) return ((size_t)s * 4 + mu) * 9 + k;
-  return ((size_t)(p * 4 + mu) * 9 + k) * g.vh + cb;
-}
-
-// Write F (mode 0), G (mode 1) or P -= dt F (mode 2) for one link.
-template <int LAYOUT>
-__device__ __forceinline__ void emit(const Geom& g, double2* out, int s, int p, int cb, int mu, int mode,
-                                     double dt, const M3<double>& F, const M3<double>& G) {
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    double2* q = out + link_elem<LAYOUT>(g, s, p, cb, mu, k);
-    if (mode == 1) {
-      st<double>(q, G.m[k]);
-    } else if (mode == 0) {
-      st<double>(q, F.m[k]);
-    } else {
-      C<double> v = ld<double>(q);
-      st<double>(q, v - dt * F.m[k]);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Adjoint of I(U) = a^dag D(U) b (eq. S3.13): for the link U_mu(x), with s_bc
 // its fermion boundary sign,
 //   Re I depends on U through -kappa s_bc Re tr(U Z),
@@ -76,51 +24,6 @@ __device__ __forceinline__ void emit(const Geom& g, double2* out, int s, int p, 
 // F = -1/2 P[U G^dag] = (coeff kappa s_bc / 2) P[U Z].  The pseudofermion
 // force of eq. S3.12 is coeff = -2, a = Y = D X, b = X.
 // ---------------------------------------------------------------------------
-template <int LAYOUT>
-__global__ __launch_bounds__(256) void k_bilinear(Geom g, const double2* __restrict__ U,
-                                                  const double2* __restrict__ a,
-                                                  const double2* __restrict__ b, double kappa,
-                                                  double coeff, int mode, double dt, double2* out) {
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int t = lb * 256 + threadIdx.x;
-  const int s = t >> 2, mu = t & 3;
-  if (s >= 2 * g.vh) return;
-  const int vh = g.vh;
-  int c[4];
-  lex_coords(g, s, c);
-  const int p = parity_of(c), cb = s >> 1;
-  const int nf = cb_shift(g, c, mu, +1);
-  const size_t half = (size_t)12 * vh;
-  C<double> B[4];
-  b_matrix(mu, B);
-  C<double> hmb[6], hma[6], hpa[6], hpb[6];
-  load_project(b + (1 - p) * half, vh, nf, B, -1.0, hmb);  // h-[b(x+mu)]
-  load_project(a + p * half, vh, cb, B, -1.0, hma);        // h-[a(x)]
-  load_project(a + (1 - p) * half, vh, nf, B, +1.0, hpa);  // h+[a(x+mu)]
-  load_project(b + p * half, vh, cb, B, +1.0, hpb);        // h+[b(x)]
-  M3<double> Z;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      C<double> z = mulcj(hmb[i], hma[k]);
-      z += mulcj(hmb[3 + i], hma[3 + k]);
-      z += mulcj(hpa[i], hpb[k]);
-      z += mulcj(hpa[3 + i], hpb[3 + k]);
-      Z.m[3 * i + k] = z;
-    }
-  const double sbc = (mu == 3 && c[3] == g.L[3] - 1) ? double(g.bc) : 1.0;
-  M3<double> F, G;
-  if (mode == 1) {
-    G = mscale(-coeff * kappa * sbc, mdag(Z));
-  } else {
-    const M3<double> Ux = load_m3<double>(gptr<double>(U, g, p, mu), vh, cb);
-    F = mscale(0.5 * coeff * kappa * sbc, proj_ta(mmul(Ux, Z)));
-  }
-  emit<LAYOUT>(g, out, s, p, cb, mu, mode, dt, F, G);
-}
-
-static inline int link_blocks(const Geom& g) { return (2 * g.vh * 4 + 255) / 256; }
 
 // ---------------------------------------------------------------------------
 // Per-link kernels in site-block form: a 256-thread block owns 64
@@ -226,7 +129,7 @@ __device__ __forceinline__ M3<double> bilinear_z(const SpinorIn<double, double2>
   return Z;
 }
 
-// The bilinear adjoint (see k_bilinear) in site-block form.
+// The bilinear adjoint (the adjoint of I(U) above) in site-block form.
 // Blocks in the t-fastest groups of gauge_site_block (its 4x4 t/z groups
 // are not used: a bilinear reads only its +mu neighbours).
 template <int LAYOUT>
@@ -300,27 +203,6 @@ hipError_t launch_bilinear_force(const Geom& g, const double2* U, const double2*
 //                      + U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu) ],
 // so G = -(beta/3) A^dag and F = (beta/6) P[U A].
 // ---------------------------------------------------------------------------
-template <int LAYOUT>
-__global__ __launch_bounds__(256) void k_gauge_force(Geom g, const double2* __restrict__ U, double beta,
-                                                     int mode, double dt, double2* out) {
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int t = lb * 256 + threadIdx.x;
-  const int s = t >> 2, mu = t & 3;
-  if (s >= 2 * g.vh) return;
-  int c[4];
-  lex_coords(g, s, c);
-  const int p = parity_of(c), cb = s >> 1;
-  const M3<double> A = staple_A(U, g, c, mu);
-  M3<double> F, G;
-  if (mode == 1) {
-    G = mscale(-beta / 3.0, mdag(A));
-  } else {
-    const M3<double> Ux = load_m3<double>(gptr<double>(U, g, p, mu), g.vh, cb);
-    F = mscale(beta / 6.0, proj_ta(mmul(Ux, A)));
-  }
-  emit<LAYOUT>(g, out, s, p, cb, mu, mode, dt, F, G);
-}
-
 // The staple force in site-block form (see k_bilinear_sb): each thread sums
 // the six staples of its link one at a time, each as two 3x3 products, so
 // at most the running sum, one partial product and two links are live.
