@@ -48,12 +48,14 @@ def test_stored_gauge_action_recomputes(g):
     assert 1 - 3 * e2 < g["mean_plaquette"] < 1 - 2 * e2
 
 
-def test_stored_smeared_trajectory_is_consistent():
-    """The stored 8^3x16 smeared trajectory: the end links are SU(3), the end
-    momenta traceless anti-Hermitian, and the trajectory's H at the start
-    agrees with the heat-bath identity S_f(D(V)^dag eta) = |eta|^2 (the rest
-    of H0 is K + S_G of the stored seeds)."""
-    with open(os.path.join(HERE, "c5_8x8x8x16_smeared_trajectory.json")) as f:
+@pytest.mark.parametrize("name", ["c5_8x8x8x16_smeared_trajectory.json", "c5_8x8x8x8_periodic_trajectory.json"])
+def test_stored_smeared_trajectory_is_consistent(name):
+    """The stored smeared trajectories (8^3x16 antiperiodic, 8^4 periodic): the
+    end links are SU(3), the end momenta traceless anti-Hermitian, and the
+    trajectory's H at the start agrees with the heat-bath identity
+    S_f(D(V)^dag eta) = |eta|^2 (the rest of H0 is K + S_G of the stored
+    seeds)."""
+    with open(os.path.join(HERE, name)) as f:
         g = json.load(f)
     dims = tuple(g["dims"])
     u = np.array([[complex(*v) for v in m] for m in g["U"]]).reshape(-1, 3, 3)
