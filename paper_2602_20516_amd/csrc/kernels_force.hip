@@ -232,10 +232,10 @@ __global__ __launch_bounds__(256) void k_gauge_force_sb(Geom g, const double2* _
     shifted(g, xpm, nu, -1, xpmmn);
     // U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
     M3<double> t = mmul_nd(link_at(U, g, xpm, nu), link_at(U, g, xpn, mu));
-    A = madd(A, mmul_nd(t, link_at(U, g, c, nu)));
+    A = mmac_nd(A, t, link_at(U, g, c, nu));
     // U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu) = (U_mu(x-nu) U_nu(x+mu-nu))^dag U_nu(x-nu)
     t = mmul(link_at(U, g, xmn, mu), link_at(U, g, xpmmn, nu));
-    A = madd(A, mmul_dn(t, link_at(U, g, xmn, nu)));
+    A = mmac_dn(A, t, link_at(U, g, xmn, nu));
   }
   M3<double> M;
   if (mode == 1) {

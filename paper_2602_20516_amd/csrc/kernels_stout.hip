@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_stout_adj_a(Geom g, const double2* __re
   const M3<double> C = mscale(rho, mdag(A));
   store_m3<double>((double2*)gptr<double>(Lam, g, li.p, li.mu), vh, li.cb, mmul(GOm, Ux));
   store_m3<double>((double2*)gptr<double>(Gpart, g, li.p, li.mu), vh, li.cb,
-                   madd(mmul(Einv, G1), mmul_dn(GOm, C)));
+                   mmac_dn(mmul(Einv, G1), GOm, C));
 }
 
 // Stage B: for the link U_a(y), add rho times the gradient of
@@ -216,16 +216,16 @@ __global__ __launch_bounds__(256) void k_stout_adj_b(Geom g, const double2* __re
     {  // forward side: sites y, y+m, y+a
       const M3<double> Ua_ypm = link_at(U, g, ypm, a);
       const M3<double> Um_y = link_at(U, g, y, m);
-      const M3<double> W = madd(mmul(link_at(Lam, g, y, m), Ua_ypm), mmul(Um_y, link_at(Lam, g, ypm, a)));
-      S = madd(S, mmul_nd(W, link_at(U, g, ypa, m)));
-      S = madd(S, mmul_nd(mmul(Um_y, Ua_ypm), link_at(Lam, g, ypa, m)));
+      const M3<double> W = mmac(mmul(link_at(Lam, g, y, m), Ua_ypm), Um_y, link_at(Lam, g, ypm, a));
+      S = mmac_nd(S, W, link_at(U, g, ypa, m));
+      S = mmac_nd(S, mmul(Um_y, Ua_ypm), link_at(Lam, g, ypa, m));
     }
     {  // backward side: sites y-m, y-m+a
       const M3<double> Ua_ymm = link_at(U, g, ymm, a);
       const M3<double> Um_ymm = link_at(U, g, ymm, m);
-      const M3<double> W = madd(mmul_dn(link_at(Lam, g, ymm, m), Ua_ymm), mmul_dn(Um_ymm, link_at(Lam, g, ymm, a)));
-      S = madd(S, mmul(W, link_at(U, g, ymmpa, m)));
-      S = madd(S, mmul(mmul_dn(Um_ymm, Ua_ymm), link_at(Lam, g, ymmpa, m)));
+      const M3<double> W = mmac_dn(mmul_dn(link_at(Lam, g, ymm, m), Ua_ymm), Um_ymm, link_at(Lam, g, ymm, a));
+      S = mmac(S, W, link_at(U, g, ymmpa, m));
+      S = mmac(S, mmul_dn(Um_ymm, Ua_ymm), link_at(Lam, g, ymmpa, m));
     }
   }
   const M3<double> Gx = load_m3<double>(gptr<double>(Gpart, g, li.p, a), g.vh, li.cb);

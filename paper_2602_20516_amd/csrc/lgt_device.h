@@ -152,16 +152,73 @@ template <typename R, typename S> __device__ __forceinline__ C<R> cvt(C<S> a) {
 // ---------------------------------------------------------------------------
 template <typename R> struct M3 { C<R> m[9]; };
 
+// Products as chains of fused multiply-adds: an element of a product is
+// 2 multiplies and 10 FMAs (16 instructions as separate complex multiplies
+// and adds); the accumulating forms (acc + a b) fold the sum into the chain.
+template <typename R> __device__ __forceinline__ R rfma(R a, R b, R c);
+template <> __device__ __forceinline__ double rfma<double>(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+template <> __device__ __forceinline__ float rfma<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+// s + a b,  s + a conj(b),  s + conj(a) b
+template <typename R> __device__ __forceinline__ C<R> cmac(C<R> s, C<R> a, C<R> b) {
+  return {rfma(-a.im, b.im, rfma(a.re, b.re, s.re)), rfma(a.im, b.re, rfma(a.re, b.im, s.im))};
+}
+template <typename R> __device__ __forceinline__ C<R> cmac_cj(C<R> s, C<R> a, C<R> b) {
+  return {rfma(a.im, b.im, rfma(a.re, b.re, s.re)), rfma(-a.re, b.im, rfma(a.im, b.re, s.im))};
+}
+template <typename R> __device__ __forceinline__ C<R> cjmac(C<R> s, C<R> a, C<R> b) {
+  return {rfma(a.im, b.im, rfma(a.re, b.re, s.re)), rfma(-a.im, b.re, rfma(a.re, b.im, s.im))};
+}
+// acc + a b
+template <typename R> __device__ __forceinline__ M3<R> mmac(const M3<R>& acc, const M3<R>& a, const M3<R>& b) {
+  M3<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      C<R> s = cmac(acc.m[3 * i + j], a.m[3 * i], b.m[j]);
+      s = cmac(s, a.m[3 * i + 1], b.m[3 + j]);
+      c.m[3 * i + j] = cmac(s, a.m[3 * i + 2], b.m[6 + j]);
+    }
+  return c;
+}
+// acc + a b^dag
+template <typename R> __device__ __forceinline__ M3<R> mmac_nd(const M3<R>& acc, const M3<R>& a, const M3<R>& b) {
+  M3<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      C<R> s = cmac_cj(acc.m[3 * i + j], a.m[3 * i], b.m[3 * j]);
+      s = cmac_cj(s, a.m[3 * i + 1], b.m[3 * j + 1]);
+      c.m[3 * i + j] = cmac_cj(s, a.m[3 * i + 2], b.m[3 * j + 2]);
+    }
+  return c;
+}
+// acc + a^dag b
+template <typename R> __device__ __forceinline__ M3<R> mmac_dn(const M3<R>& acc, const M3<R>& a, const M3<R>& b) {
+  M3<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      C<R> s = cjmac(acc.m[3 * i + j], a.m[i], b.m[j]);
+      s = cjmac(s, a.m[3 + i], b.m[3 + j]);
+      c.m[3 * i + j] = cjmac(s, a.m[6 + i], b.m[6 + j]);
+    }
+  return c;
+}
 template <typename R> __device__ __forceinline__ M3<R> mmul(const M3<R>& a, const M3<R>& b) {
   M3<R> c;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      C<R> s = a.m[3 * i] * b.m[j];
-      s += a.m[3 * i + 1] * b.m[3 + j];
-      s += a.m[3 * i + 2] * b.m[6 + j];
-      c.m[3 * i + j] = s;
+      const C<R> x = a.m[3 * i], y = b.m[j];
+      C<R> s = {rfma(-x.im, y.im, x.re * y.re), rfma(x.im, y.re, x.re * y.im)};
+      s = cmac(s, a.m[3 * i + 1], b.m[3 + j]);
+      c.m[3 * i + j] = cmac(s, a.m[3 * i + 2], b.m[6 + j]);
     }
   return c;
 }
@@ -172,10 +229,10 @@ template <typename R> __device__ __forceinline__ M3<R> mmul_nd(const M3<R>& a, c
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      C<R> s = mulcj(a.m[3 * i], b.m[3 * j]);
-      s += mulcj(a.m[3 * i + 1], b.m[3 * j + 1]);
-      s += mulcj(a.m[3 * i + 2], b.m[3 * j + 2]);
-      c.m[3 * i + j] = s;
+      const C<R> x = a.m[3 * i], y = b.m[3 * j];
+      C<R> s = {rfma(x.im, y.im, x.re * y.re), rfma(-x.re, y.im, x.im * y.re)};
+      s = cmac_cj(s, a.m[3 * i + 1], b.m[3 * j + 1]);
+      c.m[3 * i + j] = cmac_cj(s, a.m[3 * i + 2], b.m[3 * j + 2]);
     }
   return c;
 }
@@ -186,10 +243,10 @@ template <typename R> __device__ __forceinline__ M3<R> mmul_dn(const M3<R>& a, c
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      C<R> s = cjmul(a.m[i], b.m[j]);
-      s += cjmul(a.m[3 + i], b.m[3 + j]);
-      s += cjmul(a.m[6 + i], b.m[6 + j]);
-      c.m[3 * i + j] = s;
+      const C<R> x = a.m[i], y = b.m[j];
+      C<R> s = {rfma(x.im, y.im, x.re * y.re), rfma(-x.im, y.re, x.re * y.im)};
+      s = cjmac(s, a.m[3 + i], b.m[3 + j]);
+      c.m[3 * i + j] = cjmac(s, a.m[6 + i], b.m[6 + j]);
     }
   return c;
 }

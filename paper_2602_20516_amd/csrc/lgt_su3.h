@@ -75,11 +75,11 @@ __device__ __forceinline__ M3<double> staple_A(const double2* U, const Geom& g, 
     shifted(g, xpm, nu, -1, xpmmn);
     {
       const M3<double> u1 = link_at(U, g, xpm, nu), u2 = link_at(U, g, xpn, mu), u3 = link_at(U, g, c, nu);
-      A = madd(A, mmul_nd(mmul_nd(u1, u2), u3));
+      A = mmac_nd(A, mmul_nd(u1, u2), u3);
     }
     {
       const M3<double> v1 = link_at(U, g, xpmmn, nu), v2 = link_at(U, g, xmn, mu), v3 = link_at(U, g, xmn, nu);
-      A = madd(A, mmul_dn(mmul(v2, v1), v3));
+      A = mmac_dn(A, mmul(v2, v1), v3);
     }
   }
   return A;
