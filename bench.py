@@ -32,10 +32,13 @@ Other workloads (each prints its own JSON line; none is the headline):
               of a rational pseudofermion action), FP64, against 12
               single-shift solves
 
-Measurement helper: --hop-probe Lx Ly Lz Lt PREC NRHS launches the even/odd
-hop (NRHS > 1: the batched hop over NRHS right-hand sides) 20 times and a
-plain 512 MiB device copy, for rocprofv3 kernel traces and FETCH_SIZE /
-WRITE_SIZE counter passes (the copy calibrates the counters).
+Measurement helpers (no JSON line), for rocprofv3 kernel traces and counter
+passes: --hop-probe Lx Ly Lz Lt PREC NRHS launches the even/odd hop (NRHS >
+1: the batched hop over NRHS right-hand sides) as often as the bench line
+times it, and a plain 512 MiB device copy that calibrates FETCH_SIZE /
+WRITE_SIZE; --force-kernels launches the staple force and the fermion-force
+adjoint 10 times each on 24^3x48 and 32^3x64, then one stout level forward
+and backward 5 times on 32^3x64 (links tiled from seeded 8^4 fields).
 
 Study (not a timing): --study dh-vs-dt runs HMC chains (Metropolis) for the
 paper's step-size test, 8^4 leapfrog and 6^4 stout (rho 0.3) with the
@@ -44,6 +47,7 @@ rms Delta H, <exp(-Delta H)> and acceptance against dt.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--config 2|3|4|5]
                        [--multishift] [--stout-depth N] [--study dh-vs-dt] [--hop-probe Lx Ly Lz Lt PREC NRHS]
+                       [--force-kernels]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -132,6 +136,8 @@ def main():
     ap.add_argument("--hop-shapes", action="store_true",
                     help="time the two work shapes of the hop kernel (hop alone and inside the force)")
     ap.add_argument("--study", default=None, choices=("dh-vs-dt", "reliable-delta"))
+    ap.add_argument("--force-kernels", action="store_true",
+                    help="launch the staple-force, bilinear and stout kernels for rocprofv3 (no JSON line)")
     ap.add_argument("--hop-probe", nargs="+", default=None, metavar="ARG",
                     help="LX LY LZ LT PREC NRHS [valu|mfma]: launch the hop kernel and a calibration copy for "
                          "rocprofv3 (no JSON line)")
@@ -146,6 +152,9 @@ def main():
         sys.exit(2)
     if args.hop_probe:
         hop_probe(args.hop_probe)
+        return
+    if args.force_kernels:
+        force_kernels_probe()
         return
     if args.study == "dh-vs-dt":
         print(json.dumps(study_dh_vs_dt(args)), flush=True)
@@ -552,6 +561,40 @@ def hop_probe(argv):
     src = MHOP_SOURCES if nrhs > 1 else HOP_SOURCES
     print(f"hop {dims} {prec} nrhs {nrhs} kernel {kind}: {ms * 1e3:.2f} us per launch; copy of {a.numel() * 8 >> 20} MiB x5 done; "
           f"kernel_sources_sha {kernel_sources_sha(src)}", flush=True)
+
+
+def force_kernels_probe():
+    """The staple force and the fermion-force adjoint 10 times each on 24^3x48
+    and 32^3x64, then one stout level (rho 0.1) forward and backward 5 times on
+    32^3x64, fields tiled from seeded 8^4 ones: for rocprofv3 kernel traces
+    and counter passes of these kernels."""
+    import numpy as np
+    import torch
+
+    import lgt_inputs as li
+    import paper_2602_20516_amd as lgt
+    for dims in ((24, 24, 24, 48), (32, 32, 32, 64)):
+        reps = tuple(d // 8 for d in dims[::-1])
+        U = torch.from_numpy(_tiled_links(dims)).to("cuda")
+        a = torch.from_numpy(np.tile(li.gaussian_spinor((8,) * 4, 902), reps + (1, 1))).to("cuda")
+        b = torch.from_numpy(np.tile(li.gaussian_spinor((8,) * 4, 903), reps + (1, 1))).to("cuda")
+        lat = lgt.Lattice(dims)
+        out = lat.empty_gauge()
+        for _ in range(10):
+            lat.gauge_force(U, 6.0, out=out)
+            lat.bilinear_force(U, a, b, 0.13, -2.0, out=out)
+        del a, b
+        if dims[3] == 64:
+            G = torch.from_numpy(np.tile(li.random_links((8,) * 4, 0.5, 905), reps + (1, 1, 1))).to("cuda")
+            gout = lat.empty_gauge()
+            for _ in range(5):
+                lat.stout_smear(U, 0.1, 1, out=out)
+                lat.stout_backprop(U, G, 0.1, 1, out=gout)
+            del G, gout
+        torch.cuda.synchronize()
+        print(f"force kernels {dims} done", flush=True)
+        del U, out, lat
+        torch.cuda.empty_cache()
 
 
 def _rel(a, b):
