@@ -739,7 +739,7 @@ __device__ __forceinline__ int batch_action(const BatchState* st, int nr) {
 // (i = thread, thread + 256, ...) for all of them, then one butterfly per
 // right-hand side and the four waves in order -- the order of block_sum, so
 // the sums are those of one block_sum per right-hand side, without its 2 nr
-// barriers and nr dependent load rounds (16^4 x 12: 18 -> ~4 us a launch).
+// barriers and nr dependent load rounds.
 __global__ __launch_bounds__(256) void k_mfinalize(int mode, int nblk, int nr, const double* __restrict__ partials,
                                                    BatchState* st, double* result, double tol, int max_iter,
                                                    Mailbox* mb) {
