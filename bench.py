@@ -9,8 +9,9 @@ steps use the mixed-precision solver (FP32 inner CG, FP64 reliable updates);
 the same K calls in plain FP64 are timed after them and reported beside it.
 
 Also reported: the roofline of the CG's dominant kernel (the even/odd hop),
-timed with HIP events on the library's stream, and the FP64 CPU oracle timed
-on a bounded sample of the same call on this host.
+timed with HIP events on the library's stream; the staple (plaquette) force
+of the same workload, with its error against the stored oracle values; and
+the FP64 CPU oracle timed on a bounded sample of the same call on this host.
 
 Other workloads (each prints its own JSON line; none is the headline):
   --config 3  24^3x48, kappa 0.13: force call, mixed (FP32 and BF16-stored
@@ -271,6 +272,8 @@ def main():
             bar[name]["meets_bar"] = fo[name]["sampled_rel_err"] <= 1e-9 and fo[name]["norm_rel_diff"] <= 1e-9
     bar["speedup_mixed_vs_fp64"] = round(bar["fp64"]["ms_per_call"] / bar["mixed"]["ms_per_call"], 3)
     log(f"bench: at the force bar {bar}")
+    staple = _staple_force_16(lat, U, beta, V, args.steps)
+    log(f"bench: staple force {staple}")
     copy_gbs = _copy_ceiling()
     log(f"bench: device copy ceiling {copy_gbs:.0f} GB/s")
 
@@ -329,12 +332,56 @@ def main():
                                                       "weight, one Schur solve per force; not the metric"),
         "force_vs_oracle": force_vs_oracle,
         "at_force_bar": bar,
+        "staple_force": staple,
         "roofline": hop,
     }
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(u, eta, kappa, tol, args.cpu_budget)
     print(json.dumps(rec), flush=True)
+
+
+def _staple_force_16(lat, U, beta, V, steps):
+    """The plaquette (staple) force of the same workload, the second force of
+    a molecular-dynamics step: ms per lgt_gauge_force call (HIP events over
+    10 x steps calls; a call packs the links, then runs the staple kernel
+    with canonical FP64 output), its bytes (pack: U read and its packed copy
+    written; staple force: packed U read, F written -- 288 reals per site)
+    and the staple kernel's ~10.8 kflop per site, and the force's error
+    against the oracle's values stored for this workload."""
+    import numpy as np
+    import torch
+
+    out = lat.empty_gauge()
+    for _ in range(3):
+        lat.gauge_force(U, beta, out=out)
+    n = 10 * max(1, steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(n):
+        lat.gauge_force(U, beta, out=out)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    byts, flops = 288 * 8 * V, 10.8e3 * V
+    rec = {"ms_per_call": round(ms, 5),
+           "bytes_model": "288 reals per site: link pack (U read, packed copy written) + staple kernel "
+                          "(packed U read, F written)",
+           "algorithmic_bytes": byts, "achieved_GBs": round(byts / ms / 1e6, 1),
+           "frac_of_8TBs": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4),
+           "fp64_flops_model": "10.8 kflop per site (staple kernel)", "fp64_TFLOPs": round(flops / ms / 1e9, 2),
+           "note": "16^4 links sit in the 256 MB last-level cache; the staple kernel alone, out of the "
+                   "cache, is in profiles/force_kernels_24x24x24x48_32x32x32x64.json"}
+    gold = _golden("c2_16x16x16x16.json")
+    if gold is not None:
+        F = out.cpu().numpy()
+        links = [tuple(l) for l in gold["links"]]
+        ref = np.array([[complex(*v) for v in m] for m in gold["F_gauge"]]).reshape(-1, 3, 3)
+        got = np.stack([F[l] for l in links])
+        rec["vs_oracle"] = {"sampled_rel_err": float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel())),
+                            "norm_rel_diff": float(abs(np.linalg.norm(F.ravel()) - gold["F_gauge_fro"])
+                                                   / gold["F_gauge_fro"])}
+    return rec
 
 
 def _golden(name):
