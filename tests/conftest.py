@@ -22,8 +22,8 @@ def pytest_configure(config):
 def margin(request):
     """check(what, err, bound): assert err < bound and record both.
 
-    The records go to $LGT_MARGINS_FILE, else gpurun_out/parity_margins.json
-    under the repository root, at the end of the session."""
+    The records go to $LGT_MARGINS_FILE, else parity_margins.json at the
+    repository root (not tracked), at the end of the session."""
     def check(what, err, bound):
         err = float(err)
         _MARGINS.append({"test": request.node.nodeid, "what": what, "err": err, "gate": float(bound),
@@ -36,7 +36,7 @@ def margin(request):
 def pytest_sessionfinish(session, exitstatus):
     if not _MARGINS:
         return
-    path = os.environ.get("LGT_MARGINS_FILE") or os.path.join(ROOT, "gpurun_out", "parity_margins.json")
+    path = os.environ.get("LGT_MARGINS_FILE") or os.path.join(ROOT, "parity_margins.json")
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         worst = max(_MARGINS, key=lambda m: m["ratio"])
