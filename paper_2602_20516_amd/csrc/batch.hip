@@ -256,7 +256,7 @@ struct BatchSolver {
     LGT_HIP(launch_mnorm<double>(c->vh, 12, nr, rhs, red(), c->stream));
     read_results(nr);
     std::vector<double> target(nr), sigma(nr);
-    std::vector<int> verified(nr, 0), iters(nr, 0);
+    std::vector<int> verified(nr, 0);
     for (int k = 0; k < nr; ++k) {
       const double bb = c->host_result[k];
       if (!std::isfinite(bb)) throw Error(LGT_ERR_NONFINITE, "right-hand side holds NaN or Inf");
@@ -310,10 +310,7 @@ struct BatchSolver {
         const double rr64 = c->host_result[k];
         if (!std::isfinite(rr64)) throw Error(LGT_ERR_NONFINITE, "non-finite residual in the batched solve");
         st[k].reliable += verified[k] ? 0 : 1;
-        if (!verified[k] && rr64 <= target[k]) {
-          verified[k] = 1;
-          iters[k] = s.iter;
-        }
+        if (!verified[k] && rr64 <= target[k]) verified[k] = 1;
         if (verified[k]) {
           s.done[k] = kDoneConverged;
           w->hint[k] = 0;
@@ -332,7 +329,6 @@ struct BatchSolver {
         s.done[k] = s.iter >= o.max_iter ? kDoneMaxIter : kDoneRunning;
         if (s.done[k] == kDoneMaxIter) {
           verified[k] = 1;
-          iters[k] = s.iter;
           st[k].converged = false;
         }
       }
@@ -344,7 +340,9 @@ struct BatchSolver {
       LGT_HIP(launch_mrescale(c->vh, nr, r64, vec(vSigma), rs, ps, w->dint, vec(vPscale), c->stream));
       write_state();
     }
-    for (int k = 0; k < nr; ++k) st[k].iters += iters[k];
+    // each right-hand side's count is the iterations its own recursion ran
+    // (a stopped one idles until the batch's update without counting)
+    for (int k = 0; k < nr; ++k) st[k].iters += s.work[k];
   }
 
   void solve_M(bool dag, double2* z, const double2* b, double tol) {

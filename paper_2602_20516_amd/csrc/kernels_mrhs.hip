@@ -800,6 +800,7 @@ __global__ __launch_bounds__(256) void k_mfinalize(int mode, int nblk, int nr, c
       st->alpha[n] = st->beta[n] = st->pap[n] = 0.0;
       st->done[n] = !isfinite(rr) ? kDoneBreakdown : (rr == 0.0 ? kDoneConverged : kDoneRunning);
       st->conv_iter[n] = 0;
+      st->work[n] = 0;
       all &= st->done[n] != kDoneRunning;
     }
     st->all_done = all;
@@ -811,7 +812,8 @@ __global__ __launch_bounds__(256) void k_mfinalize(int mode, int nblk, int nr, c
   const double d2 = st->delta2;
   for (int n = 0; n < nr; ++n) {
     if (st->done[n] == kDoneUpdate) st->done[n] = kDoneUpdateHeld;
-    if (st->done[n] == kDoneRunning) {
+    if (st->done[n] == kDoneRunning) {  // the iteration ran for this right-hand side
+      st->work[n] += 1;
       const double rr = tot[n];
       st->beta[n] = rr / st->rr[n];
       st->rr[n] = rr;

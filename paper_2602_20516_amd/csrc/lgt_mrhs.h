@@ -18,6 +18,7 @@ struct BatchState {
   double delta2;
   int done[kMaxRhs];
   int conv_iter[kMaxRhs];
+  int work[kMaxRhs];  // iterations in which the right-hand side's recursion ran (its iteration count)
   double rr[kMaxRhs], pap[kMaxRhs], alpha[kMaxRhs], beta[kMaxRhs], rr_stop[kMaxRhs], rr_max[kMaxRhs];
 };
 

@@ -117,10 +117,12 @@ def test_batch_with_systems_that_stop_at_once(lgt, precision, margin):
     # D = 1: the true residual is phi - X itself
     assert st[1]["true_rel_residual"] <= 1e-12
     margin("rel_err(to_host(Xs[1]), etas[1]) < 2e-12 and rel_err(to_host(Ys[1]), etas[1])", rel_err(to_host(Xs[1]), etas[1]) < 2e-12 and rel_err(to_host(Ys[1]), etas[1]), 2e-12)
-    if precision == "fp64":
-        # (a mixed batch counts a system's iterations up to the reliable update
-        # that verifies it, and a stopped system waits for the batch's update)
-        assert st[1]["iters"] <= 2
+    # a system's count is the iterations its own recursion ran (a stopped
+    # one idles until the batch's reliable update without counting), summed
+    # over the two Schur solves: with D = 1 one per solve in FP64; the FP32
+    # recursion takes one per reliable-update cycle, and two cycles (about 7
+    # digits each) reach 1e-12
+    assert st[1]["iters"] <= (2 if precision == "fp64" else 4)
     for i, eta in ((0, etas[0]), (3, etas[2])):
         assert st[i]["true_rel_residual"] <= 1e-12
         x_ref, _, _, _ = solver.solve_ddag_d(u, phis[i], kappas[i], tol=1e-14)
