@@ -59,7 +59,7 @@ void lgt_ctx_free_batch(lgt_ctx* c) {
 }
 
 // per-RHS device arrays (slots of kMaxRhs doubles)
-enum { vOne = 0, vKap = 1, vMKap = 2, vMK2 = 3, vSigma = 4, vPscale = 5, vScale = 6 };
+enum { vOne = 0, vKap = 1, vMKap = 2, vMK2 = 3, vSigma = 4, vPscale = 5, vScale = 6, vUnverified = 7 };
 
 static BatchWork* batch_work(lgt_ctx* c, int nr) {
   if (c->batch && c->batch->nr >= nr) return c->batch;
@@ -183,26 +183,28 @@ struct BatchSolver {
 
   template <typename R, bool DAG>
   void mhop(int p_out, const R2<R>* gauge, const R2<R>* in, R2<R>* out, const R2<R>* self, const double* coef,
-            BatchState* guard = nullptr, const double* pap = nullptr) {
+            BatchState* guard = nullptr, const double* pap = nullptr, const double* mask = nullptr) {
     HopIn<R> hin{gauge, in, in};
     LGT_HIP((launch_mhop_axpy<R, DAG>(c->g, nr, gsize<R>(), p_out, hin, out, out, self, self, coef, c->stream, guard, pap,
-                                       red())));
+                                       red(), mask)));
   }
 
-  // out = Mhat^dag Mhat x (FP64), scratch: even half of bW0, odd half of bW4
-  void apply_normal64(bool dag, const double2* x, double2* out) {
+  // out = Mhat^dag Mhat x (FP64) for the right-hand sides with mask[n] != 0
+  // (all if mask is null; the others' out is left as it was), scratch: even
+  // half of bW0, odd half of bW4
+  void apply_normal64(bool dag, const double2* x, double2* out, const double* mask = nullptr) {
     double2* t = F(bW0);
     double2* wv = F(bW4) + halfn();
     if (!dag) {
-      mhop<double, false>(0, c->U64, x, t, nullptr, vec(vOne));
-      mhop<double, false>(1, c->U64, t, wv, x, vec(vMK2));
-      mhop<double, true>(0, c->U64, wv, t, nullptr, vec(vOne));
-      mhop<double, true>(1, c->U64, t, out, wv, vec(vMK2));
+      mhop<double, false>(0, c->U64, x, t, nullptr, vec(vOne), nullptr, nullptr, mask);
+      mhop<double, false>(1, c->U64, t, wv, x, vec(vMK2), nullptr, nullptr, mask);
+      mhop<double, true>(0, c->U64, wv, t, nullptr, vec(vOne), nullptr, nullptr, mask);
+      mhop<double, true>(1, c->U64, t, out, wv, vec(vMK2), nullptr, nullptr, mask);
     } else {
-      mhop<double, true>(0, c->U64, x, t, nullptr, vec(vOne));
-      mhop<double, true>(1, c->U64, t, wv, x, vec(vMK2));
-      mhop<double, false>(0, c->U64, wv, t, nullptr, vec(vOne));
-      mhop<double, false>(1, c->U64, t, out, wv, vec(vMK2));
+      mhop<double, true>(0, c->U64, x, t, nullptr, vec(vOne), nullptr, nullptr, mask);
+      mhop<double, true>(1, c->U64, t, wv, x, vec(vMK2), nullptr, nullptr, mask);
+      mhop<double, false>(0, c->U64, wv, t, nullptr, vec(vOne), nullptr, nullptr, mask);
+      mhop<double, false>(1, c->U64, t, out, wv, vec(vMK2), nullptr, nullptr, mask);
     }
   }
 
@@ -297,20 +299,27 @@ struct BatchSolver {
         stopped += s.done[k] != kDoneRunning;
       }
       if (!s.all_done && 2 * stopped < active) continue;  // nothing posted for long (see drive)
-      // reliable update for every right-hand side
-      for (int k = 0; k < nr; ++k) w->hvec[vScale * kMaxRhs + k] = 1.0 / sigma[k];
+      // reliable update for every right-hand side not yet verified (a
+      // verified one's solution is final: its FP64 residual is not formed,
+      // and the batched hops skip it)
+      for (int k = 0; k < nr; ++k) {
+        w->hvec[vScale * kMaxRhs + k] = 1.0 / sigma[k];
+        w->hvec[vUnverified * kMaxRhs + k] = verified[k] ? 0.0 : 1.0;
+      }
       upload_vecs();
       LGT_HIP(launch_mmixed_update(c->vh, nr, xs, z, vec(vScale), c->stream));
-      apply_normal64(dag, z, r64);
+      apply_normal64(dag, z, r64, vec(vUnverified));
       LGT_HIP(launch_xmy64((int)n, rhs, r64, c->stream));
       LGT_HIP(launch_mnorm<double>(c->vh, 12, nr, r64, red(), c->stream));
       read_results(nr);
       bool all = true;
       for (int k = 0; k < nr; ++k) {
         const double rr64 = c->host_result[k];
-        if (!std::isfinite(rr64)) throw Error(LGT_ERR_NONFINITE, "non-finite residual in the batched solve");
-        st[k].reliable += verified[k] ? 0 : 1;
-        if (!verified[k] && rr64 <= target[k]) verified[k] = 1;
+        if (!verified[k]) {
+          if (!std::isfinite(rr64)) throw Error(LGT_ERR_NONFINITE, "non-finite residual in the batched solve");
+          st[k].reliable += 1;
+          if (rr64 <= target[k]) verified[k] = 1;
+        }
         if (verified[k]) {
           s.done[k] = kDoneConverged;
           w->hint[k] = 0;

@@ -38,11 +38,14 @@ struct MEpiAxpy {  // out = self + coef_n * acc
   const R2<R>* self[2];
   const double* coef;  // [NR] device array
   const BatchState* guard;
+  const double* mask;  // if set: right-hand side n is computed only where mask[n] != 0
   const double* pap_partials;  // block 0 forms alpha_n (see tail)
   int pap_nblk;
   BatchState* state;
   __device__ bool skip() const { return guard && guard->all_done; }
-  __device__ bool rhs_active(int n) const { return !guard || guard->done[n] == kDoneRunning; }
+  __device__ bool rhs_active(int n) const {
+    return (!mask || mask[n] != 0.0) && (!guard || guard->done[n] == kDoneRunning);
+  }
   __device__ void apply(int p, size_t o, int n, C<R> a, double&) const {
     C<R> v = R(coef[n]) * a;
     if (self[p]) v += ld<R>(self[p] + o);
@@ -520,8 +523,9 @@ int mrhs_hop_blocks(const Geom& g, int p_out) { return p_out >= 0 ? mrhs_nbp(g, 
 template <typename R, bool DAG>
 hipError_t launch_mhop_axpy(const Geom& g, int nr, int G, int p_out, HopIn<R> hin, R2<R>* out_e, R2<R>* out_o,
                             const R2<R>* self_e, const R2<R>* self_o, const double* coef, hipStream_t s,
-                            BatchState* guard, const double* pap_partials, Reduce red) {
+                            BatchState* guard, const double* pap_partials, Reduce red, const double* mask) {
   MEpiAxpy<R> e;
+  e.mask = mask;
   e.out[0] = out_e;
   e.out[1] = out_o;
   e.self[0] = self_e;
@@ -571,7 +575,7 @@ hipError_t launch_mhop_residual(const Geom& g, int nr, int G, HopIn<double> hin,
 #define LGT_INST_MHOP(R, DAG)                                                                                   \
   template hipError_t launch_mhop_axpy<R, DAG>(const Geom&, int, int, int, HopIn<R>, R2<R>*, R2<R>*,             \
                                                 const R2<R>*, const R2<R>*, const double*, hipStream_t,          \
-                                                BatchState*, const double*, Reduce);                             \
+                                                BatchState*, const double*, Reduce, const double*);              \
   template hipError_t launch_mhop_schur_norm<R, DAG>(const Geom&, int, int, HopIn<R>, R2<R>*, const R2<R>*,      \
                                                       const double*, BatchState*, Reduce, hipStream_t);         \
   template hipError_t launch_mhop_schur_cg<R, DAG>(const Geom&, int, int, HopIn<R>, const R2<R>*, R2<R>*, R2<R>*, \

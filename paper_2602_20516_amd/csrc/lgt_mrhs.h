@@ -31,11 +31,14 @@ int mrhs_hop_blocks(const Geom& g, int p_out);
 // sides per block (1..nr; the links are loaded once per group of G) for the
 // VALU kernel, or G = -4 / -8 for the MFMA kernel (FP32 only) with groups
 // of 4 or 8 right-hand sides.
-// out = self + coef_n H in  (coef: device array [nr]); guard/pap_partials as launch_hop_axpy
+// out = self + coef_n H in  (coef: device array [nr]); guard/pap_partials as launch_hop_axpy;
+// mask (device array [nr], optional): only the right-hand sides with mask[n] != 0 are
+// computed, the others' output is left as it was
 template <typename R, bool DAG>
 hipError_t launch_mhop_axpy(const Geom& g, int nr, int G, int p_out, HopIn<R> hin, R2<R>* out_e, R2<R>* out_o,
                             const R2<R>* self_e, const R2<R>* self_o, const double* coef, hipStream_t s,
-                            BatchState* guard, const double* pap_partials, Reduce red);
+                            BatchState* guard, const double* pap_partials, Reduce red,
+                            const double* mask = nullptr);
 template <typename R, bool DAG>
 hipError_t launch_mhop_schur_norm(const Geom& g, int nr, int G, HopIn<R> hin, R2<R>* w, const R2<R>* x,
                                   const double* coef, BatchState* st, Reduce red, hipStream_t s);
