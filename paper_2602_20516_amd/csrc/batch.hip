@@ -7,7 +7,8 @@
 // recursion per right-hand side on its residual scaled to unit norm; each
 // recursion stops itself on the device at its reliable-update threshold
 // (as in the single solve), and once half of them have stopped the host
-// updates every right-hand side in FP64.
+// updates in FP64 every right-hand side not yet verified (a verified
+// solution is final and drops out of the batched hops).
 #include <algorithm>
 #include <cmath>
 
