@@ -211,7 +211,7 @@ hipError_t launch_finalize(int mode, int nblk, Reduce red, SolverState* st, int 
 template <typename R, typename T>
 __global__ __launch_bounds__(256) void k_cg_step(int n, int nblk, const double* __restrict__ partials,
                                                  const R2<R>* __restrict__ r, T* __restrict__ p, SolverState* st,
-                                                 Mailbox* mb) {
+                                                 Mailbox* mb, R2<R>* __restrict__ x) {
   const int done0 = st->done;
   if (done0 != kDoneRunning) {  // the iteration was skipped (or block 0 below already stopped it)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -238,26 +238,35 @@ __global__ __launch_bounds__(256) void k_cg_step(int n, int nblk, const double* 
   else if (rr <= st->rr_stop) code = st->delta2 > 0.0 ? kDoneUpdate : kDoneConverged;
   else if (rr <= st->delta2 * rr_max) code = kDoneUpdate;
   else if (iter >= st->max_iter) code = kDoneMaxIter;
-  if (code == kDoneRunning) {
-    // four elements per thread and trip, all loads issued before the stores
-    const R b = R(beta);
+  {
+    // x += alpha p (this iteration's step, taken whatever the decision), then
+    // p = r + beta p unless the recursion stops; four elements per thread and
+    // trip, all loads issued before the stores
+    const R b = R(beta), a = R(st->alpha);
+    const bool upd = code == kDoneRunning;
     const int stride = gridDim.x * 256;
     int i = blockIdx.x * 256 + threadIdx.x;
     for (; i + 3 * stride < n; i += 4 * stride) {
-      C<R> rv[4], pv[4];
+      C<R> rv[4], pv[4], xv[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        rv[j] = ld<R>(r + i + j * stride);
         pv[j] = Store<R, T>::ld(p + i + j * stride);
+        xv[j] = ld<R>(x + i + j * stride);
+        if (upd) rv[j] = ld<R>(r + i + j * stride);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        Store<R, T>::st(p + i + j * stride, C<R>{rv[j].re + b * pv[j].re, rv[j].im + b * pv[j].im});
+      for (int j = 0; j < 4; ++j) {
+        lgt::st<R>(x + i + j * stride, xv[j] + a * pv[j]);
+        if (upd) Store<R, T>::st(p + i + j * stride, C<R>{rv[j].re + b * pv[j].re, rv[j].im + b * pv[j].im});
+      }
     }
     for (; i < n; i += stride) {
-      const C<R> rv = ld<R>(r + i);
       const C<R> pv = Store<R, T>::ld(p + i);
-      Store<R, T>::st(p + i, C<R>{rv.re + b * pv.re, rv.im + b * pv.im});
+      lgt::st<R>(x + i, ld<R>(x + i) + a * pv);
+      if (upd) {
+        const C<R> rv = ld<R>(r + i);
+        Store<R, T>::st(p + i, C<R>{rv.re + b * pv.re, rv.im + b * pv.im});
+      }
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -271,7 +280,8 @@ __global__ __launch_bounds__(256) void k_cg_step(int n, int nblk, const double* 
 }
 
 template <typename R, typename T>
-hipError_t launch_cg_step(int n, const R2<R>* r, T* p, SolverState* st, Reduce red, int nblk, hipStream_t s) {
+hipError_t launch_cg_step(int n, const R2<R>* r, T* p, SolverState* st, Reduce red, int nblk, hipStream_t s,
+                          R2<R>* x) {
   if (nblk > red.capacity) return hipErrorInvalidValue;
   // each block also sums the nblk partials (a few thousand on large
   // lattices).  With 8-byte elements (FP32, BF16 pairs) a grid of about four
@@ -281,15 +291,15 @@ hipError_t launch_cg_step(int n, const R2<R>* r, T* p, SolverState* st, Reduce r
   // blocks), which is faster for them at 16^4 (6.3 against 7.1 us).
   const int nb = sizeof(R) == 4 ? std::max(1, std::min((n + 1023) / 1024, 1024))
                                 : std::max(1, std::min((n + 255) / 256, 2048));
-  hipLaunchKernelGGL((k_cg_step<R, T>), dim3(nb), dim3(256), 0, s, n, nblk, red.partials, r, p, st, red.mbox);
+  hipLaunchKernelGGL((k_cg_step<R, T>), dim3(nb), dim3(256), 0, s, n, nblk, red.partials, r, p, st, red.mbox, x);
   return hipGetLastError();
 }
 template hipError_t launch_cg_step<double, double2>(int, const double2*, double2*, SolverState*, Reduce, int,
-                                                    hipStream_t);
+                                                    hipStream_t, double2*);
 template hipError_t launch_cg_step<float, float2>(int, const float2*, float2*, SolverState*, Reduce, int,
-                                                  hipStream_t);
+                                                  hipStream_t, float2*);
 template hipError_t launch_cg_step<float, Bf16c>(int, const float2*, Bf16c*, SolverState*, Reduce, int,
-                                                 hipStream_t);
+                                                 hipStream_t, float2*);
 
 __global__ __launch_bounds__(256) void k_norm_dot(int n, const double2* __restrict__ a,
                                                   const double2* __restrict__ b, double* partials) {

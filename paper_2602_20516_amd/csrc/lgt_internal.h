@@ -184,7 +184,8 @@ hipError_t launch_hop_residual(const Geom& g, HopIn<double> hin, const double2* 
 // launch_rescale_residual); the new state and the mailbox post come from
 // block 0.  A skipped iteration only posts (and holds an update).
 template <typename R, typename T>
-hipError_t launch_cg_step(int n, const R2<R>* r, T* p, SolverState* st, Reduce red, int nblk, hipStream_t s);
+hipError_t launch_cg_step(int n, const R2<R>* r, T* p, SolverState* st, Reduce red, int nblk, hipStream_t s,
+                          R2<R>* x);
 template <typename R>
 hipError_t launch_cg_init(int n, const R2<R>* b, R2<R>* r, R2<R>* p, R2<R>* x, SolverState* st,
                           Reduce red, double tol, int max_iter, hipStream_t s);

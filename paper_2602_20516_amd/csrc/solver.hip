@@ -135,8 +135,11 @@ static void cg_iteration(const Geom& g, const R2<R>* gauge, double kappa, T* t, 
   // block 0 also forms alpha from the |w|^2 partials
   LGT_HIP((launch_hop_axpy<R, !DAG, T>(g, 0, HopIn<R, T>{gauge, w, w, nk}, t2, t2, nullptr, nullptr, 1.0, s, st,
                                          red.partials)));
-  LGT_HIP((launch_hop_schur_cg<R, T, !DAG>(g, HopIn<R, T>{gauge, t2, t2, nk}, w, x, r, p, k2, st, red, s)));
-  if (!fuse) LGT_HIP((launch_cg_step<R, T>(n, r, p, st, red, hop_blocks(g, 1), s)));
+  // x += alpha p: in the fourth hop's epilogue on the fused path, else in the
+  // step kernel, which reads p anyway
+  LGT_HIP((launch_hop_schur_cg<R, T, !DAG>(g, HopIn<R, T>{gauge, t2, t2, nk}, w, fuse ? x : nullptr, r, p, k2, st,
+                                           red, s)));
+  if (!fuse) LGT_HIP((launch_cg_step<R, T>(n, r, p, st, red, hop_blocks(g, 1), s, x)));
 }
 
 // CG on Mhat^dag Mhat z = rhs (odd half fields), FP64.  Returns the state's done code.
