@@ -217,9 +217,10 @@ struct BatchSolver {
     LGT_HIP((launch_mhop_schur_norm<R, DAG>(c->g, nr, gsize<R>(), h2, wv, p, vec(vMK2), w->st, red(), c->stream)));
     mhop<R, !DAG>(0, gauge, wv, t, nullptr, vec(vOne), w->st, w->partials);
     HopIn<R> h4{gauge, t, t};
-    LGT_HIP((launch_mhop_schur_cg<R, !DAG>(c->g, nr, gsize<R>(), h4, wv, x, r, p, vec(vMK2), w->st, red(),
+    // x += alpha p moves to the direction update, which reads p anyway
+    LGT_HIP((launch_mhop_schur_cg<R, !DAG>(c->g, nr, gsize<R>(), h4, wv, nullptr, r, p, vec(vMK2), w->st, red(),
                                             c->stream)));
-    LGT_HIP(launch_mxpay<R>(c->vh, nr, r, p, w->st, c->stream));
+    LGT_HIP(launch_mxpay<R>(c->vh, nr, r, p, x, w->st, c->stream));
   }
 
   void cg64(bool dag, double2* z, const double2* rhs, double tol) {

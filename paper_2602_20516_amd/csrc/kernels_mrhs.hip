@@ -89,7 +89,7 @@ struct MEpiSchurNorm {  // w = x + coef_n acc, per-RHS |w|^2
 };
 
 template <typename R>
-struct MEpiSchurCG {  // q = w + coef_n acc; x += alpha_n p; r -= alpha_n q (unless converged)
+struct MEpiSchurCG {  // q = w + coef_n acc; r -= alpha_n q (unless converged); x += alpha_n p if x is set
   static constexpr bool kReduce = true;
   const R2<R>* w;
   R2<R>* x;
@@ -104,7 +104,7 @@ struct MEpiSchurCG {  // q = w + coef_n acc; x += alpha_n p; r -= alpha_n q (unl
     if (!state->done[n]) {
       const R alpha = R(state->alpha[n]);
       const C<R> q = ld<R>(w + o) + R(coef[n]) * a;
-      st<R>(x + o, ld<R>(x + o) + alpha * ld<R>(p + o));
+      if (x) st<R>(x + o, ld<R>(x + o) + alpha * ld<R>(p + o));
       rv = rv - alpha * q;
       st<R>(r + o, rv);
     }
@@ -631,30 +631,47 @@ hipError_t launch_mnorm(int vh, int ncomp, int nr, const R2<R>* a, Reduce red, h
 template hipError_t launch_mnorm<double>(int, int, int, const double2*, Reduce, hipStream_t);
 template hipError_t launch_mnorm<float>(int, int, int, const float2*, Reduce, hipStream_t);
 
-// p = r + beta_n p for right-hand sides still running or stopping for an update
+// After the finalize of an iteration: x += alpha_n p for every right-hand
+// side whose recursion ran it (still running, or stopped by this finalize:
+// conv_iter == iter; nothing in an iteration queued after the whole batch
+// stopped, whose finalize leaves iter as it was and sets idle), then
+// p = r + beta_n p where the recursion goes on or waits for the update.  The x update is here rather than in the Schur-CG
+// epilogue because this kernel reads p anyway.
 template <typename R>
 __global__ __launch_bounds__(256) void k_mxpay(int vh, int nr, const R2<R>* __restrict__ r, R2<R>* __restrict__ p,
-                                               const BatchState* st) {
+                                               R2<R>* __restrict__ x, const BatchState* st) {
+  if (st->idle) return;  // a queued iteration after the batch stopped: nothing ran
   const int n = blockIdx.y % nr;
   const int d = st->done[n];
-  if (d != kDoneRunning && d != kDoneUpdate) return;
+  const bool ran = d == kDoneRunning || st->conv_iter[n] == st->iter;
+  const bool upd = d == kDoneRunning || d == kDoneUpdate;
+  if (!ran && !upd) return;
   const int s = blockIdx.x * 256 + threadIdx.x;
   if (s >= vh) return;
   const size_t i = (size_t)blockIdx.y * vh + s;
-  const R beta = R(st->beta[n]);
-  const R2<R> rv = r[i];
   R2<R> pv = p[i];
-  pv.x = rv.x + beta * pv.x;
-  pv.y = rv.y + beta * pv.y;
-  p[i] = pv;
+  if (ran) {
+    const R alpha = R(st->alpha[n]);
+    R2<R> xv = x[i];
+    xv.x += alpha * pv.x;
+    xv.y += alpha * pv.y;
+    x[i] = xv;
+  }
+  if (upd) {
+    const R beta = R(st->beta[n]);
+    const R2<R> rv = r[i];
+    pv.x = rv.x + beta * pv.x;
+    pv.y = rv.y + beta * pv.y;
+    p[i] = pv;
+  }
 }
 template <typename R>
-hipError_t launch_mxpay(int vh, int nr, const R2<R>* r, R2<R>* p, BatchState* st, hipStream_t s) {
-  hipLaunchKernelGGL((k_mxpay<R>), slab_grid(vh, nr), dim3(256), 0, s, vh, nr, r, p, st);
+hipError_t launch_mxpay(int vh, int nr, const R2<R>* r, R2<R>* p, R2<R>* x, BatchState* st, hipStream_t s) {
+  hipLaunchKernelGGL((k_mxpay<R>), slab_grid(vh, nr), dim3(256), 0, s, vh, nr, r, p, x, st);
   return hipGetLastError();
 }
-template hipError_t launch_mxpay<double>(int, int, const double2*, double2*, BatchState*, hipStream_t);
-template hipError_t launch_mxpay<float>(int, int, const float2*, float2*, BatchState*, hipStream_t);
+template hipError_t launch_mxpay<double>(int, int, const double2*, double2*, double2*, BatchState*, hipStream_t);
+template hipError_t launch_mxpay<float>(int, int, const float2*, float2*, float2*, BatchState*, hipStream_t);
 
 // x64 += scale_n * xs; xs = 0
 __global__ __launch_bounds__(256) void k_mmixed_update(int vh, int nr, float2* xs, double2* __restrict__ x,
@@ -752,6 +769,7 @@ __global__ __launch_bounds__(256) void k_mfinalize(int mode, int nblk, int nr, c
       for (int n = 0; n < nr; ++n)
         if (st->done[n] == kDoneUpdate) st->done[n] = kDoneUpdateHeld;
       st->any_update = 0;
+      st->idle = 1;
       post_progress(mb, st->iter, 1);
     }
     return;
@@ -795,6 +813,7 @@ __global__ __launch_bounds__(256) void k_mfinalize(int mode, int nblk, int nr, c
     st->max_iter = max_iter;
     st->delta2 = 0.0;
     st->any_update = 0;
+    st->idle = 0;
     int all = 1;
     for (int n = 0; n < nr; ++n) {
       const double rr = tot[n];
@@ -811,6 +830,7 @@ __global__ __launch_bounds__(256) void k_mfinalize(int mode, int nblk, int nr, c
     return;
   }
   // kFinCgStep
+  st->idle = 0;
   st->iter += 1;
   int all = 1, any_update = 0;
   const double d2 = st->delta2;

@@ -14,7 +14,8 @@ constexpr int kMaxRhs = 16;
 // device-side stop for reliable updates (kDoneUpdate), any_update says that
 // some right-hand side still has its final direction update to do.
 struct BatchState {
-  int nr, iter, max_iter, all_done, any_update, pad;
+  int nr, iter, max_iter, all_done, any_update;
+  int idle;  // set by an iteration's finalize that found the batch stopped (a queued no-op iteration)
   double delta2;
   int done[kMaxRhs];
   int conv_iter[kMaxRhs];
@@ -56,7 +57,7 @@ template <typename R>
 hipError_t launch_mnorm(int vh, int ncomp, int nr, const R2<R>* a, Reduce red, hipStream_t s);
 // half-field updates, per right-hand side n
 template <typename R>
-hipError_t launch_mxpay(int vh, int nr, const R2<R>* r, R2<R>* p, BatchState* st, hipStream_t s);
+hipError_t launch_mxpay(int vh, int nr, const R2<R>* r, R2<R>* p, R2<R>* x, BatchState* st, hipStream_t s);
 hipError_t launch_mmixed_update(int vh, int nr, float2* xs, double2* x, const double* scale, hipStream_t s);
 hipError_t launch_mrescale(int vh, int nr, const double2* r64, const double* sigma, float2* r, float2* p,
                            const int* restart, const double* pscale, hipStream_t s);
