@@ -154,11 +154,13 @@ hipError_t launch_hop_step(const Geom& g, const R2<R>* gauge, int nk, R2<R>* t, 
 //  (1) t = H p                                      launch_hop_axpy (guard)
 //  (2) w = p + coef H t, |w|^2 partials             launch_hop_schur_norm
 //  (3) t = H^dag w; block 0: alpha = rr / |w|^2    launch_hop_axpy with pap_partials
-//  (4) q = w + coef H^dag t; x += alpha p; r -= alpha q; |r|^2 partials
+//  (4) q = w + coef H^dag t; r -= alpha q; |r|^2 partials
 //                                                   launch_hop_schur_cg
 //  (5) rr, beta and the stop decision (every block sums the partials),
-//      p = r + beta p unless stopping, block 0 records the state and posts
-//                                                   launch_cg_step
+//      x += alpha p, p = r + beta p unless stopping, block 0 records the
+//      state and posts                              launch_cg_step
+// (on small lattices (1) also does (5) of the previous iteration, see
+// launch_hop_step, and (4) then takes the x update)
 // (for the dagger operator the roles of H and H^dag swap).  t, w, p are
 // stored as T; x and r as R2<R>.
 template <typename R, typename T, bool DAG>
@@ -179,8 +181,9 @@ hipError_t launch_hop_residual(const Geom& g, HopIn<double> hin, const double2* 
 // Vector kernels (kernels_field.hip).  n = number of complex elements.
 // End of a CG iteration: rr = sum of the nblk |r|^2 partials of (4), beta =
 // rr / rr_prev, the stop test (target, reliable-update threshold, iteration
-// cap, non-finite), p = r + beta p (p stored as T) unless the recursion
-// stops here (the reliable update then forms the next direction, see
+// cap, non-finite), x += alpha p (the iteration's step, whatever the
+// decision), p = r + beta p (p stored as T) unless the recursion stops here
+// (the reliable update then forms the next direction, see
 // launch_rescale_residual); the new state and the mailbox post come from
 // block 0.  A skipped iteration only posts (and holds an update).
 template <typename R, typename T>
