@@ -159,6 +159,8 @@ struct BatchSolver {
   const SolverOpts& o;
   std::vector<double> kap;
   std::vector<SolveStats> st;  // per right-hand side
+  const float2* links32 = nullptr;  // links of the FP32 inner hops (set by the first mixed solve)
+  int nk32 = 9;
 
   Reduce red() const { return Reduce{w->partials, c->result, 0, w->npart, c->mbox_dev}; }
   template <typename R>
@@ -184,8 +186,8 @@ struct BatchSolver {
 
   template <typename R, bool DAG>
   void mhop(int p_out, const R2<R>* gauge, const R2<R>* in, R2<R>* out, const R2<R>* self, const double* coef,
-            BatchState* guard = nullptr, const double* pap = nullptr, const double* mask = nullptr) {
-    HopIn<R> hin{gauge, in, in};
+            BatchState* guard = nullptr, const double* pap = nullptr, const double* mask = nullptr, int nk = 9) {
+    HopIn<R> hin{gauge, in, in, nk};
     LGT_HIP((launch_mhop_axpy<R, DAG>(c->g, nr, gsize<R>(), p_out, hin, out, out, self, self, coef, c->stream, guard, pap,
                                        red(), mask)));
   }
@@ -209,14 +211,16 @@ struct BatchSolver {
     }
   }
 
+  // gauge: packed links with nk components per link (9, or 6 for the FP32
+  // two-row copy of SU(3) links)
   template <typename R, bool DAG>
-  void iteration(const R2<R>* gauge, R2<R>* t, R2<R>* wv, R2<R>* x, R2<R>* r, R2<R>* p) {
+  void iteration(const R2<R>* gauge, R2<R>* t, R2<R>* wv, R2<R>* x, R2<R>* r, R2<R>* p, int nk = 9) {
     const size_t n = halfn();
-    mhop<R, DAG>(0, gauge, p, t, nullptr, vec(vOne), w->st);
-    HopIn<R> h2{gauge, t, t};
+    mhop<R, DAG>(0, gauge, p, t, nullptr, vec(vOne), w->st, nullptr, nullptr, nk);
+    HopIn<R> h2{gauge, t, t, nk};
     LGT_HIP((launch_mhop_schur_norm<R, DAG>(c->g, nr, gsize<R>(), h2, wv, p, vec(vMK2), w->st, red(), c->stream)));
-    mhop<R, !DAG>(0, gauge, wv, t, nullptr, vec(vOne), w->st, w->partials);
-    HopIn<R> h4{gauge, t, t};
+    mhop<R, !DAG>(0, gauge, wv, t, nullptr, vec(vOne), w->st, w->partials, nullptr, nk);
+    HopIn<R> h4{gauge, t, t, nk};
     // x += alpha p moves to the direction update, which reads p anyway
     LGT_HIP((launch_mhop_schur_cg<R, !DAG>(c->g, nr, gsize<R>(), h4, wv, nullptr, r, p, vec(vMK2), w->st, red(),
                                             c->stream)));
@@ -255,10 +259,20 @@ struct BatchSolver {
     float2* rs = w->h[3];
     float2* ps = w->h[4];
     double2* r64 = F(bW2) + n;
+    // the inner hops read the two-row copy of the links when every link is
+    // SU(3) and the VALU batched hop runs (the MFMA form reads full links);
+    // the check's flag arrives with the sync below
+    const bool first = !links32;
+    if (first) c->compress_links();
     LGT_HIP(launch_zero64((int)n, z, c->stream));
     LGT_HIP(launch_zero32((int)n, xs, c->stream));
     LGT_HIP(launch_mnorm<double>(c->vh, 12, nr, rhs, red(), c->stream));
     read_results(nr);
+    if (first) {
+      const bool two_row = c->host_flags[1] == 0 && gsize<float>() > 0;
+      links32 = two_row ? c->U32c : c->U32;
+      nk32 = two_row ? 6 : 9;
+    }
     std::vector<double> target(nr), sigma(nr);
     std::vector<int> verified(nr, 0);
     for (int k = 0; k < nr; ++k) {
@@ -288,8 +302,8 @@ struct BatchSolver {
     write_state();
     while (!s.all_done) {
       c->drive(s.iter, [&] {
-        if (dag) iteration<float, true>(c->U32, ts, ws, xs, rs, ps);
-        else iteration<float, false>(c->U32, ts, ws, xs, rs, ps);
+        if (dag) iteration<float, true>(links32, ts, ws, xs, rs, ps, nk32);
+        else iteration<float, false>(links32, ts, ws, xs, rs, ps, nk32);
       });
       read_state();
       // the device asks for the update once half of the unverified right-hand
@@ -519,11 +533,23 @@ double lgt_ctx::bench_mhop(int nr, bool f32, const void* psi, int nrep) {
   for (int k = 0; k < kMaxRhs; ++k) w->hvec[vOne * kMaxRhs + k] = 1.0;
   LGT_HIP(hipMemcpyAsync(w->dvec, w->hvec, 8 * kMaxRhs * sizeof(double), hipMemcpyHostToDevice, stream));
   const double* one = w->dvec + vOne * kMaxRhs;
-  if (f32) LGT_HIP(launch_convert_64_32((int)h, w->f[bPhi] + h, w->h[0], stream));
+  // FP32: the links the batched solve's inner hops read (the two-row copy when
+  // every link is SU(3) and the VALU kernel runs)
+  const float2* links32 = U32;
+  int nk32 = 9;
+  if (f32) {
+    LGT_HIP(launch_convert_64_32((int)h, w->f[bPhi] + h, w->h[0], stream));
+    compress_links();
+    sync();
+    if (host_flags[1] == 0 && G > 0) {
+      links32 = U32c;
+      nk32 = 6;
+    }
+  }
   const Reduce red{w->partials, result, 0, w->npart, nullptr};
   auto once = [&] {
     if (f32) {
-      HopIn<float> hin{U32, w->h[0], w->h[0]};
+      HopIn<float> hin{links32, w->h[0], w->h[0], nk32};
       LGT_HIP((launch_mhop_axpy<float, false>(g, nr, G, 0, hin, w->h[1], w->h[1], nullptr, nullptr, one, stream,
                                                nullptr, nullptr, red)));
     } else {

@@ -190,17 +190,35 @@ __global__ __launch_bounds__(256) void k_hop_mrhs(Geom g, int nr, int G, int nbp
     nf = cb_shift(g, c, mu, +1);
     nb = cb_shift(g, c, mu, -1);
   }
-  const BufRsrc ruf = make_rsrc(gptr<R>(hin.gauge, g, p, mu), (size_t)9 * gs);
-  const BufRsrc rub = make_rsrc(gptr<R>(hin.gauge, g, 1 - p, mu), (size_t)9 * gs);
+  // links [2][4][nk][vh]: all nine components, or (FP32) the first two rows
+  // of SU(3) links with the third rebuilt in registers (a third less link
+  // traffic per group, as in the single-field hop)
+  const int nk = hin.nk;
+  const BufRsrc ruf = make_rsrc(hin.gauge + (size_t)((p * 4 + mu) * nk) * g.vh, (size_t)nk * gs);
+  const BufRsrc rub = make_rsrc(hin.gauge + (size_t)(((1 - p) * 4 + mu) * nk) * g.vh, (size_t)nk * gs);
   constexpr bool kKeepLinks = sizeof(R) == 4;
   M3<R> Uf, Ub;
 #pragma unroll
   for (int k = 0; k < 9; ++k) Uf.m[k] = Ub.m[k] = czero<R>();
   if (kKeepLinks && active && act) {
+    if (nk == 9) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      Uf.m[k] = ld_buf<R>(ruf, (unsigned)cb * E, k * gs);
-      Ub.m[k] = ld_buf<R>(rub, (unsigned)nb * E, k * gs);
+      for (int k = 0; k < 9; ++k) {
+        Uf.m[k] = ld_buf<R>(ruf, (unsigned)cb * E, k * gs);
+        Ub.m[k] = ld_buf<R>(rub, (unsigned)nb * E, k * gs);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        Uf.m[k] = ld_buf<R>(ruf, (unsigned)cb * E, k * gs);
+        Ub.m[k] = ld_buf<R>(rub, (unsigned)nb * E, k * gs);
+      }
+      Uf.m[6] = conj(Uf.m[1] * Uf.m[5] - Uf.m[2] * Uf.m[4]);
+      Uf.m[7] = conj(Uf.m[2] * Uf.m[3] - Uf.m[0] * Uf.m[5]);
+      Uf.m[8] = conj(Uf.m[0] * Uf.m[4] - Uf.m[1] * Uf.m[3]);
+      Ub.m[6] = conj(Ub.m[1] * Ub.m[5] - Ub.m[2] * Ub.m[4]);
+      Ub.m[7] = conj(Ub.m[2] * Ub.m[3] - Ub.m[0] * Ub.m[5]);
+      Ub.m[8] = conj(Ub.m[0] * Ub.m[4] - Ub.m[1] * Ub.m[3]);
     }
   }
   for (int n = n0; n < n1; ++n) {
@@ -493,6 +511,7 @@ template <typename R, bool DAG, typename Epi>
 static hipError_t mlaunch(const Geom& g, int nr, int G, int p_out, const HopIn<R>& hin, const Epi& epi, Reduce red,
                           hipStream_t s) {
   if (nr < 1 || nr > kMaxRhs) return hipErrorInvalidValue;
+  if (hin.nk != 9 && (hin.nk != 6 || sizeof(R) != 4)) return hipErrorInvalidValue;  // two-row links: FP32 only
   const int gs = G < 0 ? -G : G;
   if (gs < 1 || gs > kMaxRhs || (G < 0 && gs != 4 && gs != 8)) return hipErrorInvalidValue;
   const int nbp = mrhs_nbp(g, G);
@@ -500,6 +519,7 @@ static hipError_t mlaunch(const Geom& g, int nr, int G, int p_out, const HopIn<R
   const int rows = p_out >= 0 ? nbp : 2 * nbp;
   if (Epi::kReduce && (size_t)rows * kMaxRhs > red.ndoubles) return hipErrorInvalidValue;
   if (G < 0) {
+    if (hin.nk != 9) return hipErrorInvalidValue;  // the MFMA form reads full links
     if constexpr (std::is_same<R, float>::value) {
       if (gs == 8)
         hipLaunchKernelGGL((k_hop_mrhs_mfma<DAG, Epi, 8>), dim3(rows * ngrp), dim3(256), 0, s, g, nr, nbp, ngrp,
