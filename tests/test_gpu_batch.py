@@ -242,3 +242,25 @@ def test_batch_solve_with_each_kernel(lgt, margin):
             margin(f"batched solve ({kind} FP32 hop) X vs oracle kappa {k}", rel_err(to_host(X), x_ref), 1e-9)
     for a, b in zip(iters["valu"], iters["mfma"]):
         assert abs(a - b) <= 3
+
+
+def test_mixed_batch_with_links_outside_su3(lgt, margin):
+    """Links scaled by 0.9 are not SU(3): the batched FP32 hop must read them
+    in full (no third-row reconstruction) and still reach the oracle's
+    answer, in about the iterations of the FP64 batch."""
+    dims = (6, 6, 6, 6)
+    u, items = workload(dims)
+    u = 0.9 * u
+    items = items[::3]
+    phis = [dirac.dslash_dag(u, eta, k) for k, eta in items]
+    lat = lgt.Lattice(dims)
+    U, P, ks = to_dev(u), [to_dev(p) for p in phis], [k for k, _ in items]
+    Xs, _, st = lat.cg_solve_batch(U, P, ks, lgt.Params(precision="mixed_fp32", tol=1e-12))
+    _, _, st64 = lat.cg_solve_batch(U, P, ks, lgt.Params(precision="fp64", tol=1e-12))
+    say("batch outside SU(3)", [s["iters"] for s in st], [s["iters"] for s in st64])
+    for (k, eta), phi, X, s, s64 in zip(items, phis, Xs, st, st64):
+        assert s["true_rel_residual"] <= 1e-12
+        x_ref, _, _, _ = solver.solve_ddag_d(u, phi, k, tol=1e-15)
+        margin(f"batched X vs oracle, links outside SU(3), kappa {k}", rel_err(to_host(X), x_ref), 1e-10)
+        # a wrongly rebuilt third row would cost many more iterations
+        assert s["iters"] <= s64["iters"] + 8
