@@ -514,8 +514,8 @@ HOP_RUNS = 5  # runs of those launches; the bench line quotes the median run
 def _hop_line(lat, U, E, V, prec, nrep=HOP_REPS):
     """Roofline figures of the single-field hop: algorithmic bytes are 96 reals
     per lattice site (all 4V links as full 3x3 matrices, input and output half
-    spinors); the FP32 kernel reads SU(3) links as two rows (72 reals per
-    site), given beside."""
+    spinors); the kernel reads SU(3) links as two rows (72 reals per site),
+    given beside."""
     p = 8 if prec == "fp64" else 4
     # median of HOP_RUNS runs of nrep launches each: one run can catch a
     # disturbance of the GPU (its mean then sits ~10 % high); every run's
@@ -527,9 +527,8 @@ def _hop_line(lat, U, E, V, prec, nrep=HOP_REPS):
     out = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
            "avg_launch_us": round(ms * 1e3, 3), "run_means_us": [round(r * 1e3, 3) for r in runs],
            "algorithmic_bytes_per_launch": alg}
-    if prec != "fp64":
-        out["two_row_bytes_per_launch"] = 72 * p * V
-        out["frac_two_row_bytes"] = round(72 * p * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    out["two_row_bytes_per_launch"] = 72 * p * V
+    out["frac_two_row_bytes"] = round(72 * p * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     return out
 
 
@@ -940,7 +939,7 @@ def bench_hop_shapes(args):
     return {"metric": "hop kernel work shape: 32 vs 64 sites per block", "unit": "us (hop), ms (force)",
             "n_gpus": 1, "higher_is_better": False, "dtype": "f32 / f64",
             "data": "synthetic (seeded SU(3) links eps=0.3, Gaussian eta; phi = D^dag eta, kappa 0.125)",
-            "config": {"workload": "one even/odd hop launch (FP32 two-row links / FP64), and the force call "
+            "config": {"workload": "one even/odd hop launch (two-row links, FP32 / FP64), and the force call "
                                    "(mixed FP32 / FP64 CG to 1e-10) up to 16^3x32; the 64-site hop in both "
                                    "block orders"},
             "rows": rows}

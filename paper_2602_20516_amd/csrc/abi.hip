@@ -211,6 +211,7 @@ lgt_status lgt_destroy(lgt_ctx* c) {
   (void)hipFree(c->U64);
   (void)hipFree(c->U32);
   (void)hipFree(c->U32c);
+  (void)hipFree(c->U64c);
   (void)hipFree(c->P64);
   (void)hipFree(c->state);
   (void)hipFree(c->partials);
@@ -957,20 +958,18 @@ lgt_status lgt_hop_benchmark(lgt_ctx* c, const void* U, const void* psi, int32_t
       b32 = c->h32(6);
       LGT_HIP(launch_convert_64_32((int)h, a + h, a32, c->stream));
     }
-    // FP32: the links in the form the mixed solver's hops read them (two
-    // rows when they are SU(3))
+    // the links in the form the CG hops read them (two rows when they are SU(3))
     int nk = 9;
-    if (f32) {
-      c->compress_links();
-      c->sync();
-      if (c->host_flags[1] == 0) nk = 6;
-    }
+    if (f32) c->compress_links();
+    else c->compress_links64();
+    c->sync();
+    if (c->host_flags[f32 ? 1 : 2] == 0) nk = 6;
     auto once = [&] {
       if (f32) {
         HopIn<float> hin{nk == 6 ? c->U32c : c->U32, a32, a32, nk};
         LGT_HIP((launch_hop_axpy<float, false>(c->g, 0, hin, b32, b32, nullptr, nullptr, 1.0, c->stream)));
       } else {
-        HopIn<double> hin{c->U64, a + h, a + h};
+        HopIn<double> hin{nk == 6 ? c->U64c : c->U64, a + h, a + h, nk};
         LGT_HIP((launch_hop_axpy<double, false>(c->g, 0, hin, b, b, nullptr, nullptr, 1.0, c->stream)));
       }
     };

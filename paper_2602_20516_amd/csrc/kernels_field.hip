@@ -388,32 +388,47 @@ hipError_t launch_convert_64_32(int n, const double2* x, float2* y, hipStream_t 
   return hipGetLastError();
 }
 
-// x (FP64) += scale * xs (FP32); xs = 0
-__global__ __launch_bounds__(256) void k_compress_links(int vh, const float2* __restrict__ U, float2* __restrict__ Uc,
-                                                        int* flag) {
+// Two-row copy of a packed link field ([2][4][9][vh] -> [2][4][6][vh]) and
+// the check that the links are SU(3): flag is set when a stored third row
+// differs from the conjugate cross product of the first two by more than tol
+// (per component, |re| + |im|), or is not finite.
+// FP64 links whose stored third row is within this of the rebuilt one (a few
+// dozen rounding units) are taken as SU(3) by the FP64 solver's hops.
+constexpr double kTwoRowTol64 = 1e-14;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_compress_links(int vh, const R2<R>* __restrict__ U, R2<R>* __restrict__ Uc,
+                                                        int* flag, R tol) {
   const int t = blockIdx.x * 256 + threadIdx.x;  // link (parity, mu) slowest, site fastest
   if (t >= 8 * vh) return;
   const int pm = t / vh, cb = t - pm * vh;
-  const float2* src = U + (size_t)pm * 9 * vh + cb;
-  float2* dst = Uc + (size_t)pm * 6 * vh + cb;
-  C<float> m[9];
+  const R2<R>* src = U + (size_t)pm * 9 * vh + cb;
+  R2<R>* dst = Uc + (size_t)pm * 6 * vh + cb;
+  C<R> m[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) m[k] = ld<float>(src + (size_t)k * vh);
+  for (int k = 0; k < 9; ++k) m[k] = ld<R>(src + (size_t)k * vh);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) st<float>(dst + (size_t)k * vh, m[k]);
-  const C<float> r6 = conj(m[1] * m[5] - m[2] * m[4]);
-  const C<float> r7 = conj(m[2] * m[3] - m[0] * m[5]);
-  const C<float> r8 = conj(m[0] * m[4] - m[1] * m[3]);
-  const float dev = fmaxf(fmaxf(fabsf(r6.re - m[6].re) + fabsf(r6.im - m[6].im),
-                                fabsf(r7.re - m[7].re) + fabsf(r7.im - m[7].im)),
-                          fabsf(r8.re - m[8].re) + fabsf(r8.im - m[8].im));
-  if (!(dev <= 1e-5f)) *flag = 1;  // also for NaN
+  for (int k = 0; k < 6; ++k) st<R>(dst + (size_t)k * vh, m[k]);
+  const C<R> r6 = conj(m[1] * m[5] - m[2] * m[4]);
+  const C<R> r7 = conj(m[2] * m[3] - m[0] * m[5]);
+  const C<R> r8 = conj(m[0] * m[4] - m[1] * m[3]);
+  const R dev = fmax(fmax(fabs(r6.re - m[6].re) + fabs(r6.im - m[6].im),
+                          fabs(r7.re - m[7].re) + fabs(r7.im - m[7].im)),
+                     fabs(r8.re - m[8].re) + fabs(r8.im - m[8].im));
+  if (!(dev <= tol)) *flag = 1;  // also for NaN
 }
 hipError_t launch_compress_links(const Geom& g, const float2* U32, float2* Uc, int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_compress_links, dim3((8 * g.vh + 255) / 256), dim3(256), 0, s, g.vh, U32, Uc, flag);
+  hipLaunchKernelGGL(k_compress_links<float>, dim3((8 * g.vh + 255) / 256), dim3(256), 0, s, g.vh, U32, Uc, flag,
+                     1e-5f);
+  return hipGetLastError();
+}
+hipError_t launch_compress_links(const Geom& g, const double2* U64, double2* Uc, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_compress_links<double>, dim3((8 * g.vh + 255) / 256), dim3(256), 0, s, g.vh, U64, Uc, flag,
+                     kTwoRowTol64);
   return hipGetLastError();
 }
 
+// x (FP64) += scale * xs (FP32); xs = 0
 __global__ __launch_bounds__(256) void k_mixed_fold(int n, float2* xs, double2* __restrict__ x,
                                                     const SolverState* st) {
   const double scale = 1.0 / st->sigma;

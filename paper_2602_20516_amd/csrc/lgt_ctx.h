@@ -96,10 +96,11 @@ struct lgt_ctx {
   std::string err;
 
   // packed links: FP64 [2][4][9][vh], FP32 copy (mixed precision), and the
-  // FP32 copy's first two rows [2][4][6][vh] for the inner solver's hops
+  // first two rows [2][4][6][vh] of each for the CG hops
   double2* U64 = nullptr;
   float2* U32 = nullptr;
   float2* U32c = nullptr;
+  double2* U64c = nullptr;
   // packed momenta for the MD driver
   double2* P64 = nullptr;
 
@@ -114,7 +115,7 @@ struct lgt_ctx {
   double* partials = nullptr;
   double* result = nullptr;      // device results
   double* host_result = nullptr; // pinned mirror
-  int* flags = nullptr;          // device: [0] non-finite input, [1] links not SU(3)
+  int* flags = nullptr;          // device: [0] non-finite input, [1] links not SU(3), [2] the same for FP64
   int* host_flags = nullptr;     // pinned
   lgt::SolverState* host_state = nullptr;  // pinned
   lgt::Mailbox* mbox_host = nullptr;        // pinned, coherent: progress posted by CG steps
@@ -134,6 +135,8 @@ struct lgt_ctx {
   // Enqueues the two-row copy of U32 and the check that its links are SU(3),
   // whose result (host_flags[1] == 0) is valid after the caller's next sync.
   void compress_links();
+  // The same for U64 (host_flags[2] == 0: its links are SU(3) to FP64 rounding).
+  void compress_links64();
   void ensure_p64();
 
   // solver (solver.hip)

@@ -201,11 +201,12 @@ hipError_t launch_xmy64(int n, const double2* x, double2* y, hipStream_t s);    
 hipError_t launch_zero64(int n, double2* y, hipStream_t s);
 hipError_t launch_zero32(int n, float2* y, hipStream_t s);
 hipError_t launch_convert_64_32(int n, const double2* x, float2* y, hipStream_t s);
-// FP32 links in two-row form: Uc[p][mu][6][vh] = rows 0 and 1 of U32, and
-// flag set to 1 (never cleared here) if for some link the third row stored
-// in U32 is not the conjugate cross product of the first two (to 1e-5), i.e.
-// the links are not SU(3) and must not be compressed.
+// Links in two-row form: Uc[p][mu][6][vh] = rows 0 and 1 of U, and flag set
+// to 1 (never cleared here) if for some link the third row stored in U is not
+// the conjugate cross product of the first two (FP32 to 1e-5, FP64 to 1e-14),
+// i.e. the links are not SU(3) and must not be compressed.
 hipError_t launch_compress_links(const Geom& g, const float2* U32, float2* Uc, int* flag, hipStream_t s);
+hipError_t launch_compress_links(const Geom& g, const double2* U64, double2* Uc, int* flag, hipStream_t s);
 // mixed precision helpers
 // Device-side reliable update, enqueued without a host round trip:
 //   launch_mixed_fold:       x += xs / st->sigma; xs = 0

@@ -59,6 +59,13 @@ void lgt_ctx::compress_links() {
   LGT_HIP(hipMemcpyAsync(host_flags + 1, flags + 1, sizeof(int), hipMemcpyDeviceToHost, stream));
 }
 
+void lgt_ctx::compress_links64() {
+  if (!U64c) LGT_HIP(hipMalloc(&U64c, (size_t)48 * vh * sizeof(double2)));
+  LGT_HIP(hipMemsetAsync(flags + 2, 0, sizeof(int), stream));
+  LGT_HIP(launch_compress_links(g, U64, U64c, flags + 2, stream));
+  LGT_HIP(hipMemcpyAsync(host_flags + 2, flags + 2, sizeof(int), hipMemcpyDeviceToHost, stream));
+}
+
 void lgt_ctx::ensure_p64() {
   if (!P64) LGT_HIP(hipMalloc(&P64, (size_t)72 * vh * sizeof(double2)));
 }
@@ -150,12 +157,19 @@ int lgt_ctx::cg_normal64(bool dag, double2* z, const double2* rhs, double tol, i
   double2* r = f64(kW2) + half_elems();
   double2* p = f64(kW3) + half_elems();
   double2* w = f64(kW4) + half_elems();
+  // the hops read two-row links when the links are SU(3) to FP64 rounding
+  // (the third row rebuilt in registers: a quarter less traffic per hop)
+  compress_links64();
+  sync();
+  const bool c12 = host_flags[2] == 0;
+  const double2* links = c12 ? U64c : U64;
+  const int nk = c12 ? 6 : 9;
   LGT_HIP(launch_cg_init<double>(n, rhs, r, p, z, state, red(), tol, max_iter, stream));
   bool fresh = true;
   for (int iter0 = 0;;) {
     drive(iter0, [&] {
-      if (dag) cg_iteration<double, double2, true>(g, U64, kappa, t, t2, w, z, r, p, state, red(), stream, n, fresh);
-      else cg_iteration<double, double2, false>(g, U64, kappa, t, t2, w, z, r, p, state, red(), stream, n, fresh);
+      if (dag) cg_iteration<double, double2, true>(g, links, kappa, t, t2, w, z, r, p, state, red(), stream, n, fresh, nk);
+      else cg_iteration<double, double2, false>(g, links, kappa, t, t2, w, z, r, p, state, red(), stream, n, fresh, nk);
       fresh = false;
     });
     LGT_HIP(hipMemcpyAsync(host_state, state, sizeof(SolverState), hipMemcpyDeviceToHost, stream));
