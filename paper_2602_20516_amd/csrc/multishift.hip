@@ -236,17 +236,24 @@ SolveStats lgt_ctx::solve_multishift(const double2* phi, int ns, const double* s
   LGT_HIP(hipMemcpyAsync(state, host_state, sizeof(SolverState), hipMemcpyHostToDevice, stream));
   const double k2 = -kappa * kappa;
   const Reduce rd = red();
+  // the recursion's hops read two-row links when the links are SU(3) to FP64
+  // rounding, as the single-shift FP64 CG's; the true residuals below use the
+  // full links
+  compress_links64();
+  sync();
+  const int nk = host_flags[2] == 0 ? 6 : 9;
+  const double2* links = nk == 6 ? U64c : U64;
   auto iteration = [&] {
-    LGT_HIP((launch_hop_axpy<double, false>(g, 0, HopIn<double>{U64, p, p}, t, t, nullptr, nullptr, 1.0, stream,
-                                             state)));
-    LGT_HIP((launch_hop_schur_norm<double, double2, false>(g, HopIn<double>{U64, t, t}, wv, p, k2, state, rd,
+    LGT_HIP((launch_hop_axpy<double, false>(g, 0, HopIn<double>{links, p, p, nk}, t, t, nullptr, nullptr, 1.0,
+                                             stream, state)));
+    LGT_HIP((launch_hop_schur_norm<double, double2, false>(g, HopIn<double>{links, t, t, nk}, wv, p, k2, state, rd,
                                                             stream)));
     // block 0 also forms alpha = |r|^2 / |Mhat p|^2 from the partials
-    LGT_HIP((launch_hop_axpy<double, true>(g, 0, HopIn<double>{U64, wv, wv}, t, t, nullptr, nullptr, 1.0, stream,
-                                            state, rd.partials)));
+    LGT_HIP((launch_hop_axpy<double, true>(g, 0, HopIn<double>{links, wv, wv, nk}, t, t, nullptr, nullptr, 1.0,
+                                            stream, state, rd.partials)));
     // r -= alpha A p, |r|^2 partials; the base solution is not formed
-    LGT_HIP((launch_hop_schur_cg<double, double2, true>(g, HopIn<double>{U64, t, t}, wv, nullptr, r, p, k2, state, rd,
-                                                         stream)));
+    LGT_HIP((launch_hop_schur_cg<double, double2, true>(g, HopIn<double>{links, t, t, nk}, wv, nullptr, r, p, k2,
+                                                         state, rd, stream)));
     hipLaunchKernelGGL(k_msfinalize, dim3(1), dim3(256), 0, stream, hop_blocks(g, 1), rd.partials, state, w->ss,
                        rd.mbox);
     LGT_HIP(hipGetLastError());
